@@ -1,0 +1,160 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark.
+
+This module only generates data (grid coordinates, initial fields, media,
+source placement, problem mixes).  It holds none of the ADI arithmetic and
+imports neither the GPU library nor the oracle.
+
+Grid conventions follow Section 2 of the paper: row index j runs along y,
+column index i along x, spacing h in both directions.
+  * nodal CFD grid: pressure and both velocities at nodes (i h, j h);
+  * staggered MFD grid: pressure at X_cb x Y_cb (faces 0 and n h plus the
+    cell centres (k - 1/2) h), horizontal velocity at X_n x Y_cb, vertical
+    velocity at X_cb x Y_n.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+CFD = 0
+MFD = 1
+
+
+def node_coords(n: int, h: float) -> np.ndarray:
+    """X_n: nodes 0, h, ..., n h."""
+    return np.arange(n + 1, dtype=np.float64) * h
+
+
+def cb_coords(n: int, h: float) -> np.ndarray:
+    """X_cb: the two faces plus the n cell centres (Section 2.2)."""
+    x = np.empty(n + 2, dtype=np.float64)
+    x[0] = 0.0
+    x[1:n + 1] = (np.arange(n, dtype=np.float64) + 0.5) * h
+    x[n + 1] = n * h
+    return x
+
+
+def pressure_coords(method: int, n: int, h: float) -> np.ndarray:
+    return node_coords(n, h) if method == CFD else cb_coords(n, h)
+
+
+def shapes(method: int, nx: int, ny: int) -> dict:
+    """Array shapes (rows, cols) of U, V, W and the material arrays."""
+    if method == CFD:
+        s = (ny + 1, nx + 1)
+        return {"U": s, "K": s, "V": s, "Rv": s, "W": s, "Rw": s}
+    return {"U": (ny + 2, nx + 2), "K": (ny + 2, nx + 2),
+            "V": (ny + 2, nx + 1), "Rv": (ny + 2, nx + 1),
+            "W": (ny + 1, nx + 2), "Rw": (ny + 1, nx + 2)}
+
+
+def standing_mode(method: int, nx: int, ny: int, h: float, kx: int, ky: int) -> dict:
+    """U0 = sin(kx pi x) sin(ky pi y) at the pressure points, V0 = W0 = 0.
+
+    On the unit square this vanishes on all four walls, so it satisfies the
+    homogeneous Dirichlet condition; with c = 1 the exact solution is
+    U0 cos(pi sqrt(kx^2 + ky^2) t).
+    """
+    x = pressure_coords(method, nx, h)
+    y = pressure_coords(method, ny, h)
+    U = np.outer(np.sin(ky * math.pi * y), np.sin(kx * math.pi * x))
+    sh = shapes(method, nx, ny)
+    U[0, :] = U[-1, :] = 0.0
+    U[:, 0] = U[:, -1] = 0.0
+    return {"U": U, "V": np.zeros(sh["V"]), "W": np.zeros(sh["W"])}
+
+
+def random_fields(method: int, nx: int, ny: int, seed: int, scale: float = 1.0) -> dict:
+    """Gaussian pressure and velocities (zero Dirichlet pressure on the walls)."""
+    rng = np.random.default_rng(seed)
+    sh = shapes(method, nx, ny)
+    U = scale * rng.standard_normal(sh["U"])
+    U[0, :] = U[-1, :] = 0.0
+    U[:, 0] = U[:, -1] = 0.0
+    return {"U": U, "V": scale * rng.standard_normal(sh["V"]),
+            "W": scale * rng.standard_normal(sh["W"])}
+
+
+def random_medium(method: int, nx: int, ny: int, seed: int, lo=0.5, hi=1.5) -> dict:
+    """Smoothly varying positive kappa (pressure points) and 1/rho (velocity points)."""
+    rng = np.random.default_rng(seed)
+    sh = shapes(method, nx, ny)
+
+    def smooth(shape):
+        r, c = shape
+        y = np.linspace(0.0, 1.0, r)[:, None]
+        x = np.linspace(0.0, 1.0, c)[None, :]
+        f = np.zeros(shape)
+        for _ in range(3):
+            a, b, p, q = rng.uniform(0.5, 3.0, 4)
+            f += np.sin(a * math.pi * x + p) * np.cos(b * math.pi * y + q)
+        f = (f - f.min()) / max(f.max() - f.min(), 1e-30)
+        return lo + (hi - lo) * f
+
+    return {"K": smooth(sh["K"]), "Rv": smooth(sh["Rv"]), "Rw": smooth(sh["Rw"])}
+
+
+def layered_speed(method: int, nx: int, ny: int, h: float, seed: int) -> np.ndarray:
+    """Layered wave speed c(x, y) [m/s] at the pressure points.
+
+    Between 3 and 8 layers; interface depths drawn uniformly in
+    (0.1, 0.95) * L_y and sorted; each interface undulates by at most
+    0.03 * L_y through 1-3 sinusoids; layer speeds drawn uniformly in
+    [1500, 4500] m/s and sorted to increase with depth; tanh transitions of
+    width 2h.  Depth is measured from row j = 0 (the free surface).
+    """
+    rng = np.random.default_rng(seed)
+    Lx, Ly = nx * h, ny * h
+    nlayers = int(rng.integers(3, 9))
+    depths = np.sort(rng.uniform(0.1, 0.95, nlayers - 1)) * Ly
+    speeds = np.sort(rng.uniform(1500.0, 4500.0, nlayers))
+    x = pressure_coords(method, nx, h)
+    y = pressure_coords(method, ny, h)
+    c = np.full((y.size, x.size), speeds[0])
+    for k, z0 in enumerate(depths):
+        nwaves = int(rng.integers(1, 4))
+        amp = rng.uniform(0.0, 0.03 * Ly, nwaves) / nwaves
+        wl = rng.uniform(0.2, 1.0, nwaves) * Lx
+        ph = rng.uniform(0.0, 2.0 * math.pi, nwaves)
+        z = z0 + sum(a * np.sin(2.0 * math.pi * x / w + p) for a, w, p in zip(amp, wl, ph))
+        step = 0.5 * (1.0 + np.tanh((y[:, None] - z[None, :]) / (2.0 * h)))
+        c = c + (speeds[k + 1] - speeds[k]) * step
+    return c
+
+
+def ricker_source(i: int, j: int, f0: float = 15.0, amp: float = 1.0) -> dict:
+    """Point source placement and Ricker parameters (delay t0 = 1 / f0)."""
+    return {"i": int(i), "j": int(j), "f0": float(f0), "t0": 1.0 / float(f0), "amp": float(amp)}
+
+
+def seismic_problem(method: int, n: int, seed: int = 0, h: float = 5.0, cfl: float = 0.8) -> dict:
+    """Layered-medium problem: n x n cells of h metres, rho = 1, kappa = c^2,
+    15 Hz Ricker at (i = n/2, j = 16), zero initial fields, dt = cfl h / c_max."""
+    c = layered_speed(method, n, n, h, seed)
+    cmax = float(c.max())
+    sh = shapes(method, n, n)
+    return {
+        "method": method, "nx": n, "ny": n, "h": h, "dt": cfl * h / cmax, "cmax": cmax,
+        "K": c * c, "src": ricker_source(n // 2, 16),
+        "U": np.zeros(sh["U"]), "V": np.zeros(sh["V"]), "W": np.zeros(sh["W"]),
+    }
+
+
+def batch_mix(seed: int = 0, count: int = 256, lo: int = 64, hi: int = 1024) -> list:
+    """Problem mix of the batched workload: Nx, Ny independent and
+    log-uniform on [lo, hi], method uniform on {CFD, MFD}, per-problem medium
+    seed, Ricker source at a uniform interior point at least 8 cells from the
+    walls."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        nx = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        ny = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        method = int(rng.integers(0, 2))
+        si = int(rng.integers(8, nx - 8 + 1))
+        sj = int(rng.integers(8, ny - 8 + 1))
+        out.append({"method": method, "nx": nx, "ny": ny, "medium_seed": int(rng.integers(0, 2**31)),
+                    "src_i": si, "src_j": sj})
+    return out

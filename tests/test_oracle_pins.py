@@ -1,0 +1,431 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: the references are the printed
+coefficients (Appendices A/B, via tests/golden), Taylor moments, LAPACK on the
+dense matrices, a dense Kronecker assembly of the split (eqs. A1HA2H,
+ecua2:PR, ecua3:PR2), the exact standing-wave solution and the closed-form
+Peaceman-Rachford amplification of a single mode.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_07583_amd import inputs
+from tests.dense_pr import DenseProblem
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "operators_appendix.json")
+
+
+def frac(rows):
+    return np.array([p / q for p, q in rows])
+
+
+@pytest.fixture(scope="module")
+def printed():
+    with open(GOLD) as f:
+        return {k: frac(v) for k, v in json.load(f).items() if not k.startswith("_")}
+
+
+# ---------------------------------------------------------------- P1 operators
+
+def test_cfd_operators_match_printed_rows(printed):
+    n, h = 12, 1.0
+    P, Q, Pb, Qb = O.cfd_matrices(n, h)
+    assert np.array_equal(P[0, :2], printed["P4_row0"])
+    assert np.array_equal(P[n, n - 1:], printed["P4_rowN"])
+    assert np.array_equal(Q[0, :4], printed["Q4_row0"])
+    assert np.array_equal(Q[n, n - 3:], printed["Q4_rowN"])
+    for i in range(1, n):
+        assert np.array_equal(P[i, i - 1:i + 2], printed["P4_interior"])
+        assert np.array_equal(Q[i, i - 1:i + 2], printed["Q4_interior"])
+    assert np.array_equal(Pb[0, :2], printed["Pbar4_row0"])
+    assert np.array_equal(Pb[-1, -2:], printed["Pbar4_rowlast"])
+    assert np.array_equal(Qb[0, :4], printed["Qbar4_row0"])
+    assert np.array_equal(Qb[-1, -4:], printed["Qbar4_rowlast"])
+    # the reduced first row removes f'_0 from row0 - 6 row1 of (P, Q) (Appendix A)
+    assert np.array_equal(-(P[0, :3] - 6 * P[1, :3])[1:], Pb[0, :2])
+    assert np.array_equal(-(Q[0, :4] - 6 * Q[1, :4]), Qb[0, :4])
+
+
+def test_mfd_operators_match_printed_rows(printed):
+    n, h = 12, 1.0
+    D, G = O.mfd_matrices(n, h)
+    assert np.allclose(D[0, :6], printed["D4_row0"], rtol=0, atol=1e-16)
+    assert np.allclose(G[0, :6], printed["G4_row0"], rtol=0, atol=1e-15)
+    assert np.allclose(G[1, :5], printed["G4_row1"], rtol=0, atol=1e-16)
+    for r in range(1, n - 1):
+        assert np.allclose(D[r, r - 1:r + 3], printed["D4_interior"], rtol=0, atol=1e-16)
+    for r in range(2, n - 1):
+        assert np.allclose(G[r, r - 1:r + 3], printed["G4_interior"], rtol=0, atol=1e-16)
+    # bottom rows are the centro-skew mirror of the printed top rows
+    assert np.array_equal(D[::-1, ::-1], -D)
+    assert np.array_equal(G[::-1, ::-1], -G)
+
+
+@pytest.mark.parametrize("n", [8, 13, 32])
+def test_cfd_operators_are_fourth_order_exact(n):
+    """P f' = Q f holds exactly for monomials of degree <= 4 on every row,
+    boundary rows included, and fails at degree 5 (unit spacing)."""
+    P, Q, Pb, Qb = O.cfd_matrices(n, 1.0)
+    x = np.arange(n + 1, dtype=np.float64) / n     # scale to [0, 1] for conditioning
+    P, Q, Pb, Qb = O.cfd_matrices(n, 1.0 / n)
+    for p in range(6):
+        f = x ** p
+        fp = p * x ** (p - 1) if p else np.zeros_like(x)
+        r = P @ fp - Q @ f
+        rb = Pb @ fp[1:n] - Qb @ f
+        if p <= 4:
+            assert np.abs(r).max() < 1e-10 and np.abs(rb).max() < 1e-10, p
+        else:
+            assert np.abs(r).max() > 1e-6 and np.abs(rb).max() > 1e-6
+
+
+@pytest.mark.parametrize("n", [8, 13, 32])
+def test_mfd_operators_are_fourth_order_exact(n):
+    h = 1.0 / n
+    D, G = O.mfd_matrices(n, h)
+    xn = inputs.node_coords(n, h)
+    xc = inputs.cb_coords(n, h)
+    for p in range(6):
+        dv = D @ xn ** p - (p * xc[1:-1] ** (p - 1) if p else 0.0)
+        gu = G @ xc ** p - (p * xn ** (p - 1) if p else 0.0)
+        if p <= 4:
+            assert np.abs(dv).max() < 1e-9 and np.abs(gu).max() < 1e-9, p
+        else:
+            assert np.abs(dv).max() > 1e-6 and np.abs(gu).max() > 1e-6
+
+
+# ---------------------------------------------------------------- P2 line solves
+
+def test_thomas_pivots_closed_form():
+    """No-pivot LU of P and Pbar: pivots 6, 1, 3, 11/3, ... -> 2 + sqrt 3,
+    last pivot 6 - 18/d; Pbar: 6, 3, 11/3, ... -> 6 sqrt 3 - 6 at the end."""
+    n = 40
+    pP, pB = O.cfd_pivots(n)
+    assert pP[0] == 6.0 and pP[1] == 1.0 and pP[2] == 3.0
+    assert abs(pP[3] - 11.0 / 3.0) < 1e-15
+    assert abs(pP[n - 1] - (2 + math.sqrt(3))) < 1e-14
+    assert abs(pP[n] - (6 - 18 / (2 + math.sqrt(3)))) < 1e-13
+    assert pB[0] == 6.0 and pB[1] == 3.0
+    assert abs(pB[-1] - (6 * math.sqrt(3) - 6)) < 1e-13
+    assert (pP > 0).all() and (pB > 0).all()
+
+
+@pytest.mark.parametrize("n", [8, 9, 31, 64])
+def test_line_derivatives_match_lapack(n):
+    rng = np.random.default_rng(n)
+    h = 1.0 / n
+    P, Q, Pb, Qb = O.cfd_matrices(n, h)
+    f = rng.standard_normal(n + 1)
+    ref = np.linalg.solve(P, Q @ f)
+    got = O.cfd_d(f, h)
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    refb = np.linalg.solve(Pb, Qb @ f)
+    gotb = O.cfd_dbar(f, h)
+    assert np.abs(gotb - refb).max() <= 1e-14 * np.abs(refb).max()
+    D, G = O.mfd_matrices(n, h)
+    u = rng.standard_normal(n + 2)
+    assert np.abs(O.mfd_g(u, h) - G @ u).max() <= 1e-13 * np.abs(G @ u).max()
+    assert np.abs(O.mfd_d(f, h) - D @ f).max() <= 1e-13 * np.abs(D @ f).max()
+
+
+# ---------------------------------------------------------------- P3 accuracy
+
+def _rate(errs, ns):
+    return [math.log(errs[k] / errs[k + 1]) / math.log(ns[k + 1] / ns[k]) for k in range(len(ns) - 1)]
+
+
+def _trimmed(rates):
+    """Rate summary of Section 4: mean after dropping the highest and lowest."""
+    r = sorted(rates)
+    return sum(r[1:-1]) / len(r[1:-1])
+
+
+def test_line_derivatives_fourth_order_under_refinement():
+    ns = [16, 32, 64, 128]
+    e = {"d": [], "dbar": [], "g": [], "D": []}
+    for n in ns:
+        h = 1.0 / n
+        x = inputs.node_coords(n, h)
+        xc = inputs.cb_coords(n, h)
+        f = np.sin(2.3 * x + 0.4)
+        e["d"].append(np.abs(O.cfd_d(f, h) - 2.3 * np.cos(2.3 * x + 0.4)).max())
+        e["dbar"].append(np.abs(O.cfd_dbar(f, h) - 2.3 * np.cos(2.3 * x[1:n] + 0.4)).max())
+        e["g"].append(np.abs(O.mfd_g(np.sin(2.3 * xc + 0.4), h) - 2.3 * np.cos(2.3 * x + 0.4)).max())
+        e["D"].append(np.abs(O.mfd_d(f, h) - 2.3 * np.cos(2.3 * xc[1:-1] + 0.4)).max())
+    for k, v in e.items():
+        r = _rate(v, ns)
+        assert min(r) > 3.7, (k, r)
+
+
+# ---------------------------------------------------------------- P4 stage semantics
+
+def _dense_for(method, nx, ny, h, a, K, Rv, Rw):
+    if method == O.CFD:
+        _, _, Pbx, Qbx = O.cfd_matrices(nx, h)
+        Px, Qx, _, _ = O.cfd_matrices(nx, h)
+        Py, Qy, Pby, Qby = O.cfd_matrices(ny, h)
+        Dx, Gx = np.linalg.solve(Pbx, Qbx), np.linalg.solve(Px, Qx)
+        Dy, Gy = np.linalg.solve(Pby, Qby), np.linalg.solve(Py, Qy)
+    else:
+        Dx, Gx = O.mfd_matrices(nx, h)
+        Dy, Gy = O.mfd_matrices(ny, h)
+    return DenseProblem(Dx, Gx, Dy, Gy, nx, ny, method,
+                        K[1:-1, 1:-1], Rv[1:-1, :], Rw[:, 1:-1], a)
+
+
+def _tiny_case(method, nx, ny, seed, with_src=True):
+    h = 1.0 / max(nx, ny)
+    f = inputs.random_fields(method, nx, ny, seed)
+    med = inputs.random_medium(method, nx, ny, seed + 100)
+    src = None
+    if with_src:
+        src = {"i": nx // 2, "j": ny // 3, "f0": 3.0, "t0": 0.2, "amp": 1.0}
+    return h, f, med, src
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (9, 12), (12, 10)])
+def test_step_converged_sweeps_match_dense_lu(method, nx, ny):
+    """64 sweeps (contraction <= 0.375 at cfl 0.5) reproduce the exactly
+    solved stages of eqs. ecua2:PR / ecua3:PR2 assembled densely."""
+    h, f, med, src = _tiny_case(method, nx, ny, 7 + nx + 3 * ny)
+    kmax = med["K"].max() * max(med["Rv"].max(), med["Rw"].max())
+    dt = 0.5 * h / math.sqrt(kmax)
+    t0 = 0.05
+    U, V, W = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=1, sweeps=64,
+                    K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src, t0=t0)
+    dp = _dense_for(method, nx, ny, h, dt / 2, med["K"], med["Rv"], med["Rw"])
+    Fm = np.zeros((dp.niy, dp.nix)); Fm1 = np.zeros_like(Fm)
+    Fm[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, t0)
+    Fm1[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, t0 + dt)
+    z = dp.pack(f["U"][1:-1, 1:-1], f["V"][1:-1, :], f["W"][:, 1:-1])
+    Ue, Ve, We = dp.unpack(dp.step_exact(z, Fm, Fm1))
+    for got, ref in ((U[1:-1, 1:-1], Ue), (V[1:-1, :], Ve), (W[:, 1:-1], We)):
+        assert np.abs(got - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1.0)
+    # entries the method never writes keep their values
+    assert np.array_equal(U[0], f["U"][0]) and np.array_equal(U[:, -1], f["U"][:, -1])
+    assert np.array_equal(V[0], f["V"][0]) and np.array_equal(V[-1], f["V"][-1])
+    assert np.array_equal(W[:, 0], f["W"][:, 0]) and np.array_equal(W[:, -1], f["W"][:, -1])
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+@pytest.mark.parametrize("sweeps", [2, 6])
+def test_finite_sweeps_match_dense_iteration(method, sweeps):
+    """At a fixed sweep count the oracle equals the matrix form of eqs.
+    adiSolve / adiSolve2 (V_0 = V^m, W_0 = W*), over three steps."""
+    nx, ny = 11, 9
+    h, f, med, src = _tiny_case(method, nx, ny, 3)
+    dt = 0.8 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    U, V, W = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=3, sweeps=sweeps,
+                    K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    dp = _dense_for(method, nx, ny, h, dt / 2, med["K"], med["Rv"], med["Rw"])
+    z = dp.pack(f["U"][1:-1, 1:-1], f["V"][1:-1, :], f["W"][:, 1:-1])
+    for m in range(3):
+        Fm = np.zeros((dp.niy, dp.nix)); Fm1 = np.zeros_like(Fm)
+        Fm[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, m * dt)
+        Fm1[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, (m + 1) * dt)
+        z = dp.step_sweeps(z, Fm, Fm1, sweeps)
+    Ue, Ve, We = dp.unpack(z)
+    for got, ref in ((U[1:-1, 1:-1], Ue), (V[1:-1, :], Ve), (W[:, 1:-1], We)):
+        assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+
+
+@pytest.mark.parametrize("method,cfl,rate", [(O.CFD, 0.8, 0.48), (O.MFD, 0.5, 0.375)])
+def test_sweeps_converge_geometrically_to_exact_stage(method, cfl, rate):
+    """The error of K sweeps against the exact stages falls geometrically,
+    no faster than the fixed-point contraction of the operators."""
+    nx = ny = 10
+    h, f, med, _ = _tiny_case(method, nx, ny, 11, with_src=False)
+    one = np.ones_like
+    med = {"K": one(med["K"]), "Rv": one(med["Rv"]), "Rw": one(med["Rw"])}
+    dt = cfl * h
+    dp = _dense_for(method, nx, ny, h, dt / 2, med["K"], med["Rv"], med["Rw"])
+    z = dp.pack(f["U"][1:-1, 1:-1], f["V"][1:-1, :], f["W"][:, 1:-1])
+    Z = np.zeros((dp.niy, dp.nix))
+    Ue, _, _ = dp.unpack(dp.step_exact(z, Z, Z))
+    errs = []
+    for K in (4, 8, 12, 16):
+        U, _, _ = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=1, sweeps=K, **med)
+        errs.append(np.abs(U[1:-1, 1:-1] - Ue).max())
+    per_sweep = [(errs[k + 1] / errs[k]) ** 0.25 for k in range(3)]
+    assert all(0.2 * rate < r < 1.0 for r in per_sweep), per_sweep
+    assert errs[-1] < 1e-2 * errs[0]
+
+
+# ---------------------------------------------------------------- P5/P6 physics
+
+def pr_mode_factor(alpha, beta, a, nsteps):
+    """Closed-form PR-CN amplification of the mode (sin a x sin b y, cos sin,
+    sin cos) with exact derivatives, c = rho = 1: pressure coefficient after
+    nsteps steps (eqs. CN, ecua2:PR, ecua3:PR2 on a 3x3 symbol)."""
+    A1 = np.array([[0, alpha, 0], [-alpha, 0, 0], [0, 0, 0.0]])
+    A2 = np.array([[0, 0, beta], [0, 0, 0], [-beta, 0, 0.0]])
+    I = np.eye(3)
+    M = np.linalg.solve(I - a * A2, I + a * A1) @ np.linalg.solve(I - a * A1, I + a * A2)
+    return np.linalg.matrix_power(M, nsteps)[0, 0]
+
+
+@pytest.mark.parametrize("N,expect", [(24, 7.614e-3), (50, 1.760e-3), (100, 4.402e-4)])
+def test_cfd_standing_wave_error_equals_pr_time_error(N, expect):
+    """CFD, c = 1, dt = h, T = 1: the max error against the exact solution
+    sin(pi x) sin(pi y) cos(sqrt 2 pi t) equals the closed-form PR-CN time
+    error to within 1 %, and the remaining (spatial) error is tiny."""
+    h = 1.0 / N
+    f = inputs.standing_mode(O.CFD, N, N, h, 1, 1)
+    U, V, W = O.run(O.CFD, f["U"], f["V"], f["W"], h=h, dt=h, nsteps=N, sweeps=6)
+    exact = f["U"] * math.cos(math.sqrt(2) * math.pi)
+    err = np.abs(U - exact).max()
+    g = pr_mode_factor(math.pi, math.pi, h / 2, N)
+    assert abs(g - math.cos(math.sqrt(2) * math.pi)) == pytest.approx(expect, rel=2e-3)
+    assert err == pytest.approx(expect, rel=1e-2)
+    assert np.abs(U - g * f["U"]).max() < 2e-3 * err
+
+
+def test_rates_cfd():
+    """Full error at dt = h converges at order 2 (time error dominates); the
+    error against the time-discrete closed form converges at order ~4.  The
+    spatial rate is taken on N <= 100: by 200 steps the roundoff-seeded
+    growth of the CFD boundary modes (see the eigenvalue test below) reaches
+    the 1e-9 level of the N = 200 spatial error."""
+    ns = [24, 50, 100, 200]
+    full, spatial = [], []
+    for N in ns:
+        h = 1.0 / N
+        f = inputs.standing_mode(O.CFD, N, N, h, 1, 1)
+        U, _, _ = O.run(O.CFD, f["U"], f["V"], f["W"], h=h, dt=h, nsteps=N, sweeps=6)
+        full.append(np.abs(U - f["U"] * math.cos(math.sqrt(2) * math.pi)).max())
+        spatial.append(np.abs(U - pr_mode_factor(math.pi, math.pi, h / 2, N) * f["U"]).max())
+    rf, rs = _rate(full, ns), _rate(spatial[:3], ns[:3])
+    assert all(abs(r - 2.0) < 0.05 for r in rf), rf
+    assert min(rs) > 3.7, rs
+
+
+def test_rates_mfd():
+    """MFD standing mode sin(2 pi x) sin(3 pi y), dt = h/2, T = 0.25:
+    spatial error (against the time-discrete closed form) at order ~4."""
+    ns = [16, 32, 64, 128]
+    spatial = []
+    for N in ns:
+        h = 1.0 / N
+        f = inputs.standing_mode(O.MFD, N, N, h, 2, 3)
+        nsteps = N // 2
+        U, _, _ = O.run(O.MFD, f["U"], f["V"], f["W"], h=h, dt=h / 2, nsteps=nsteps, sweeps=6)
+        g = pr_mode_factor(2 * math.pi, 3 * math.pi, h / 4, nsteps)
+        spatial.append(np.abs(U - g * f["U"]).max())
+    rs = _rate(spatial, ns)
+    assert _trimmed(rs) > 3.9 and min(rs) > 3.5, rs
+
+
+def test_mfd_config2_mode_time_error_small_grid():
+    """Same closed form for the MFD mode on a 128 grid, 100 steps of h/2."""
+    N = 128
+    h = 1.0 / N
+    f = inputs.standing_mode(O.MFD, N, N, h, 2, 3)
+    U, _, _ = O.run(O.MFD, f["U"], f["V"], f["W"], h=h, dt=h / 2, nsteps=100, sweeps=6)
+    T = 100 * h / 2
+    g = pr_mode_factor(2 * math.pi, 3 * math.pi, h / 4, 100)
+    exact_err = abs(g - math.cos(math.sqrt(13) * math.pi * T)) * np.abs(f["U"]).max()
+    err = np.abs(U - f["U"] * math.cos(math.sqrt(13) * math.pi * T)).max()
+    assert err == pytest.approx(exact_err, rel=0.05)
+
+
+# ---------------------------------------------------------------- P7 symmetry
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_transposed_problem_with_swapped_order_is_bitwise_transpose(method):
+    nx, ny = 13, 10
+    h, f, med, src = _tiny_case(method, nx, ny, 21)
+    dt = 0.6 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    kw = dict(h=h, dt=dt, nsteps=4, sweeps=6)
+    U, V, W = O.run(method, f["U"], f["V"], f["W"], K=med["K"], Rv=med["Rv"], Rw=med["Rw"],
+                    src=src, order=0, **kw)
+    srcT = dict(src, i=src["j"], j=src["i"])
+    Ut, Vt, Wt = O.run(method, f["U"].T, f["W"].T, f["V"].T, K=med["K"].T, Rv=med["Rw"].T,
+                       Rw=med["Rv"].T, src=srcT, order=1, **kw)
+    assert np.array_equal(Ut.T, U)
+    assert np.array_equal(Wt.T, V)
+    assert np.array_equal(Vt.T, W)
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_mirror_symmetric_problem_stays_symmetric(method):
+    n = 16
+    h = 1.0 / n
+    sh = inputs.shapes(method, n, n)
+    y = inputs.pressure_coords(method, n, h)
+    K = np.repeat((1.0 + 0.5 * np.sin(3 * y))[:, None], sh["K"][1], axis=1)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal(sh["U"])
+    U = 0.5 * (U + U[:, ::-1])
+    U[0] = U[-1] = 0; U[:, 0] = U[:, -1] = 0
+    V = np.zeros(sh["V"]); W = np.zeros(sh["W"])
+    # a source on the mirror line (CFD node column n/2); the MFD centre line
+    # carries no pressure point for even n, so that case runs unforced
+    src = {"i": n // 2, "j": 5, "f0": 2.0, "t0": 0.3} if method == O.CFD else None
+    U1, V1, W1 = O.run(method, U, V, W, h=h, dt=0.5 * h / 1.5, nsteps=10, sweeps=6, K=K, src=src)
+    assert np.abs(U1 - U1[:, ::-1]).max() <= 1e-13 * np.abs(U1).max()
+    assert np.abs(W1 - W1[:, ::-1]).max() <= 1e-13 * np.abs(W1).max()
+    assert np.abs(V1 + V1[:, ::-1]).max() <= 1e-13 * np.abs(V1).max()
+
+
+# ---------------------------------------------------------------- P8 stability
+
+def _energy(f):
+    return sum(float((a ** 2).sum()) for a in f)
+
+
+def test_mfd_even_sweeps_bounded_odd_sweeps_grow():
+    """At cfl 0.8 (fixed-point contraction ~0.96) an even sweep count keeps
+    the MFD energy bounded; an odd count amplifies the unconverged modes."""
+    n = 32
+    h = 1.0 / n
+    f = inputs.random_fields(O.MFD, n, n, 1)
+    e0 = _energy((f["U"], f["V"], f["W"]))
+    out = {}
+    for K in (6, 7):
+        g = O.run(O.MFD, f["U"], f["V"], f["W"], h=h, dt=0.8 * h, nsteps=100, sweeps=K)
+        out[K] = _energy(g) / e0
+    assert out[6] < 1.5
+    assert out[7] > 1e6
+
+
+def test_cfd_semidiscrete_operator_has_growing_boundary_modes():
+    """The literal CFD pairing (Pbar^-1 Qbar on velocity, P^-1 Q with the
+    4th-order closure on pressure, edge velocities evolved) has 1-D
+    semi-discrete eigenvalues with Re(lambda) h ~ 0.1; the mimetic pair has
+    none.  The growth is independent of the time step and of the sweeps."""
+    n = 32
+    h = 1.0 / n
+    P, Q, Pb, Qb = O.cfd_matrices(n, h)
+    Gc = np.linalg.solve(P, Q)[:, 1:n]
+    Dc = np.linalg.solve(Pb, Qb)
+    L = np.block([[np.zeros((n - 1, n - 1)), -Dc], [-Gc, np.zeros((n + 1, n + 1))]])
+    re = np.linalg.eigvals(L).real * h
+    assert 0.05 < re.max() < 0.2
+    D, G = O.mfd_matrices(n, h)
+    Lm = np.block([[np.zeros((n, n)), -D], [-G[:, 1:n + 1], np.zeros((n + 1, n + 1))]])
+    assert np.linalg.eigvals(Lm).real.max() * h < 1e-12
+    # the full 2-D scheme grows from roughness even with converged stages
+    f = inputs.random_fields(O.CFD, n, n, 2)
+    g = O.run(O.CFD, f["U"], f["V"], f["W"], h=h, dt=0.5 * h, nsteps=100, sweeps=40)
+    assert _energy(g) / _energy((f["U"], f["V"], f["W"])) > 1e3
+
+
+# ---------------------------------------------------------------- source
+
+def test_ricker_source_closed_form():
+    src = {"i": 3, "j": 4, "f0": 15.0, "t0": 1 / 15.0, "amp": 2.0}
+    h = 5.0
+    assert O.source_value(src, h, src["t0"]) == pytest.approx(2.0 / 25.0, rel=1e-15)
+    tz = src["t0"] + 1.0 / (math.sqrt(2) * math.pi * 15.0)
+    assert abs(O.source_value(src, h, tz)) < 1e-15
+    # zero mean and even symmetry about the delay
+    ts = np.linspace(src["t0"] - 0.5, src["t0"] + 0.5, 20001)
+    vals = np.array([O.source_value(src, h, t) for t in ts])
+    assert abs(np.trapezoid(vals, ts)) < 1e-9
+    assert np.abs(vals - vals[::-1]).max() < 1e-12
