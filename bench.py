@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Peaceman-Rachford ADI step on one MI355X.
+
+Workload: the layered-medium seismic configuration at 4096 x 4096 cells
+(h = 5 m, 3-8 seeded layers 1500-4500 m/s, 15 Hz Ricker source near the top,
+dt at CFL 0.8, rho = 1, 6 sweeps per stage).  One benchmark step is one ADI
+time step of each spatial variant (compact CFD and mimetic MFD) on that grid,
+FP32; the FP64 figures of the same step are reported beside it.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--sweeps", type=int, default=6)
+    ap.add_argument("--methods", default="cfd,mfd")
+    ap.add_argument("--dtypes", default="fp32,fp64")
+    ap.add_argument("--cpu-baseline-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def alg_bytes_per_pass(method, n, elem, k_varies, r_varies):
+    """Algorithmic HBM bytes of one line pass: read the pressure hand-off,
+    the velocity and kappa (when it varies) and 1/rho (when it varies),
+    write the pressure hand-off and the velocity."""
+    nu = (n - 1) ** 2 if method == 0 else n * n            # interior pressure points
+    nv = (n + 1) * (n - 1 if method == 0 else n)             # velocity points on interior lines
+    return elem * (2 * nu + 2 * nv + (nu if k_varies else 0) + (nv if r_varies else 0))
+
+
+def gpu_case(method, dtype, n, steps, warmup, sweeps):
+    import torch
+    from paper_2006_07583_amd import adi, inputs
+    pr = inputs.seismic_problem(method, n, seed=0)
+    tdt = torch.float32 if dtype == adi.FP32 else torch.float64
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
+    U, V, W, K = t(pr["U"]), t(pr["V"]), t(pr["W"]), t(pr["K"])
+    p = adi.make_params(method, dtype, n, n, pr["h"], pr["dt"], pr["cmax"], sweeps=sweeps, src=pr["src"])
+    stream = torch.cuda.current_stream()
+    pb = adi.Problem(p, stream).bind(U, V, W, K)
+    pb.run(warmup)
+    pb.sync()
+
+    def timed(k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        pb.run(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, time.perf_counter() - w0
+
+    t_ev, t_wall = timed(steps)
+    half = max(1, steps // 2)
+    t_half, _ = timed(half)
+    # per line-pass duration: the difference removes the once-per-call
+    # transposes and explicit pass; every step is two line passes
+    per_pass = (t_ev - t_half) / (2.0 * (steps - half)) if steps > half else t_ev / (2.0 * steps)
+    finite = bool(torch.isfinite(U).all().item())
+    pb.close()
+    return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite}
+
+
+def cpu_baseline(n, steps, methods):
+    import oracle as O
+    from paper_2006_07583_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    total_t, total_pts = 0.0, 0
+    for m in methods:
+        pr = inputs.seismic_problem(m, n, seed=0)
+        t0 = time.perf_counter()
+        O.run(m, pr["U"], pr["V"], pr["W"], h=pr["h"], dt=pr["dt"], nsteps=steps, sweeps=6,
+              K=pr["K"], src=pr["src"], threads=threads)
+        total_t += time.perf_counter() - t0
+        total_pts += n * n * steps
+    return {"value": total_pts / total_t, "unit": "grid-point-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps of each of {'+'.join('CFD' if m == 0 else 'MFD' for m in methods)} "
+                      f"on the {n}x{n} layered grid, FP64 oracle, {threads} OpenMP threads, {total_t:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); "
+              "the batched problems shard as whole problems and no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+    from paper_2006_07583_amd import adi
+    mmap = {"cfd": adi.CFD, "mfd": adi.MFD}
+    dmap = {"fp32": adi.FP32, "fp64": adi.FP64}
+    methods = [mmap[m] for m in args.methods.split(",")]
+    dtypes = [dmap[d] for d in args.dtypes.split(",")]
+    n, K, W = args.n, args.steps, args.warmup
+    res = {}
+    for d in dtypes:
+        for m in methods:
+            r = gpu_case(m, d, n, K, W, args.sweeps)
+            elem = 4 if d == adi.FP32 else 8
+            r["alg_bytes_pass"] = alg_bytes_per_pass(m, n, elem, True, False)
+            r["gbs"] = r["alg_bytes_pass"] / r["per_pass"] / 1e9
+            r["pt_steps_s"] = n * n * K / r["t"]
+            res[(m, d)] = r
+            print(f"# {'CFD' if m == 0 else 'MFD'} {'fp32' if d == 0 else 'fp64'}: "
+                  f"{r['pt_steps_s']:.4g} pt-steps/s, {r['t'] / K * 1e3:.3f} ms/step, "
+                  f"pass {r['per_pass'] * 1e6:.1f} us, {r['gbs']:.0f} GB/s alg, finite={r['finite']}",
+                  file=sys.stderr, flush=True)
+    head = adi.FP32 if adi.FP32 in dtypes else dtypes[0]
+    tt = sum(res[(m, head)]["t"] for m in methods)
+    value = n * n * K * len(methods) / tt
+    # dominant kernel: the slowest line pass of the headline dtype
+    dom = max(methods, key=lambda m: res[(m, head)]["per_pass"])
+    rd = res[(dom, head)]
+    variants = {}
+    for (m, d), r in res.items():
+        variants[f"{'cfd' if m == 0 else 'mfd'}_{'fp32' if d == 0 else 'fp64'}"] = {
+            "pt_steps_s": r["pt_steps_s"], "ms_per_step": r["t"] / K * 1e3,
+            "line_pass_us": r["per_pass"] * 1e6, "alg_GBs": r["gbs"], "hbm_frac": r["gbs"] / HBM_PEAK_GBS,
+            "finite": r["finite"]}
+    out = {
+        "metric": "ADI grid-point-steps/s at 4096^2 FP32 vs FP64 + %HBM peak; p50/p99 solve latency",
+        "value": value, "unit": "grid-point-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": tt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if head == adi.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"layered-medium seismic grid {n}x{n}, h=5 m, Ricker 15 Hz, CFL 0.8, "
+                               f"{args.sweeps} sweeps; one step = one ADI step of "
+                               + " and ".join("CFD" if m == 0 else "MFD" for m in methods),
+                   "grid": n, "methods": args.methods, "sweeps": args.sweeps},
+        "roofline": {"bound": "hbm", "achieved": rd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rd["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"line_pass {'CFD' if dom == 0 else 'MFD'} "
+                               f"{'fp32' if head == adi.FP32 else 'fp64'}"},
+        "variants": variants,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_steps, methods)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,145 @@
+/*
+ * adi.h - C ABI of the MI355X Peaceman-Rachford ADI library (libadi.so).
+ *
+ * The library advances the 2-D velocity-pressure acoustic system
+ *     u_t = -kappa div(v) + f,   rho v_t = -grad u            (Section 2, eq. 1)
+ * on a rectangular grid of nx x ny cells of spacing h, with homogeneous
+ * Dirichlet pressure on the four walls, by the Crank-Nicolson time
+ * discretisation factored with the Peaceman-Rachford split (eqs. CN, PR two
+ * stages).  Each stage couples pressure and one velocity component along the
+ * grid lines of one direction and is solved by a fixed, even number of
+ * fixed-point sweeps (eqs. adiSolve, adiSolve2; Algorithms 3 and 4).  Two
+ * spatial discretisations are offered:
+ *   ADI_CFD  nodal fourth-order compact differences, P4/Q4 and the reduced
+ *            Pbar4/Qbar4 (Section 2.1, Appendix A): every derivative along a
+ *            line is one tridiagonal solve;
+ *   ADI_MFD  staggered fourth-order mimetic operators D4/G4 (Section 2.2,
+ *            Appendix B): every derivative is a banded stencil.
+ * One step applies, in order: the explicit y-part of stage 1 (A, W*), the
+ * row iterations (Ubar*, V*), the explicit x-part of stage 2 (C, V^{m+1}) and
+ * the column iterations (U^{m+1}, W^{m+1}) (Algorithms 1 and 2).
+ *
+ * Arrays are row-major, row index j along y, column index i along x, all of
+ * the problem's dtype (float for ADI_FP32, double for ADI_FP64), in device
+ * memory.  Shapes (rows x cols):
+ *                 CFD                MFD
+ *   U, K          (ny+1) x (nx+1)    (ny+2) x (nx+2)   pressure points
+ *   V, Rv         (ny+1) x (nx+1)    (ny+2) x (nx+1)   horizontal velocity
+ *   W, Rw         (ny+1) x (nx+1)    (ny+1) x (nx+2)   vertical velocity
+ * K holds kappa at the pressure points, Rv and Rw hold 1/rho at the velocity
+ * points.  Boundary pressure entries are Dirichlet data and stay zero; the
+ * first and last rows of V and the first and last columns of W are never
+ * read or written.
+ *
+ * Status codes: every entry point returns an adi_status; arguments are
+ * validated on the host before any device work is queued.  No entry point
+ * aborts, throws or prints.
+ *
+ * Threads: one adi_problem must not be used by two host threads at once.
+ * Device work is queued asynchronously on the stream given at creation.
+ */
+#ifndef ADI_H
+#define ADI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum adi_status {
+    ADI_OK = 0,
+    ADI_EINVAL = -1,     /* invalid argument (message: adi_last_error) */
+    ADI_ENOMEM = -2,     /* device allocation failed */
+    ADI_EDEVICE = -3,    /* a HIP runtime call failed */
+    ADI_EBUSY = -4,      /* object in use */
+    ADI_ENOTREADY = -5,  /* problem not bound yet */
+    ADI_ENUMERIC = -6    /* non-finite values detected */
+} adi_status;
+
+typedef enum adi_method { ADI_CFD = 0, ADI_MFD = 1 } adi_method;
+typedef enum adi_dtype { ADI_FP32 = 0, ADI_FP64 = 1 } adi_dtype;
+
+/* Problem description.  Set struct_size = sizeof(adi_params); fill the rest
+ * or start from adi_params_init. */
+typedef struct adi_params {
+    uint32_t struct_size;
+    int32_t method;      /* adi_method */
+    int32_t dtype;       /* adi_dtype */
+    int32_t order;       /* 0: x-implicit stage first (the paper's order) */
+    int32_t nx, ny;      /* cells per direction, each >= 8 */
+    int32_t sweeps;      /* fixed-point sweeps per stage: even, >= 2 (paper: 6-8) */
+    int32_t src_i, src_j;/* pressure index (column i, row j) of the Ricker point
+                            source, both interior; -1 = no source */
+    int32_t reserved0;
+    double h;            /* grid spacing (both directions) */
+    double dt;           /* time step; cfl = dt c_max / h must stay below the
+                            fixed-point limit: 1.15 (CFD), 0.81 (MFD) */
+    double t0;           /* time of step 0 */
+    double c_max;        /* maximum wave speed sqrt(kappa / rho) */
+    double kappa0;       /* kappa when no K array is bound */
+    double rinv0;        /* 1/rho when no Rv / Rw array is bound */
+    double src_f0;       /* Ricker peak frequency */
+    double src_t0;       /* Ricker delay */
+    double src_amp;      /* Ricker amplitude; forcing = s(t) / h^2 at the point */
+} adi_params;
+
+typedef struct adi_problem adi_problem;
+
+/* Human-readable name of a status code (static storage). */
+const char* adi_status_string(int status);
+
+/* Message of the last error raised on this host thread ("" if none). */
+const char* adi_last_error(void);
+
+/* Fill *p with defaults: CFD, FP32, order 0, 6 sweeps, no source,
+ * kappa0 = rinv0 = 1, struct_size set.  Sizes, h, dt, c_max left zero. */
+int adi_params_init(adi_params* p);
+
+/* Validate *p and create a problem bound to the current HIP device and to
+ * hip_stream (a hipStream_t, or NULL for the null stream).  No device memory
+ * is allocated until adi_bind.  *out receives the handle; release it with
+ * adi_destroy. */
+int adi_create(const adi_params* p, void* hip_stream, adi_problem** out);
+
+/* Bytes of device workspace adi_bind needs for these parameters, given which
+ * material arrays will be bound (non-zero flag = array present). */
+int adi_workspace_size(const adi_params* p, int has_K, int has_Rv, int has_Rw,
+                       size_t* bytes);
+
+/* Attach the caller's device arrays (shapes above).  U, V, W hold the state
+ * and are updated in place by adi_step / adi_run; K, Rv, Rw may be NULL
+ * (constant kappa0 / rinv0) and are read during this call only.  ld[0..5]
+ * are the leading dimensions (elements) of U, V, W, K, Rv, Rw; NULL or 0
+ * entries mean densely packed rows.  workspace may be NULL (the library then
+ * allocates and owns it) or caller memory of at least adi_workspace_size
+ * bytes, 256-byte aligned, which the caller keeps alive until adi_destroy.
+ * The call returns after the device has consumed K, Rv, Rw.  Resets the step
+ * counter to 0. */
+int adi_bind(adi_problem* pb, void* U, void* V, void* W,
+             const void* K, const void* Rv, const void* Rw,
+             const int64_t* ld, void* workspace, size_t workspace_bytes);
+
+/* Queue nsteps Peaceman-Rachford steps (Algorithm 1 / 2 loop body) on the
+ * problem's stream.  On completion U, V, W hold time level m + nsteps. */
+int adi_run(adi_problem* pb, int64_t nsteps);
+
+/* adi_run(pb, 1). */
+int adi_step(adi_problem* pb);
+
+/* Wait for all queued work of the problem. */
+int adi_sync(adi_problem* pb);
+
+/* Current time level m (time t0 + m dt) / set it (checkpoint resume). */
+int adi_get_step(const adi_problem* pb, int64_t* m);
+int adi_set_step(adi_problem* pb, int64_t m);
+
+/* Free the problem and any workspace the library allocated. */
+int adi_destroy(adi_problem* pb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADI_H */

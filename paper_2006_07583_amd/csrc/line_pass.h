@@ -1,0 +1,44 @@
+// Internal interface between the host layer and the line-pass kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adi {
+
+enum { LINE_CFD = 0, LINE_MFD = 1 };
+enum { LINE_SWEEP = 0, LINE_FINAL = 1, LINE_EXPLICIT = 2 };
+enum { LINE_WS = 512 };   // slots per window (both dtypes)
+
+// Arguments of one line pass.  Along a line, slot s holds the pressure value
+// of index s (interior slots 1..n-1 for CFD, 1..n for MFD) and the velocity
+// value of node s (0..n).  For line q:
+//   uin[(s-1)*uin_ld + q], ak[(s-1)*ak_ld + q]        pressure-type inputs
+//   vin[s*vin_ld + q],     ar[s*ar_ld + q]            velocity-type inputs
+//   vout[s*vout_ld + q]                                velocity output
+//   uout[q*uout_ld + (s-1)]  (transposed), or uout[(s-1)*uout_ld + q] (final)
+template <typename T>
+struct LinePassArgs {
+    const T* uin; int64_t uin_ld;
+    const T* vin; int64_t vin_ld;
+    const T* ak;  int64_t ak_ld;     // a*kappa, NULL -> ak0
+    const T* ar;  int64_t ar_ld;     // a*(1/rho), NULL -> ar0
+    T* vout; int64_t vout_ld;
+    T* uout; int64_t uout_ld;
+    const T* coef;                   // compact: [nwin][6][LINE_WS] factor tables
+    T ak0, ar0, inv_h, aF;
+    int nlines, n, ns, nlg, nwin, S, H, sweeps;
+    int src_q, src_s;                // source (line, slot), -1 = none
+    int deep;                        // single window: deep halo exchange
+};
+
+template <typename T>
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st);
+
+template <typename T>
+hipError_t launch_scaled_copy(T* dst, int64_t dld, const T* src, int64_t srs, int64_t scs, int rows,
+                              int cols, T scale, hipStream_t st);
+
+int line_lanes(int dtype);
+int line_halo(int dtype, int method, int sweeps);
+
+}  // namespace adi

@@ -1,0 +1,526 @@
+// Windowed line pass of the Peaceman-Rachford ADI step on CDNA4 (gfx950).
+//
+// One launch performs, for every interior grid line of one direction, the
+// implicit half of a Peaceman-Rachford stage (the fixed-point sweeps of
+// eqs. adiSolve / adiSolve2, Algorithms 3 and 4) fused with the explicit half
+// of the following stage along the same line (the C / V^{m+1} computations of
+// Algorithm 1, or A / W* of the next step).  With a = dt/2 and, along the
+// line, G = pressure->velocity derivative, D = velocity->pressure derivative:
+//     u_1 = A - aK D(B)
+//     u_k = A - aK D(B - aR G(u_{k-1}))           k = 2..K
+//     v_K = B - aR G(u_K)
+//     vel_out = 2 v_K - B   ( = v_K - aR G(u_K) )
+//     U_out   = u_K - aK D(v_K) + aF
+// (FINAL mode writes u_K and v_K instead; EXPLICIT mode writes
+//  B - aR G(A) and A - aK D(B) + aF.)
+//
+// Data placement.  A workgroup owns LW adjacent lines (adjacent in memory,
+// so every global access is a full 128-byte row segment) and a window of WS
+// consecutive positions ("slots") along them.  Lane l of wave w handles line
+// l % LW and the R consecutive slots of segment w*(64/LW) + l/LW; all line
+// data of a window lives in VGPRs.  Stencil halos and the carries of the
+// segmented tridiagonal recurrences cross segments through LDS.  Windows of
+// one line overlap by H slots on each side; only the central slots are
+// written.  The windowed problem drops the couplings to slots outside the
+// window; for the compact scheme the inverse of P decays like
+// (2 - sqrt 3)^d, so with H chosen per dtype the central values equal the
+// full-line values to below the rounding unit (the mimetic stencils have a
+// finite dependence cone and H covers it exactly).
+//
+// Compact operators (Appendix A): G = P^-1 Q, D = Pbar^-1 Qbar, each one
+// tridiagonal solve with the no-pivot LU factors of the window-restricted
+// matrix (precomputed on the host per window, staged in LDS).  A window edge
+// inside the line gets the diagonal 2 + sqrt 3 so its factors equal the
+// interior limit.  Within a workgroup the forward and backward recurrences
+// are split over segments: each lane runs its segment with zero carry, the
+// carries of the previous (next) TS segments are combined from LDS, and the
+// segment is corrected with the products of the multipliers.  Carries from
+// farther segments are below the rounding unit (factor (2 - sqrt 3)^(R TS)).
+//
+// Mimetic operators (Appendix B): explicit 4-tap stencils with the printed
+// 6/5-tap boundary rows and their centro-skew mirrors.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "line_pass.h"
+
+namespace adi {
+
+template <typename T> struct Tile;
+template <> struct Tile<float> {
+    static constexpr int LW = 32, R = 16, NW = 16, TS = 2;
+};
+template <> struct Tile<double> {
+    static constexpr int LW = 16, R = 8, NW = 16, TS = 4;
+};
+
+template <typename T> struct K {
+    static constexpr int LW = Tile<T>::LW, R = Tile<T>::R, NW = Tile<T>::NW, TS = Tile<T>::TS;
+    static constexpr int SPW = 64 / LW;
+    static constexpr int NSEG = NW * SPW;
+    static constexpr int WS = NSEG * R;
+    static constexpr int NT = NW * 64;
+    static constexpr int SL = NSEG * LW;   // one LDS field: a value per lane
+};
+
+static_assert(K<float>::WS == LINE_WS, "window size");
+static_assert(K<double>::WS == LINE_WS, "window size");
+
+template <int METHOD> struct Halo;
+template <> struct Halo<LINE_CFD> { static constexpr int N = 1, DEEP = 3; };
+template <> struct Halo<LINE_MFD> { static constexpr int N = 2, DEEP = 5; };
+
+// Value at compile-time position p of the lane's extended line: own slots,
+// or halos from the neighbouring segments; zero beyond the halos.
+template <typename T, int R, int D>
+__device__ __forceinline__ T xv(const T (&x)[R], const T (&hl)[D], const T (&hr)[D], int p) {
+    return p < -D ? T(0) : (p < 0 ? hl[D + p] : (p < R ? x[p] : (p < R + D ? hr[p - R] : T(0))));
+}
+
+template <typename T, int METHOD> struct Pass {
+    using C = K<T>;
+    static constexpr int LW = C::LW, R = C::R, NSEG = C::NSEG, WS = C::WS, SL = C::SL, TS = C::TS;
+    static constexpr int DN = Halo<METHOD>::N, DD = Halo<METHOD>::DEEP;
+    static constexpr int HF = (4 * DN > 2 * DD ? 4 * DN : 2 * DD) / 2;   // fields per ring half
+    static constexpr int RING = 2 * HF * SL;                              // elements
+    static constexpr int TAB = METHOD == LINE_CFD ? 6 * WS : 0;
+    static constexpr int TILEP = WS + 1;                                  // padded tile row
+    static constexpr int TILE = LW * TILEP;
+    static constexpr int WORK = RING + TAB;
+    static constexpr int SMEM = WORK > TILE ? WORK : TILE;
+
+    const LinePassArgs<T>& a;
+    T* ring;
+    const T* tab;
+    int seg, lq, li, s0, q, n, xc;
+    bool deep, bnd;
+
+    __device__ Pass(const LinePassArgs<T>& args, T* smem, int seg_, int lq_, int s0_, int q_)
+        : a(args), ring(smem), tab(smem + RING), seg(seg_), lq(lq_), li(seg_ * LW + lq_), s0(s0_),
+          q(q_), n(args.n), xc(0), deep(args.deep != 0), bnd(s0_ <= 1 || s0_ + R - 1 >= args.n - 1) {}
+
+    // ---- halo exchange of the first / last D values of x ----
+    template <int D>
+    __device__ __forceinline__ void publish(T* b, const T (&x)[R]) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            b[i * SL + li] = x[i];
+            b[(D + i) * SL + li] = x[R - D + i];
+        }
+    }
+    template <int D>
+    __device__ __forceinline__ void fetch(const T* b, T (&hl)[D], T (&hr)[D]) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            hl[i] = seg > 0 ? b[(D + i) * SL + (seg - 1) * LW + lq] : T(0);
+            hr[i] = seg < NSEG - 1 ? b[i * SL + (seg + 1) * LW + lq] : T(0);
+        }
+    }
+
+    // ---- pressure -> velocity derivative right-hand side / stencil ----
+    template <int D>
+    __device__ __forceinline__ void stencil_g(const T (&x)[R], const T (&hl)[D], const T (&hr)[D], T (&o)[R]) {
+        const T ih = a.inv_h;
+        if (METHOD == LINE_CFD) {
+            // Q4 u / h: interior 3 (u_{s+1} - u_{s-1}) / h
+            const T c3 = T(3) * ih;
+#pragma unroll
+            for (int k = 0; k < R; ++k) o[k] = c3 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 1));
+            if (bnd) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 0)
+                        o[k] = ih * (T(-17) * xv(x, hl, hr, k) + T(9) * xv(x, hl, hr, k + 1) +
+                                     T(9) * xv(x, hl, hr, k + 2) - xv(x, hl, hr, k + 3));
+                    if (s == n)
+                        o[k] = ih * (xv(x, hl, hr, k - 3) - T(9) * xv(x, hl, hr, k - 2) -
+                                     T(9) * xv(x, hl, hr, k - 1) + T(17) * xv(x, hl, hr, k));
+                }
+            }
+        } else {
+            // G4 u: interior (u_{s-1} - 27 u_s + 27 u_{s+1} - u_{s+2}) / (24 h)
+            const T c1 = T(9.0 / 8.0) * ih, c0 = T(-1.0 / 24.0) * ih;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                o[k] = c1 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k)) +
+                       c0 * (xv(x, hl, hr, k + 2) - xv(x, hl, hr, k - 1));
+            if (bnd) {
+                const T g0[6] = {T(-47888.0 / 14245.0), T(1790.0 / 407.0), T(-14545.0 / 9768.0),
+                                 T(8997.0 / 16280.0), T(-2335.0 / 22792.0), T(25.0 / 9768.0)};
+                const T g1[5] = {T(16.0 / 105.0), T(-31.0 / 24.0), T(29.0 / 24.0), T(-3.0 / 40.0),
+                                 T(1.0 / 168.0)};
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 0) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc += g0[c] * xv(x, hl, hr, k + c);
+                        o[k] = acc * ih;
+                    }
+                    if (s == 1) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) acc += g1[c] * xv(x, hl, hr, k - 1 + c);
+                        o[k] = acc * ih;
+                    }
+                    if (s == n - 1) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) acc += g1[c] * xv(x, hl, hr, k + 2 - c);
+                        o[k] = -acc * ih;
+                    }
+                    if (s == n) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc += g0[c] * xv(x, hl, hr, k + 1 - c);
+                        o[k] = -acc * ih;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- velocity -> pressure derivative right-hand side / stencil ----
+    template <int D>
+    __device__ __forceinline__ void stencil_d(const T (&x)[R], const T (&hl)[D], const T (&hr)[D], T (&o)[R]) {
+        const T ih = a.inv_h;
+        if (METHOD == LINE_CFD) {
+            const T c3 = T(3) * ih;
+#pragma unroll
+            for (int k = 0; k < R; ++k) o[k] = c3 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 1));
+            if (bnd) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 1)
+                        o[k] = ih * (-xv(x, hl, hr, k - 1) - T(9) * xv(x, hl, hr, k) +
+                                     T(9) * xv(x, hl, hr, k + 1) + xv(x, hl, hr, k + 2));
+                    if (s == n - 1)
+                        o[k] = ih * (-xv(x, hl, hr, k - 2) - T(9) * xv(x, hl, hr, k - 1) +
+                                     T(9) * xv(x, hl, hr, k) + xv(x, hl, hr, k + 1));
+                }
+            }
+        } else {
+            const T c1 = T(9.0 / 8.0) * ih, c0 = T(-1.0 / 24.0) * ih;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                o[k] = c1 * (xv(x, hl, hr, k) - xv(x, hl, hr, k - 1)) +
+                       c0 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 2));
+            if (bnd) {
+                const T d0[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
+                                 T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 1) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc += d0[c] * xv(x, hl, hr, k - 1 + c);
+                        o[k] = acc * ih;
+                    }
+                    if (s == n) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc += d0[c] * xv(x, hl, hr, k - c);
+                        o[k] = -acc * ih;
+                    }
+                }
+            }
+        }
+    }
+
+    // o = derivative (kind 0: pressure->velocity, 1: velocity->pressure) of x
+    template <int KIND>
+    __device__ __forceinline__ void deriv(const T (&x)[R], T (&o)[R]) {
+        if (!deep) {
+            T hl[DN], hr[DN];
+            T* b = ring + (xc & 1) * HF * SL;
+            ++xc;
+            publish<DN>(b, x);
+            __syncthreads();
+            fetch<DN>(b, hl, hr);
+            if (KIND == 0) stencil_g<DN>(x, hl, hr, o); else stencil_d<DN>(x, hl, hr, o);
+        } else {
+            T hl[DD], hr[DD];
+            __syncthreads();
+            publish<DD>(ring, x);
+            __syncthreads();
+            fetch<DD>(ring, hl, hr);
+            __syncthreads();
+            if (KIND == 0) stencil_g<DD>(x, hl, hr, o); else stencil_d<DD>(x, hl, hr, o);
+        }
+        if (METHOD == LINE_CFD) solve(o, tab + (KIND == 0 ? 0 : 3 * WS));
+    }
+
+    // In-place solve of the window's tridiagonal system (factor tables t:
+    // multipliers, inverse pivots, superdiagonal times inverse pivot).
+    __device__ __forceinline__ void solve(T (&x)[R], const T* t) {
+        const int sl0 = seg * R;
+        const T* m = t + sl0;
+        const T* dv = t + WS + sl0;
+        const T* e = t + 2 * WS + sl0;
+        // forward elimination with zero carry-in
+        T g = -m[0];
+#pragma unroll
+        for (int k = 1; k < R; ++k) {
+            const T mk = m[k];
+            x[k] = fma(-mk, x[k - 1], x[k]);
+            g = -mk * g;
+        }
+        T* b = ring + (xc & 1) * HF * SL;
+        ++xc;
+        b[li] = x[R - 1];
+        b[SL + li] = g;
+        __syncthreads();
+        T Y = T(0), pref = T(1);
+#pragma unroll
+        for (int tt = 1; tt <= TS; ++tt) {
+            const int sg = seg - tt;
+            if (sg >= 0) {
+                Y = fma(pref, b[sg * LW + lq], Y);
+                pref *= b[SL + sg * LW + lq];
+            }
+        }
+        T gg = -m[0];
+        x[0] = fma(gg, Y, x[0]);
+#pragma unroll
+        for (int k = 1; k < R; ++k) {
+            gg = -m[k] * gg;
+            x[k] = fma(gg, Y, x[k]);
+        }
+        // back substitution with zero carry-in
+        x[R - 1] *= dv[R - 1];
+        T qv = -e[R - 1];
+#pragma unroll
+        for (int k = R - 2; k >= 0; --k) {
+            x[k] = fma(-e[k], x[k + 1], x[k] * dv[k]);
+            qv = -e[k] * qv;
+        }
+        b = ring + (xc & 1) * HF * SL;
+        ++xc;
+        b[li] = x[0];
+        b[SL + li] = qv;
+        __syncthreads();
+        T X = T(0);
+        pref = T(1);
+#pragma unroll
+        for (int tt = 1; tt <= TS; ++tt) {
+            const int sg = seg + tt;
+            if (sg < NSEG) {
+                X = fma(pref, b[sg * LW + lq], X);
+                pref *= b[SL + sg * LW + lq];
+            }
+        }
+        T qq = -e[R - 1];
+        x[R - 1] = fma(qq, X, x[R - 1]);
+#pragma unroll
+        for (int k = R - 2; k >= 0; --k) {
+            qq = -e[k] * qq;
+            x[k] = fma(qq, X, x[k]);
+        }
+    }
+};
+
+template <typename T, int METHOD, int MODE>
+__global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<T> a) {
+    using P = Pass<T, METHOD>;
+    constexpr int LW = K<T>::LW, R = K<T>::R, SPW = K<T>::SPW, WS = K<T>::WS;
+    __shared__ T smem[P::SMEM];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lq = lane % LW;
+    const int seg = wave * SPW + lane / LW;
+    const int lg = blockIdx.x % a.nlg;
+    const int g = blockIdx.x / a.nlg;
+    const int c0 = g * a.S;
+    const int c1 = min(c0 + a.S, a.ns);
+    int w0 = 0;
+    if (a.nwin > 1) w0 = max(0, min(c0 - a.H, a.ns - WS));
+    const int s0 = w0 + seg * R;
+    const int q = lg * LW + lq;
+    const bool qok = q < a.nlines;
+    const int n = a.n;
+    const int ulo = 1, uhi = METHOD == LINE_CFD ? n - 1 : n;   // interior pressure slots
+    const int vhi = n;                                          // velocity slots 0..n
+
+    P p(a, smem, seg, lq, s0, q);
+
+    if (METHOD == LINE_CFD) {
+        const T* src = a.coef + (size_t)g * 6 * WS;
+        for (int i = tid; i < 6 * WS; i += K<T>::NT) smem[P::RING + i] = src[i];
+    }
+
+    T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int s = s0 + k;
+        const bool uv = qok && s >= ulo && s <= uhi;
+        const bool vv = qok && s <= vhi;
+        A[k] = uv ? a.uin[(int64_t)(s - 1) * a.uin_ld + q] : T(0);
+        KK[k] = uv ? (a.ak ? a.ak[(int64_t)(s - 1) * a.ak_ld + q] : a.ak0) : T(0);
+        B[k] = vv ? a.vin[(int64_t)s * a.vin_ld + q] : T(0);
+        RR[k] = vv ? (a.ar ? a.ar[(int64_t)s * a.ar_ld + q] : a.ar0) : T(0);
+    }
+    if (METHOD == LINE_CFD) __syncthreads();   // tables visible
+
+    if (MODE == LINE_EXPLICIT) {
+        p.template deriv<0>(A, Tt);                 // G(A)
+#pragma unroll
+        for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // B - aR G(A)
+        p.template deriv<1>(B, U);                  // D(B)
+#pragma unroll
+        for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);     // A - aK D(B)
+    } else {
+        p.template deriv<1>(B, U);
+#pragma unroll
+        for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+        for (int it = 1; it < a.sweeps; ++it) {
+            p.template deriv<0>(U, Tt);
+#pragma unroll
+            for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
+            p.template deriv<1>(Tt, U);
+#pragma unroll
+            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+        }
+        p.template deriv<0>(U, Tt);
+#pragma unroll
+        for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // v_K
+        if (MODE == LINE_SWEEP) {
+            p.template deriv<1>(Tt, A);                                   // D(v_K)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T vk = Tt[k];
+                Tt[k] = vk + (vk - B[k]);                                  // 2 v_K - B
+                U[k] = fma(-KK[k], A[k], U[k]);                            // u_K - aK D(v_K)
+            }
+        }
+    }
+
+    // ---- velocity output (central slots, native layout) ----
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int s = s0 + k;
+        if (qok && s >= c0 && s < c1 && s <= vhi) a.vout[(int64_t)s * a.vout_ld + q] = Tt[k];
+    }
+
+    // ---- pressure output ----
+    if (MODE != LINE_FINAL) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (q == a.src_q && s0 + k == a.src_s) U[k] += a.aF;
+    }
+    if (MODE == LINE_FINAL) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int s = s0 + k;
+            if (qok && s >= c0 && s < c1 && s >= ulo && s <= uhi)
+                a.uout[(int64_t)(s - 1) * a.uout_ld + q] = U[k];
+        }
+    } else {
+        // transposed store through an LDS tile: line-major rows of the
+        // central slots, written with consecutive threads on consecutive slots
+        __syncthreads();
+        T* tile = smem;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int s = s0 + k;
+            if (s >= c0 && s < c1) tile[lq * P::TILEP + (s - c0)] = U[k];
+        }
+        __syncthreads();
+        const int nc = c1 - c0;
+        const int lo = max(c0, ulo), hi = min(c1 - 1, uhi);
+        const int nv = hi - lo + 1;
+        if (nv > 0) {
+            for (int idx = tid; idx < LW * nv; idx += K<T>::NT) {
+                const int l = idx / nv, j = idx - l * nv;
+                const int qq = lg * LW + l;
+                if (qq < a.nlines)
+                    a.uout[(int64_t)qq * a.uout_ld + (lo + j - 1)] = tile[l * P::TILEP + (lo - c0) + j];
+            }
+        }
+        (void)nc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Setup kernels: scaled copy with optional transpose (32 x 32 LDS tiles).
+//   dst[r * dld + c] = scale * src[r * srs + c * scs],  r < rows, c < cols
+// With scs == 1 rows are read contiguously; with srs == 1 the tile is read
+// along columns and written along rows (a transpose).
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, int64_t dld,
+                                                          const T* __restrict__ src, int64_t srs,
+                                                          int64_t scs, int rows, int cols, T scale) {
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    if (srs == 1) {
+        // source contiguous along r: read with tx along r
+#pragma unroll
+        for (int i = 0; i < 32; i += 8) {
+            const int r = r0 + tx, c = c0 + ty + i;
+            tile[ty + i][tx] = (r < rows && c < cols) ? src[(int64_t)r * srs + (int64_t)c * scs] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 32; i += 8) {
+            const int r = r0 + ty + i, c = c0 + tx;
+            if (r < rows && c < cols) dst[(int64_t)r * dld + c] = scale * tile[tx][ty + i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 32; i += 8) {
+            const int r = r0 + ty + i, c = c0 + tx;
+            if (r < rows && c < cols) dst[(int64_t)r * dld + c] = scale * src[(int64_t)r * srs + (int64_t)c * scs];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
+    dim3 grid((unsigned)(a.nlg * a.nwin)), block(K<T>::NT);
+#define LP_CASE(M, MD)                                                                 \
+    if (method == M && mode == MD) {                                                   \
+        hipLaunchKernelGGL((line_pass_kernel<T, M, MD>), grid, block, 0, st, a);       \
+        return hipGetLastError();                                                      \
+    }
+    LP_CASE(LINE_CFD, LINE_SWEEP)
+    LP_CASE(LINE_CFD, LINE_FINAL)
+    LP_CASE(LINE_CFD, LINE_EXPLICIT)
+    LP_CASE(LINE_MFD, LINE_SWEEP)
+    LP_CASE(LINE_MFD, LINE_FINAL)
+    LP_CASE(LINE_MFD, LINE_EXPLICIT)
+#undef LP_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_scaled_copy(T* dst, int64_t dld, const T* src, int64_t srs, int64_t scs, int rows,
+                              int cols, T scale, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), block(256);
+    hipLaunchKernelGGL((scaled_copy_kernel<T>), grid, block, 0, st, dst, dld, src, srs, scs, rows, cols, scale);
+    return hipGetLastError();
+}
+
+int line_lanes(int dtype) { return dtype == 0 ? K<float>::LW : K<double>::LW; }
+
+// Overlap of neighbouring windows, in slots.  Mimetic: the dependence cone
+// of K sweeps plus the final derivative is 3K + 2 slots; two slots spare.
+// Compact: the window-edge error decays like (2 - sqrt 3)^d times the number
+// of chained solves (2K + 1); the margins keep it below the rounding unit.
+int line_halo(int dtype, int method, int sweeps) {
+    if (method == LINE_MFD) return 3 * sweeps + 4;
+    return dtype == 0 ? 20 + 2 * sweeps : 40 + 3 * sweeps;
+}
+
+template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_scaled_copy<float>(float*, int64_t, const float*, int64_t, int64_t, int, int, float, hipStream_t);
+template hipError_t launch_scaled_copy<double>(double*, int64_t, const double*, int64_t, int64_t, int, int, double, hipStream_t);
+
+}  // namespace adi

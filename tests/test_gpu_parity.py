@@ -1,0 +1,114 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: FP64 max|gpu - oracle| / max|oracle| <= 1e-12 per field; FP32 relative
+L2 <= 1e-4 per field after all steps.  Entries the method never writes must
+come back unchanged.
+"""
+import math
+
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_07583_amd import adi, inputs
+from tests.gpu_util import log, max_rel, rel_l2, run_gpu, written_parts
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-4
+
+
+def case(method, nx, ny, seed, medium=True, source=True):
+    h = 1.0 / max(nx, ny)
+    f = inputs.random_fields(method, nx, ny, seed)
+    med = inputs.random_medium(method, nx, ny, seed + 1) if medium else {"K": None, "Rv": None, "Rw": None}
+    cmax = 1.0
+    if medium:
+        cmax = math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    src = {"i": max(1, nx // 3), "j": max(1, ny // 2), "f0": 4.0, "t0": 0.1, "amp": 1.0} if source else None
+    return h, f, med, cmax, src
+
+
+def compare(method, dtype, nx, ny, seed, nsteps, cfl, sweeps=6, medium=True, source=True, chunks=None):
+    h, f, med, cmax, src = case(method, nx, ny, seed, medium, source)
+    dt = cfl * h / cmax
+    log(f"case method={method} dtype={dtype} nx={nx} ny={ny} steps={nsteps} sweeps={sweeps} seed={seed}")
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, sweeps=sweeps,
+                K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    got = run_gpu(method, dtype, f, h=h, dt=dt, c_max=cmax, nsteps=nsteps, sweeps=sweeps,
+                  K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src, chunks=chunks)
+    errs = []
+    for g, r in zip(written_parts(method, *got), written_parts(method, *ref)):
+        errs.append(max_rel(g, r) if dtype == adi.FP64 else rel_l2(g, r))
+    # untouched entries
+    U, V, W = got
+    for a, b in ((U[0], f["U"][0]), (U[-1], f["U"][-1]), (U[:, 0], f["U"][:, 0]), (U[:, -1], f["U"][:, -1]),
+                 (V[0], f["V"][0]), (V[-1], f["V"][-1]), (W[:, 0], f["W"][:, 0]), (W[:, -1], f["W"][:, -1])):
+        tol = 0 if dtype == adi.FP64 else 1e-6 * np.abs(b).max()
+        assert np.abs(a - b).max() <= tol
+    log(f"  errors U,V,W = {errs}")
+    return errs
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (9, 13), (33, 20), (64, 64)])
+def test_small_grids_fp64(method, nx, ny):
+    errs = compare(method, adi.FP64, nx, ny, 7 * nx + ny, 5, 0.6)
+    assert max(errs) <= TOL64, errs
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (33, 20), (100, 77)])
+def test_small_grids_fp32(method, nx, ny):
+    errs = compare(method, adi.FP32, nx, ny, 3 * nx + ny, 5, 0.6)
+    assert max(errs) <= TOL32, errs
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
+def test_multi_window_lines(method, dtype):
+    """Lines longer than one window (several overlapping windows, ragged tail)."""
+    errs = compare(method, dtype, 1300, 600, 11, 3, 0.8 if method == adi.MFD else 1.0)
+    assert max(errs) <= (TOL64 if dtype == adi.FP64 else TOL32), errs
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("sweeps", [2, 8, 16])
+def test_sweep_counts(method, sweeps):
+    errs = compare(method, adi.FP64, 530, 40, 5, 2, 0.5, sweeps=sweeps)
+    assert max(errs) <= TOL64, errs
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+def test_constant_medium_no_source(method):
+    errs = compare(method, adi.FP64, 70, 90, 2, 6, 0.7, medium=False, source=False)
+    assert max(errs) <= TOL64, errs
+
+
+@pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
+def test_split_runs_equal_one_run(dtype):
+    """n + n steps in two calls give the same state as 2n steps in one call."""
+    h, f, med, cmax, src = case(adi.MFD, 40, 50, 4)
+    kw = dict(h=h, dt=0.5 * h / cmax, c_max=cmax, K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    a = run_gpu(adi.MFD, dtype, f, nsteps=6, **kw)
+    b = run_gpu(adi.MFD, dtype, f, nsteps=6, chunks=[3, 3], **kw)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= (1e-14 if dtype == adi.FP64 else 1e-6) * max(np.abs(x).max(), 1)
+
+
+def test_config1_cfd_standing_wave_fp64():
+    """CFD FP64, 101 x 101 nodes, c = 1, dt = h, 100 steps: parity with the
+    oracle and the PR-CN time error 4.402e-4 against the exact solution."""
+    N = 100
+    h = 1.0 / N
+    f = inputs.standing_mode(adi.CFD, N, N, h, 1, 1)
+    log("case config1 CFD FP64 N=100 steps=100")
+    ref = O.run(O.CFD, f["U"], f["V"], f["W"], h=h, dt=h, nsteps=N, sweeps=6)
+    got = run_gpu(adi.CFD, adi.FP64, f, h=h, dt=h, c_max=1.0, nsteps=N)
+    for g, r in zip(written_parts(adi.CFD, *got), written_parts(adi.CFD, *ref)):
+        assert max_rel(g, r) <= TOL64
+    err = np.abs(got[0] - f["U"] * math.cos(math.sqrt(2) * math.pi)).max()
+    assert err == pytest.approx(4.402e-4, rel=1e-2)
