@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=6)
     ap.add_argument("--methods", default="cfd,mfd")
     ap.add_argument("--dtypes", default="fp32,fp64")
-    ap.add_argument("--cpu-baseline-steps", type=int, default=3)
+    ap.add_argument("--cpu-baseline-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
