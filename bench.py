@@ -50,7 +50,7 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps):
     import torch
     from paper_2006_07583_amd import adi, inputs
     pr = inputs.seismic_problem(method, n, seed=0)
-    tdt = torch.float32 if dtype == adi.FP32 else torch.float64
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
     U, V, W, K = t(pr["U"]), t(pr["V"]), t(pr["W"]), t(pr["K"])

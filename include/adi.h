@@ -21,7 +21,7 @@
  *
  * Arrays are row-major, row index j along y, column index i along x, all of
  * the problem's dtype (float for ADI_FP32, double for ADI_FP64), in device
- * memory.  Shapes (rows x cols):
+ * memory (ADI_FP32C uses float arrays).  Shapes (rows x cols):
  *                 CFD                MFD
  *   U, K          (ny+1) x (nx+1)    (ny+2) x (nx+2)   pressure points
  *   V, Rv         (ny+1) x (nx+1)    (ny+2) x (nx+1)   horizontal velocity
@@ -59,7 +59,12 @@ typedef enum adi_status {
 } adi_status;
 
 typedef enum adi_method { ADI_CFD = 0, ADI_MFD = 1 } adi_method;
-typedef enum adi_dtype { ADI_FP32 = 0, ADI_FP64 = 1 } adi_dtype;
+/* ADI_FP32C: FP32 arithmetic and FP32 caller arrays; within a run the state
+ * carried between passes is kept as (value, low word) pairs and every pass
+ * accumulates its FP32 increment with TwoSum, so rounding does not build up
+ * over many steps.  The low words live in the workspace for the duration of
+ * one adi_run call (the caller's arrays receive the rounded sum). */
+typedef enum adi_dtype { ADI_FP32 = 0, ADI_FP64 = 1, ADI_FP32C = 2 } adi_dtype;
 
 /* Problem description.  Set struct_size = sizeof(adi_params); fill the rest
  * or start from adi_params_init. */
@@ -67,7 +72,7 @@ typedef struct adi_params {
     uint32_t struct_size;
     int32_t method;      /* adi_method */
     int32_t dtype;       /* adi_dtype */
-    int32_t order;       /* 0: x-implicit stage first (the paper's order) */
+    int32_t order;       /* 0: x-implicit stage first (the paper's order); 1: y-implicit first */
     int32_t nx, ny;      /* cells per direction, each >= 8 */
     int32_t sweeps;      /* fixed-point sweeps per stage: even, >= 2 (paper: 6-8) */
     int32_t src_i, src_j;/* pressure index (column i, row j) of the Ricker point

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadi.so")
 
 CFD, MFD = 0, 1
-FP32, FP64 = 0, 1
+FP32, FP64, FP32C = 0, 1, 2
 
 STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
           -4: "ADI_EBUSY", -5: "ADI_ENOTREADY", -6: "ADI_ENUMERIC"}

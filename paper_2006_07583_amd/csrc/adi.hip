@@ -54,6 +54,8 @@ constexpr double kDelta = 3.7320508075688772935;   // 2 + sqrt 3, interior pivot
 
 struct Plan {
     int n = 0, ns = 0, nlines = 0, nlg = 0, nwin = 0, S = 0, H = 0, deep = 0;
+    int ver = 1;   // 1: single-window kernel (line_pass.hip), 2: multi-window (line_pass2.hip)
+    int seg = 0;   // slots per lane segment of the multi-window kernel
 };
 
 int64_t pad_to(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -63,18 +65,21 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
     p.n = n;
     p.ns = method == ADI_CFD ? n + 1 : n + 2;
     p.nlines = nlines;
-    const int lw = adi::line_lanes(dtype);
-    p.nlg = (nlines + lw - 1) / lw;
     p.H = adi::line_halo(dtype, method, sweeps);
     if (p.ns <= adi::LINE_WS) {
+        p.ver = 1;
         p.nwin = 1;
         p.S = p.ns;
         p.deep = 1;
     } else {
+        p.ver = 2;
+        p.seg = adi::line2_seg(dtype);
         p.S = adi::LINE_WS - 2 * p.H;
         p.nwin = (p.ns + p.S - 1) / p.S;
         p.deep = 0;
     }
+    const int lw = p.ver == 1 ? adi::line_lanes(dtype) : adi::line2_lanes(dtype);
+    p.nlg = (nlines + lw - 1) / lw;
     return p;
 }
 
@@ -121,6 +126,62 @@ double coef_Pbar(int r, int which, int n) {
     return which == 1 ? 4.0 : 1.0;
 }
 
+// Multi-window tables: per window and kind (P, Pbar) six arrays of LINE_WS:
+// multiplier m, inverse pivot / alpha, sup * inverse pivot, and per lane
+// segment of `seg` slots the responses a_k (to the forward carry), b_k (to
+// the first value of the next segment) and, at the segment's first slot, the
+// product G of -m over the segment; all in the scaled variables of the
+// multi-window kernel.
+void build_tables2(const Plan& p, std::vector<double>& out) {
+    const int WS = adi::LINE_WS, R = p.seg;
+    constexpr double alpha = 0.26794919243112270647;
+    std::vector<double> one;
+    out.assign((size_t)p.nwin * 12 * WS, 0.0);
+    Plan p1 = p;
+    for (int g = 0; g < p.nwin; ++g) {
+        // factors of the window-restricted matrices (same as the single-window tables)
+        std::vector<double> t((size_t)6 * WS, 0.0);
+        const int w0 = window_start(p, g);
+        const int wl = std::min(w0 + WS, p.ns) - 1;
+        factor_rows(std::max(w0, 0), std::min(wl, p.n), 0, p.n, w0, coef_P, p.n, t.data(), t.data() + WS,
+                    t.data() + 2 * WS);
+        factor_rows(std::max(w0, 1), std::min(wl, p.n - 1), 1, p.n - 1, w0, coef_Pbar, p.n, t.data() + 3 * WS,
+                    t.data() + 4 * WS, t.data() + 5 * WS);
+        for (int kind = 0; kind < 2; ++kind) {
+            const double* m = t.data() + kind * 3 * WS;
+            const double* dinv = m + WS;
+            const double* e = m + 2 * WS;
+            double* o = out.data() + ((size_t)g * 12 + (size_t)kind * 6) * WS;
+            double *om = o, *od = o + WS, *oe = o + 2 * WS, *oa = o + 3 * WS, *ob = o + 4 * WS, *oG = o + 5 * WS;
+            for (int i = 0; i < WS; ++i) {
+                om[i] = m[i];
+                od[i] = dinv[i] / alpha;
+                oe[i] = e[i];
+            }
+            for (int s0 = 0; s0 < WS; s0 += R) {
+                std::vector<double> gk(R);
+                double gg = 1.0;
+                for (int k = 0; k < R; ++k) {
+                    gg *= -m[s0 + k];
+                    gk[k] = gg;
+                }
+                oG[s0] = gk[R - 1];
+                double an = 0.0, bn = 1.0;
+                for (int k = R - 1; k >= 0; --k) {
+                    const double ak = gk[k] * od[s0 + k] - (k == R - 1 ? 0.0 : oe[s0 + k] * an);
+                    const double bk = -oe[s0 + k] * bn;
+                    oa[s0 + k] = ak;
+                    ob[s0 + k] = bk;
+                    an = ak;
+                    bn = bk;
+                }
+            }
+        }
+    }
+    (void)p1;
+    (void)one;
+}
+
 void build_tables(const Plan& p, std::vector<double>& out) {
     const int WS = adi::LINE_WS;
     out.assign((size_t)p.nwin * 6 * WS, 0.0);
@@ -160,6 +221,7 @@ struct adi_problem {
     int64_t ldx = 0, ldy = 0;
     void *UAT = nullptr, *UC = nullptr, *VT[2] = {nullptr, nullptr}, *WSb[2] = {nullptr, nullptr};
     void *aK = nullptr, *aKT = nullptr, *aRvT = nullptr, *aRw = nullptr, *coefX = nullptr, *coefY = nullptr;
+    void *UATlo = nullptr, *UClo = nullptr, *VTlo[2] = {nullptr, nullptr}, *WSblo[2] = {nullptr, nullptr};
     int vcur = 0, wcur = 0;
     Plan px, py;
 };
@@ -167,7 +229,7 @@ struct adi_problem {
 namespace {
 
 struct Layout {
-    size_t off[12];
+    size_t off[18];
     size_t total;
 };
 
@@ -192,8 +254,16 @@ Layout layout(const adi_problem& pb) {
     put(8, pb.hasRv ? (size_t)(p.nx + 1) * ldy : 0);     // aRvT
     put(9, pb.hasRw ? (size_t)(p.ny + 1) * ldx : 0);     // aRw
     const bool cfd = p.method == ADI_CFD;
-    put(10, cfd ? (size_t)pb.px.nwin * 6 * adi::LINE_WS : 0);   // coefX
-    put(11, cfd ? (size_t)pb.py.nwin * 6 * adi::LINE_WS : 0);   // coefY
+    auto tabs = [&](const Plan& pl) { return (size_t)pl.nwin * (pl.ver == 1 ? 6 : 12) * adi::LINE_WS; };
+    put(10, cfd ? tabs(pb.px) : 0);   // coefX
+    put(11, cfd ? tabs(pb.py) : 0);   // coefY
+    const bool comp = p.dtype == ADI_FP32C;   // low words of the carried state
+    put(12, comp ? nix * ldy : 0);
+    put(13, comp ? niy * ldx : 0);
+    put(14, comp ? (size_t)(p.nx + 1) * ldy : 0);
+    put(15, comp ? (size_t)(p.nx + 1) * ldy : 0);
+    put(16, comp ? (size_t)(p.ny + 1) * ldx : 0);
+    put(17, comp ? (size_t)(p.ny + 1) * ldx : 0);
     L.total = cur;
     return L;
 }
@@ -203,8 +273,10 @@ int validate(const adi_params* p) {
     if (p->struct_size != sizeof(adi_params))
         return fail(ADI_EINVAL, "struct_size %u != %zu", p->struct_size, sizeof(adi_params));
     if (p->method != ADI_CFD && p->method != ADI_MFD) return fail(ADI_EINVAL, "unknown method %d", p->method);
-    if (p->dtype != ADI_FP32 && p->dtype != ADI_FP64) return fail(ADI_EINVAL, "unknown dtype %d", p->dtype);
-    if (p->order != 0) return fail(ADI_EINVAL, "order %d not supported (0 = x-implicit stage first)", p->order);
+    if (p->dtype != ADI_FP32 && p->dtype != ADI_FP64 && p->dtype != ADI_FP32C)
+        return fail(ADI_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->order != 0 && p->order != 1)
+        return fail(ADI_EINVAL, "order must be 0 (x-implicit stage first) or 1 (y-implicit first)");
     if (p->nx < 8 || p->ny < 8) return fail(ADI_EINVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
     if (p->nx > (1 << 20) || p->ny > (1 << 20)) return fail(ADI_EINVAL, "grid too large");
     if (p->sweeps < 2 || p->sweeps > 16 || (p->sweeps & 1))
@@ -232,7 +304,7 @@ int validate(const adi_params* p) {
 
 void derive(adi_problem* pb) {
     const auto& p = pb->p;
-    pb->esz = p.dtype == ADI_FP32 ? 4 : 8;
+    pb->esz = p.dtype == ADI_FP64 ? 8 : 4;
     pb->nix = p.method == ADI_CFD ? p.nx - 1 : p.nx;
     pb->niy = p.method == ADI_CFD ? p.ny - 1 : p.ny;
     pb->a = 0.5 * p.dt;
@@ -263,10 +335,19 @@ adi::LinePassArgs<T> base_args(const adi_problem& pb, const Plan& pl, const void
     return a;
 }
 
+// One buffer of the device state: value array plus, for the compensated
+// FP32 mode, its low-word array.
+template <typename T> struct Buf {
+    T* hi;
+    T* lo;
+    int64_t ld;
+};
+
 template <typename T>
 int run_impl(adi_problem* pb, int64_t nsteps) {
     const auto& p = pb->p;
     const int method = p.method;
+    const bool comp = p.dtype == ADI_FP32C;
     hipStream_t st = pb->st;
     T* U = (T*)pb->U;
     T* V = (T*)pb->V;
@@ -277,62 +358,96 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
         if (!has_src) return T(0);
         return (T)(pb->a * ricker(p, p.t0 + (double)m * p.dt) / h2);
     };
+    const int64_t ldx = pb->ldx, ldy = pb->ldy;
+    auto lo = [&](void* x) -> T* { return comp ? (T*)x : nullptr; };
+    const Buf<T> UAT{(T*)pb->UAT, lo(pb->UATlo), ldy}, UC{(T*)pb->UC, lo(pb->UClo), ldx};
+    const Buf<T> VT[2] = {{(T*)pb->VT[0], lo(pb->VTlo[0]), ldy}, {(T*)pb->VT[1], lo(pb->VTlo[1]), ldy}};
+    const Buf<T> WSb[2] = {{(T*)pb->WSb[0], lo(pb->WSblo[0]), ldx}, {(T*)pb->WSb[1], lo(pb->WSblo[1]), ldx}};
+    const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
 
-    // V (interior rows) -> VT
-    HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->VT[pb->vcur], pb->ldy, V + pb->ldV, 1, pb->ldV, p.nx + 1,
-                                       pb->niy, T(1), st), "transpose V");
-    // explicit part of stage 1 along columns: A and W* of step m
-    {
-        auto a = base_args<T>(*pb, pb->py, pb->coefY);
-        a.uin = U + pb->ldU + 1;  a.uin_ld = pb->ldU;
-        a.vin = W + 1;            a.vin_ld = pb->ldW;
-        a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = pb->ldx;
-        a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = pb->ldx;
-        a.vout = (T*)pb->WSb[pb->wcur]; a.vout_ld = pb->ldx;
-        a.uout = (T*)pb->UAT;           a.uout_ld = pb->ldy;
-        if (has_src) { a.src_q = p.src_i - 1; a.src_s = p.src_j; a.aF = aF(pb->step); }
-        HIP_TRY(adi::launch_line_pass<T>(a, method, adi::LINE_EXPLICIT, st), "explicit pass");
-    }
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int64_t m = pb->step + s;
-        const T f1 = aF(m + 1);
-        // row pass: stage-1 sweeps along x, then C and V^{m+1}
-        {
-            auto a = base_args<T>(*pb, pb->px, pb->coefX);
-            a.uin = (const T*)pb->UAT;          a.uin_ld = pb->ldy;
-            a.vin = (const T*)pb->VT[pb->vcur]; a.vin_ld = pb->ldy;
-            a.ak = pb->hasK ? (const T*)pb->aKT : nullptr;   a.ak_ld = pb->ldy;
-            a.ar = pb->hasRv ? (const T*)pb->aRvT : nullptr; a.ar_ld = pb->ldy;
-            a.vout = (T*)pb->VT[1 - pb->vcur]; a.vout_ld = pb->ldy;
-            a.uout = (T*)pb->UC;               a.uout_ld = pb->ldx;
-            if (has_src) { a.src_q = p.src_j - 1; a.src_s = p.src_i; a.aF = f1; }
-            HIP_TRY(adi::launch_line_pass<T>(a, method, adi::LINE_SWEEP, st), "row pass");
-            pb->vcur ^= 1;
+    // Pass along x (lines = interior rows, layouts UAT / VT) and along y
+    // (lines = interior columns, layouts UC / WSb).
+    auto pass = [&](int dir, const Buf<T>& uin, const Buf<T>& vin, const Buf<T>& vout, const Buf<T>& uout,
+                    int utrans, T f, int mode) -> int {
+        const Plan& pl = dir == 0 ? pb->px : pb->py;
+        auto a = base_args<T>(*pb, pl, dir == 0 ? pb->coefX : pb->coefY);
+        a.uin = uin.hi; a.uin_lo = uin.lo; a.uin_ld = uin.ld;
+        a.vin = vin.hi; a.vin_lo = vin.lo; a.vin_ld = vin.ld;
+        if (dir == 0) {
+            a.ak = pb->hasK ? (const T*)pb->aKT : nullptr;   a.ak_ld = ldy;
+            a.ar = pb->hasRv ? (const T*)pb->aRvT : nullptr; a.ar_ld = ldy;
+        } else {
+            a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = ldx;
+            a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = ldx;
         }
-        // column pass: stage-2 sweeps along y, then the next step's A and W*
-        {
-            const bool last = s == nsteps - 1;
-            auto a = base_args<T>(*pb, pb->py, pb->coefY);
-            a.uin = (const T*)pb->UC;            a.uin_ld = pb->ldx;
-            a.vin = (const T*)pb->WSb[pb->wcur]; a.vin_ld = pb->ldx;
-            a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = pb->ldx;
-            a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = pb->ldx;
-            if (last) {
-                a.vout = W + 1;             a.vout_ld = pb->ldW;
-                a.uout = U + pb->ldU + 1;   a.uout_ld = pb->ldU;
-                HIP_TRY(adi::launch_line_pass<T>(a, method, adi::LINE_FINAL, st), "column pass");
+        a.vout = vout.hi; a.vout_lo = vout.lo; a.vout_ld = vout.ld;
+        a.uout = uout.hi; a.uout_lo = uout.lo; a.uout_ld = uout.ld;
+        a.utrans = utrans;
+        if (has_src) {
+            a.src_q = dir == 0 ? p.src_j - 1 : p.src_i - 1;
+            a.src_s = dir == 0 ? p.src_i : p.src_j;
+            a.aF = f;
+        }
+        hipError_t e = pl.ver == 1 ? adi::launch_line_pass<T>(a, method, mode, st, comp)
+                                   : adi::launch_line_pass2<T>(a, method, mode, st, comp);
+        if (e != hipSuccess) return hip_fail(e, dir == 0 ? "row pass" : "column pass");
+        return ADI_OK;
+    };
+    auto nolo = [](const Buf<T>& b) { return Buf<T>{b.hi, nullptr, b.ld}; };
+    int rc;
+#define PASS(...) do { rc = pass(__VA_ARGS__); if (rc != ADI_OK) return rc; } while (0)
+
+    // V (interior rows) -> VT; low words start at zero
+    HIP_TRY(adi::launch_scaled_copy<T>(VT[pb->vcur].hi, ldy, V + pb->ldV, 1, pb->ldV, p.nx + 1, pb->niy, T(1), st),
+            "transpose V");
+    if (comp) HIP_TRY(adi::launch_fill_zero<T>(VT[pb->vcur].lo, ldy, p.nx + 1, pb->niy, st), "zero V low words");
+    if (p.order == 0) {
+        // explicit y part of stage 1: A and W* of step m
+        PASS(1, Uu, Wu, WSb[pb->wcur], UAT, 1, aF(pb->step), adi::LINE_EXPLICIT);
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int64_t m = pb->step + s;
+            const T f1 = aF(m + 1);
+            // rows: stage-1 sweeps along x, then C and V^{m+1}
+            PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], UC, 1, f1, adi::LINE_SWEEP);
+            pb->vcur ^= 1;
+            // columns: stage-2 sweeps along y, then the next step's A and W*
+            if (s == nsteps - 1) {
+                PASS(1, UC, WSb[pb->wcur], Wu, Uu, 0, T(0), adi::LINE_FINAL);
             } else {
-                a.vout = (T*)pb->WSb[1 - pb->wcur]; a.vout_ld = pb->ldx;
-                a.uout = (T*)pb->UAT;               a.uout_ld = pb->ldy;
-                if (has_src) { a.src_q = p.src_i - 1; a.src_s = p.src_j; a.aF = f1; }
-                HIP_TRY(adi::launch_line_pass<T>(a, method, adi::LINE_SWEEP, st), "column pass");
+                PASS(1, UC, WSb[pb->wcur], WSb[1 - pb->wcur], UAT, 1, f1, adi::LINE_SWEEP);
                 pb->wcur ^= 1;
             }
         }
+    } else {
+        // y-implicit stage first: the same passes in the other order
+        HIP_TRY(adi::launch_scaled_copy<T>(UAT.hi, ldy, U + pb->ldU + 1, 1, pb->ldU, pb->nix, pb->niy, T(1), st),
+                "transpose U");
+        HIP_TRY(adi::launch_scaled_copy<T>(WSb[pb->wcur].hi, ldx, W + 1, pb->ldW, 1, p.ny + 1, pb->nix, T(1), st),
+                "copy W");
+        if (comp) HIP_TRY(adi::launch_fill_zero<T>(WSb[pb->wcur].lo, ldx, p.ny + 1, pb->nix, st), "zero W low words");
+        // explicit x part of stage 1: A and V* of step m
+        PASS(0, nolo(UAT), nolo(VT[pb->vcur]), VT[1 - pb->vcur], UC, 1, aF(pb->step), adi::LINE_EXPLICIT);
+        pb->vcur ^= 1;
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int64_t m = pb->step + s;
+            const T f1 = aF(m + 1);
+            PASS(1, UC, WSb[pb->wcur], WSb[1 - pb->wcur], UAT, 1, f1, adi::LINE_SWEEP);
+            pb->wcur ^= 1;
+            if (s == nsteps - 1)
+                PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], Buf<T>{U + pb->ldU + 1, nullptr, pb->ldU}, 1, T(0),
+                     adi::LINE_FINAL);
+            else
+                PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], UC, 1, f1, adi::LINE_SWEEP);
+            pb->vcur ^= 1;
+        }
+        // W^{m+n} (interior columns) back to the caller
+        HIP_TRY(adi::launch_scaled_copy<T>(W + 1, pb->ldW, WSb[pb->wcur].hi, ldx, 1, p.ny + 1, pb->nix, T(1), st,
+                                           WSb[pb->wcur].lo), "copy W back");
     }
+#undef PASS
     // VT -> V (interior rows)
-    HIP_TRY(adi::launch_scaled_copy<T>(V + pb->ldV, pb->ldV, (const T*)pb->VT[pb->vcur], 1, pb->ldy, pb->niy,
-                                       p.nx + 1, T(1), st), "transpose V back");
+    HIP_TRY(adi::launch_scaled_copy<T>(V + pb->ldV, pb->ldV, VT[pb->vcur].hi, 1, ldy, pb->niy, p.nx + 1, T(1), st,
+                                       VT[pb->vcur].lo), "transpose V back");
     pb->step += nsteps;
     return ADI_OK;
 }
@@ -352,8 +467,8 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
         HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aRw, pb->ldx, Rw + 1, ldRw, 1, p.ny + 1, pb->nix, a, st), "aRw");
     if (p.method == ADI_CFD) {
         std::vector<double> tx, ty;
-        build_tables(pb->px, tx);
-        build_tables(pb->py, ty);
+        if (pb->px.ver == 1) build_tables(pb->px, tx); else build_tables2(pb->px, tx);
+        if (pb->py.ver == 1) build_tables(pb->py, ty); else build_tables2(pb->py, ty);
         std::vector<T> cx(tx.begin(), tx.end()), cy(ty.begin(), ty.end());
         HIP_TRY(hipMemcpyAsync(pb->coefX, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefX");
         HIP_TRY(hipMemcpyAsync(pb->coefY, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefY");
@@ -474,14 +589,15 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->own_ws = true;
     }
     pb->ws_bytes = L.total;
-    void** slots[12] = {&pb->UAT, &pb->UC, &pb->VT[0], &pb->VT[1], &pb->WSb[0], &pb->WSb[1],
-                        &pb->aK, &pb->aKT, &pb->aRvT, &pb->aRw, &pb->coefX, &pb->coefY};
-    for (int i = 0; i < 12; ++i) *slots[i] = pb->ws + L.off[i];
+    void** slots[18] = {&pb->UAT, &pb->UC, &pb->VT[0], &pb->VT[1], &pb->WSb[0], &pb->WSb[1],
+                        &pb->aK, &pb->aKT, &pb->aRvT, &pb->aRw, &pb->coefX, &pb->coefY,
+                        &pb->UATlo, &pb->UClo, &pb->VTlo[0], &pb->VTlo[1], &pb->WSblo[0], &pb->WSblo[1]};
+    for (int i = 0; i < 18; ++i) *slots[i] = pb->ws + L.off[i];
     pb->U = U; pb->V = V; pb->W = W;
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];
     pb->vcur = pb->wcur = 0;
     pb->step = 0;
-    int rc = p.dtype == ADI_FP32
+    int rc = p.dtype != ADI_FP64
                  ? bind_materials<float>(pb, (const float*)K, (const float*)Rv, (const float*)Rw, l[3], l[4], l[5])
                  : bind_materials<double>(pb, (const double*)K, (const double*)Rv, (const double*)Rw, l[3], l[4], l[5]);
     if (rc != ADI_OK) return rc;
@@ -496,7 +612,7 @@ int adi_run(adi_problem* pb, int64_t nsteps) {
     if (nsteps < 0) return fail(ADI_EINVAL, "nsteps < 0");
     if (nsteps == 0) return ADI_OK;
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
-    return pb->p.dtype == ADI_FP32 ? run_impl<float>(pb, nsteps) : run_impl<double>(pb, nsteps);
+    return pb->p.dtype != ADI_FP64 ? run_impl<float>(pb, nsteps) : run_impl<double>(pb, nsteps);
 }
 
 int adi_step(adi_problem* pb) { return adi_run(pb, 1); }

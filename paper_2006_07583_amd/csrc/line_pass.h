@@ -15,7 +15,7 @@ enum { LINE_WS = 512 };   // slots per window (both dtypes)
 //   uin[(s-1)*uin_ld + q], ak[(s-1)*ak_ld + q]        pressure-type inputs
 //   vin[s*vin_ld + q],     ar[s*ar_ld + q]            velocity-type inputs
 //   vout[s*vout_ld + q]                                velocity output
-//   uout[q*uout_ld + (s-1)]  (transposed), or uout[(s-1)*uout_ld + q] (final)
+//   uout[q*uout_ld + (s-1)]  (utrans = 1), or uout[(s-1)*uout_ld + q] (utrans = 0)
 template <typename T>
 struct LinePassArgs {
     const T* uin; int64_t uin_ld;
@@ -29,16 +29,33 @@ struct LinePassArgs {
     int nlines, n, ns, nlg, nwin, S, H, sweeps;
     int src_q, src_s;                // source (line, slot), -1 = none
     int deep;                        // single window: deep halo exchange
+    int gbase, gstride, gcount;      // multi-window kernel: windows g = gbase + i*gstride, i < gcount
+    int utrans;                      // 1: pressure output transposed (via LDS), 0: natural layout
+    // compensated FP32 state: low words of the inputs (NULL = zero) and of
+    // the outputs (NULL = store the rounded sum only)
+    const T* uin_lo; const T* vin_lo; T* vout_lo; T* uout_lo;
 };
 
 template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st);
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
 
+// dst[r*dld + c] = scale * (src[r*srs + c*scs] + src2[same])   (src2 may be NULL)
 template <typename T>
 hipError_t launch_scaled_copy(T* dst, int64_t dld, const T* src, int64_t srs, int64_t scs, int rows,
-                              int cols, T scale, hipStream_t st);
+                              int cols, T scale, hipStream_t st, const T* src2 = nullptr);
+
+// dst[r*dld + c] = 0 for r < rows, c < cols
+template <typename T>
+hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t st);
 
 int line_lanes(int dtype);
 int line_halo(int dtype, int method, int sweeps);
+
+// Multi-window variant (line_pass2.hip): lines per workgroup and slots per
+// lane segment; compact factor tables hold 12 arrays of LINE_WS per window.
+template <typename T>
+hipError_t launch_line_pass2(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
+int line2_lanes(int dtype);
+int line2_seg(int dtype);
 
 }  // namespace adi

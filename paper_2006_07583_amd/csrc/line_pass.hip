@@ -43,6 +43,8 @@
 #include <stdint.h>
 
 #include "line_pass.h"
+#include "pass_common.h"
+#include <type_traits>
 
 namespace adi {
 
@@ -323,7 +325,7 @@ template <typename T, int METHOD> struct Pass {
     }
 };
 
-template <typename T, int METHOD, int MODE>
+template <typename T, int METHOD, int MODE, bool COMP>
 __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<T> a) {
     using P = Pass<T, METHOD>;
     constexpr int LW = K<T>::LW, R = K<T>::R, SPW = K<T>::SPW, WS = K<T>::WS;
@@ -366,17 +368,32 @@ __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<
     }
     if (METHOD == LINE_CFD) __syncthreads();   // tables visible
 
-    if (MODE == LINE_EXPLICIT) {
+    if (MODE == LINE_EXPLICIT || COMP) {
         p.template deriv<0>(A, Tt);                 // G(A)
-#pragma unroll
-        for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // B - aR G(A)
         p.template deriv<1>(B, U);                  // D(B)
+        if (MODE == LINE_EXPLICIT) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);     // A - aK D(B)
-    } else {
-        p.template deriv<1>(B, U);
+            for (int k = 0; k < R; ++k) {
+                // W* = B - aR G(A), A_out = A - aK D(B)   (increments when compensated)
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
+            }
+        } else {
+            // compensated: iterate on the increments, A' = -aK D(B), B' = -aR G(A)
 #pragma unroll
-        for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            for (int k = 0; k < R; ++k) {
+                A[k] = -KK[k] * U[k];
+                B[k] = -RR[k] * Tt[k];
+                U[k] = A[k];
+            }
+        }
+    }
+    if (MODE != LINE_EXPLICIT) {
+        if (!COMP) {
+            p.template deriv<1>(B, U);
+#pragma unroll
+            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+        }
         for (int it = 1; it < a.sweeps; ++it) {
             p.template deriv<0>(U, Tt);
 #pragma unroll
@@ -389,60 +406,22 @@ __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<
 #pragma unroll
         for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // v_K
         if (MODE == LINE_SWEEP) {
+            if (COMP) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] += A[k];
+            }
             p.template deriv<1>(Tt, A);                                   // D(v_K)
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const T vk = Tt[k];
-                Tt[k] = vk + (vk - B[k]);                                  // 2 v_K - B
+                Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);                 // 2 v_K - B
                 U[k] = fma(-KK[k], A[k], U[k]);                            // u_K - aK D(v_K)
             }
         }
     }
 
-    // ---- velocity output (central slots, native layout) ----
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int s = s0 + k;
-        if (qok && s >= c0 && s < c1 && s <= vhi) a.vout[(int64_t)s * a.vout_ld + q] = Tt[k];
-    }
-
-    // ---- pressure output ----
-    if (MODE != LINE_FINAL) {
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (q == a.src_q && s0 + k == a.src_s) U[k] += a.aF;
-    }
-    if (MODE == LINE_FINAL) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int s = s0 + k;
-            if (qok && s >= c0 && s < c1 && s >= ulo && s <= uhi)
-                a.uout[(int64_t)(s - 1) * a.uout_ld + q] = U[k];
-        }
-    } else {
-        // transposed store through an LDS tile: line-major rows of the
-        // central slots, written with consecutive threads on consecutive slots
-        __syncthreads();
-        T* tile = smem;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int s = s0 + k;
-            if (s >= c0 && s < c1) tile[lq * P::TILEP + (s - c0)] = U[k];
-        }
-        __syncthreads();
-        const int nc = c1 - c0;
-        const int lo = max(c0, ulo), hi = min(c1 - 1, uhi);
-        const int nv = hi - lo + 1;
-        if (nv > 0) {
-            for (int idx = tid; idx < LW * nv; idx += K<T>::NT) {
-                const int l = idx / nv, j = idx - l * nv;
-                const int qq = lg * LW + l;
-                if (qq < a.nlines)
-                    a.uout[(int64_t)qq * a.uout_ld + (lo + j - 1)] = tile[l * P::TILEP + (lo - c0) + j];
-            }
-        }
-        (void)nc;
-    }
+    pass_outputs<T, R, LW, K<T>::NT, P::TILEP, COMP>(a, smem, Tt, U, s0, q, qok, lq, lg, c0, c1, uhi, vhi,
+                                                    tid, MODE != LINE_FINAL);
 }
 
 // ------------------------------------------------------------------------
@@ -454,7 +433,8 @@ __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<
 template <typename T>
 __global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, int64_t dld,
                                                           const T* __restrict__ src, int64_t srs,
-                                                          int64_t scs, int rows, int cols, T scale) {
+                                                          int64_t scs, int rows, int cols, T scale,
+                                                          const T* __restrict__ src2) {
     __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -463,7 +443,8 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, i
 #pragma unroll
         for (int i = 0; i < 32; i += 8) {
             const int r = r0 + tx, c = c0 + ty + i;
-            tile[ty + i][tx] = (r < rows && c < cols) ? src[(int64_t)r * srs + (int64_t)c * scs] : T(0);
+            const int64_t o = (int64_t)r * srs + (int64_t)c * scs;
+            tile[ty + i][tx] = (r < rows && c < cols) ? (src2 ? src[o] + src2[o] : src[o]) : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -475,17 +456,20 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, i
 #pragma unroll
         for (int i = 0; i < 32; i += 8) {
             const int r = r0 + ty + i, c = c0 + tx;
-            if (r < rows && c < cols) dst[(int64_t)r * dld + c] = scale * src[(int64_t)r * srs + (int64_t)c * scs];
+            if (r < rows && c < cols) {
+                const int64_t o = (int64_t)r * srs + (int64_t)c * scs;
+                dst[(int64_t)r * dld + c] = scale * (src2 ? src[o] + src2[o] : src[o]);
+            }
         }
     }
 }
 
-template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
+template <typename T, bool COMP>
+hipError_t launch_lp(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
     dim3 grid((unsigned)(a.nlg * a.nwin)), block(K<T>::NT);
 #define LP_CASE(M, MD)                                                                 \
     if (method == M && mode == MD) {                                                   \
-        hipLaunchKernelGGL((line_pass_kernel<T, M, MD>), grid, block, 0, st, a);       \
+        hipLaunchKernelGGL((line_pass_kernel<T, M, MD, COMP>), grid, block, 0, st, a); \
         return hipGetLastError();                                                      \
     }
     LP_CASE(LINE_CFD, LINE_SWEEP)
@@ -499,11 +483,34 @@ hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipS
 }
 
 template <typename T>
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp) {
+    if (!comp) return launch_lp<T, false>(a, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_lp<T, true>(a, method, mode, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t launch_scaled_copy(T* dst, int64_t dld, const T* src, int64_t srs, int64_t scs, int rows,
-                              int cols, T scale, hipStream_t st) {
+                              int cols, T scale, hipStream_t st, const T* src2) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), block(256);
-    hipLaunchKernelGGL((scaled_copy_kernel<T>), grid, block, 0, st, dst, dld, src, srs, scs, rows, cols, scale);
+    hipLaunchKernelGGL((scaled_copy_kernel<T>), grid, block, 0, st, dst, dld, src, srs, scs, rows, cols, scale,
+                       src2);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fill_zero_kernel(T* __restrict__ dst, int64_t dld, int rows, int cols) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c < cols && r < rows) dst[(int64_t)r * dld + c] = T(0);
+}
+
+template <typename T>
+hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows), block(256);
+    hipLaunchKernelGGL((fill_zero_kernel<T>), grid, block, 0, st, dst, dld, rows, cols);
     return hipGetLastError();
 }
 
@@ -518,9 +525,13 @@ int line_halo(int dtype, int method, int sweeps) {
     return dtype == 0 ? 20 + 2 * sweeps : 40 + 3 * sweeps;
 }
 
-template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_scaled_copy<float>(float*, int64_t, const float*, int64_t, int64_t, int, int, float, hipStream_t);
-template hipError_t launch_scaled_copy<double>(double*, int64_t, const double*, int64_t, int64_t, int, int, double, hipStream_t);
+template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool);
+template hipError_t launch_scaled_copy<float>(float*, int64_t, const float*, int64_t, int64_t, int, int, float,
+                                             hipStream_t, const float*);
+template hipError_t launch_scaled_copy<double>(double*, int64_t, const double*, int64_t, int64_t, int, int, double,
+                                              hipStream_t, const double*);
+template hipError_t launch_fill_zero<float>(float*, int64_t, int, int, hipStream_t);
+template hipError_t launch_fill_zero<double>(double*, int64_t, int, int, hipStream_t);
 
 }  // namespace adi

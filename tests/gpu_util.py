@@ -13,18 +13,18 @@ def log(msg):
 
 
 def run_gpu(method, dtype, fields, *, h, dt, c_max, nsteps, sweeps=6, K=None, Rv=None, Rw=None,
-            src=None, t0=0.0, kappa0=1.0, rinv0=1.0, chunks=None):
+            src=None, t0=0.0, kappa0=1.0, rinv0=1.0, chunks=None, order=0):
     """Copy (U, V, W, materials) to the GPU, run nsteps (optionally split into
     the given chunk sizes), return float64 numpy copies of U, V, W."""
     import torch
-    tdt = torch.float32 if dtype == adi.FP32 else torch.float64
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
     dev = torch.device("cuda:0")
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
     U, V, W = t(fields["U"]), t(fields["V"]), t(fields["W"])
     ny = U.shape[0] - (1 if method == adi.CFD else 2)
     nx = U.shape[1] - (1 if method == adi.CFD else 2)
     p = adi.make_params(method, dtype, nx, ny, h, dt, c_max, sweeps=sweeps, src=src, t0=t0,
-                        kappa0=kappa0, rinv0=rinv0)
+                        kappa0=kappa0, rinv0=rinv0, order=order)
     pb = adi.Problem(p).bind(U, V, W, t(K), t(Rv), t(Rw))
     for c in (chunks or [nsteps]):
         pb.run(c)

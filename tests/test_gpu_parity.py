@@ -112,3 +112,77 @@ def test_config1_cfd_standing_wave_fp64():
         assert max_rel(g, r) <= TOL64
     err = np.abs(got[0] - f["U"] * math.cos(math.sqrt(2) * math.pi)).max()
     assert err == pytest.approx(4.402e-4, rel=1e-2)
+
+
+def _order_run(method, dtype, f, med, src, h, dt, cmax, nsteps, order):
+    from tests.gpu_util import run_gpu as rg
+    return rg(method, dtype, f, h=h, dt=dt, c_max=cmax, nsteps=nsteps, K=med["K"], Rv=med["Rv"],
+              Rw=med["Rw"], src=src, order=order)
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
+@pytest.mark.parametrize("nx,ny", [(40, 29), (700, 530)])
+def test_role_swap_transposed_problem_bitwise(method, dtype, nx, ny):
+    """The row and column passes swap roles when the problem is transposed and
+    the y-implicit stage goes first: the result is the exact transpose."""
+    h, f, med, cmax, src = case(method, nx, ny, 17)
+    dt = 0.7 * h / cmax
+    log(f"case role-swap method={method} dtype={dtype} nx={nx} ny={ny}")
+    a = _order_run(method, dtype, f, med, src, h, dt, cmax, 4, 0)
+    fT = {"U": f["U"].T, "V": f["W"].T, "W": f["V"].T}
+    medT = {"K": med["K"].T, "Rv": med["Rw"].T, "Rw": med["Rv"].T}
+    srcT = dict(src, i=src["j"], j=src["i"])
+    b = _order_run(method, dtype, fT, medT, srcT, h, dt, cmax, 4, 1)
+    assert np.array_equal(b[0].T, a[0])
+    assert np.array_equal(b[2].T, a[1])
+    assert np.array_equal(b[1].T, a[2])
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+def test_order1_matches_oracle(method):
+    h, f, med, cmax, src = case(method, 600, 90, 23)
+    dt = 0.7 * h / cmax
+    log(f"case order1 method={method}")
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=3, sweeps=6,
+                K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src, order=1)
+    got = _order_run(method, adi.FP64, f, med, src, h, dt, cmax, 3, 1)
+    for g, r in zip(written_parts(method, *got), written_parts(method, *ref)):
+        assert max_rel(g, r) <= TOL64
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (33, 20), (1300, 600)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_compensated_fp32(method, nx, ny, order):
+    h, f, med, cmax, src = case(method, nx, ny, 5 * nx + ny + order)
+    dt = 0.6 * h / cmax
+    log(f"case fp32c method={method} nx={nx} ny={ny} order={order}")
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=4, sweeps=6,
+                K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src, order=order)
+    got = run_gpu(method, adi.FP32C, f, h=h, dt=dt, c_max=cmax, nsteps=4, K=med["K"], Rv=med["Rv"],
+                  Rw=med["Rw"], src=src, order=order)
+    errs = [rel_l2(g, r) for g, r in zip(written_parts(method, *got), written_parts(method, *ref))]
+    log(f"  errors {errs}")
+    assert max(errs) <= TOL32, errs
+
+
+@pytest.mark.parametrize("method,nsteps", [(adi.CFD, 100), (adi.MFD, 600)])
+def test_compensated_error_not_above_plain_fp32(method, nsteps):
+    """Smooth standing mode: the compensated FP32 state drifts from the FP64
+    oracle no more than plain FP32 does.  The compact scheme runs a shorter
+    horizon: its growing boundary modes amplify any rounding difference
+    (the oracle's own included) within a few hundred steps."""
+    N = 600
+    h = 1.0 / N
+    f = inputs.standing_mode(method, N, N, h, 3, 2)
+    dt = 0.5 * h
+    log(f"case fp32c-vs-fp32 method={method} steps={nsteps}")
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, sweeps=6)
+    e = {}
+    for dt_ in (adi.FP32, adi.FP32C):
+        got = run_gpu(method, dt_, f, h=h, dt=dt, c_max=1.0, nsteps=nsteps)
+        e[dt_] = rel_l2(got[0][1:-1, 1:-1], ref[0][1:-1, 1:-1])
+    log(f"  fp32 {e[adi.FP32]:.3e}  fp32c {e[adi.FP32C]:.3e}")
+    assert e[adi.FP32C] <= e[adi.FP32] * 1.05
+    assert e[adi.FP32C] <= TOL32

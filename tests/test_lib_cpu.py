@@ -59,7 +59,7 @@ def test_workspace_size_grows_with_materials():
     (lambda p: setattr(p, "dt", 1.2 / 64), "cfl"),
     (lambda p: setattr(p, "method", 5), "method"),
     (lambda p: setattr(p, "dtype", 9), "dtype"),
-    (lambda p: setattr(p, "order", 1), "order"),
+    (lambda p: setattr(p, "order", 2), "order"),
     (lambda p: setattr(p, "h", 0.0), "h must"),
     (lambda p: setattr(p, "c_max", 0.0), "c_max"),
     (lambda p: setattr(p, "struct_size", 8), "struct_size"),
