@@ -34,6 +34,11 @@ def parse():
     ap.add_argument("--dtypes", default="fp32,fp64")
     ap.add_argument("--cpu-baseline-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=256,
+                    help="steps of the batched 256-problem workload (0 = skip it)")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +86,54 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps):
     return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite}
 
 
+def batch_case(steps, count):
+    """The batched workload: `count` problems (Nx, Ny log-uniform on
+    [64, 1024], CFD / MFD uniform, layered media, Ricker source, FP32,
+    6 sweeps, CFL 0.8), advanced `steps` steps together (grouped launches,
+    graph replay) and, for comparison, one problem at a time with adi_run."""
+    import torch
+    from paper_2006_07583_amd import adi, inputs
+    mix = inputs.batch_mix(0, count=count)
+    st = torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    probs, cells = [], 0
+    for m in mix:
+        c = inputs.layered_speed(m["method"], m["nx"], m["ny"], 5.0, m["medium_seed"])
+        sh = inputs.shapes(m["method"], m["nx"], m["ny"])
+        U, V, W = (torch.zeros(sh[k], dtype=torch.float32, device=dev) for k in ("U", "V", "W"))
+        K = torch.from_numpy(c * c).to(dev, torch.float32)
+        cmax = float(c.max())
+        p = adi.make_params(m["method"], adi.FP32, m["nx"], m["ny"], 5.0, 0.8 * 5.0 / cmax, cmax,
+                            src=inputs.ricker_source(m["src_i"], m["src_j"]))
+        probs.append(adi.Problem(p, st).bind(U, V, W, K))
+        cells += m["nx"] * m["ny"]
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    b = adi.Batch(probs, st, graph=True)
+    b.run(2)
+    t_batch = timed(lambda: b.run(steps))
+    launches = b.launches
+    b.close()
+    for pb in probs:
+        pb.run(1)
+    t_alone = timed(lambda: [pb.run(steps) for pb in probs])
+    for pb in probs:
+        pb.close()
+    return {"problems": count, "cells": cells, "steps": steps,
+            "batched_pt_steps_s": cells * steps / t_batch, "alone_pt_steps_s": cells * steps / t_alone,
+            "speedup": t_alone / t_batch, "batched_s": t_batch, "alone_s": t_alone,
+            "grouped_launches": launches}
+
+
 def cpu_baseline(n, steps, methods):
     import oracle as O
     from paper_2006_07583_amd import inputs
@@ -110,6 +163,14 @@ def main():
     methods = [mmap[m] for m in args.methods.split(",")]
     dtypes = [dmap[d] for d in args.dtypes.split(",")]
     n, K, W = args.n, args.steps, args.warmup
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy calibration: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
+        del src, dst
     res = {}
     for d in dtypes:
         for m in methods:
@@ -150,6 +211,12 @@ def main():
                                f"{'fp32' if head == adi.FP32 else 'fp64'}"},
         "variants": variants,
     }
+    if args.batch_steps > 0:
+        bc = batch_case(args.batch_steps, args.batch_count)
+        print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "
+              f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched, {bc['alone_pt_steps_s']:.4g} one at a time "
+              f"({bc['speedup']:.2f}x), {bc['grouped_launches']} grouped launches", file=sys.stderr, flush=True)
+        out["batched"] = bc
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_steps, methods)
     print(json.dumps(out), flush=True)

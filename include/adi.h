@@ -143,6 +143,44 @@ int adi_set_step(adi_problem* pb, int64_t m);
 /* Free the problem and any workspace the library allocated. */
 int adi_destroy(adi_problem* pb);
 
+/* ---- Batched runs ----------------------------------------------------
+ * Many independent problems advanced together.  The paper observes
+ * (Sections 3.2 and 5) that overlapping many small kernels with streams did
+ * not pay because launch costs exceeded the work per launch; here each
+ * half-step of all problems is one launch per kernel variant (tile shape x
+ * method x mode, at most a few), each workgroup picking its problem and
+ * line group from a table.  Results are identical, bit for bit, to running
+ * every problem alone with adi_run. */
+typedef struct adi_batch adi_batch;
+
+/* Replay the launches of the steady-state steps from a captured hipGraph. */
+#define ADI_BATCH_GRAPH 1
+
+/* Group count bound problems (any methods, dtypes, sizes, orders) of the
+ * current device.  The batch keeps the pointers, not the problems: they must
+ * stay alive and bound while the batch is used.  Work is queued on
+ * hip_stream (NULL = null stream; ADI_BATCH_GRAPH needs a created stream),
+ * ordered after each problem's own stream and before later work on it.
+ * flags: 0 or ADI_BATCH_GRAPH. */
+int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, int flags,
+                     adi_batch** out);
+
+/* Queue nsteps steps of every problem of the batch (each problem ends at
+ * its own time level m + nsteps, as after adi_run(problem, nsteps)).  The
+ * call allocates a descriptor buffer on first use and blocks until the
+ * previous run of the batch has finished. */
+int adi_batch_run(adi_batch* b, int64_t nsteps);
+
+/* Wait for the batch's queued work. */
+int adi_batch_sync(adi_batch* b);
+
+/* Number of grouped line-pass launches of the last adi_batch_run (graph
+ * replays included; the per-problem set-up and explicit passes excluded). */
+int adi_batch_launches(const adi_batch* b, int64_t* n);
+
+/* Free the batch (not its problems). */
+int adi_batch_destroy(adi_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

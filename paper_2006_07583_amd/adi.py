@@ -20,7 +20,11 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync",
-           "adi_get_step", "adi_set_step", "adi_destroy")
+           "adi_get_step", "adi_set_step", "adi_destroy",
+           "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
+           "adi_batch_destroy")
+
+BATCH_GRAPH = 1
 
 
 class AdiParams(ctypes.Structure):
@@ -67,6 +71,11 @@ def lib():
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
         L.adi_set_step.argtypes = [vp, i64]
         L.adi_destroy.argtypes = [vp]
+        L.adi_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_int, ctypes.POINTER(vp)]
+        L.adi_batch_run.argtypes = [vp, i64]
+        L.adi_batch_sync.argtypes = [vp]
+        L.adi_batch_launches.argtypes = [vp, ctypes.POINTER(i64)]
+        L.adi_batch_destroy.argtypes = [vp]
         for name in EXPORTS[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -158,6 +167,45 @@ class Problem:
             lib().adi_destroy(self._h)
             self._h = ctypes.c_void_p()
             self._keep = ()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several bound :class:`Problem` objects advanced together
+    (``adi_batch_*``): one grouped launch per kernel variant and half-step."""
+
+    def __init__(self, problems, stream=None, graph=False):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        self._problems = list(problems)
+        arr = (ctypes.c_void_p * len(self._problems))(*[p._h.value for p in self._problems])
+        self._h = ctypes.c_void_p()
+        _check(lib().adi_batch_create(arr, len(self._problems), ctypes.c_void_p(stream.cuda_stream),
+                                      BATCH_GRAPH if graph else 0, ctypes.byref(self._h)))
+
+    def run(self, nsteps: int):
+        _check(lib().adi_batch_run(self._h, int(nsteps)))
+
+    def sync(self):
+        _check(lib().adi_batch_sync(self._h))
+
+    @property
+    def launches(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().adi_batch_launches(self._h, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if self._h:
+            lib().adi_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

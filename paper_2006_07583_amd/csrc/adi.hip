@@ -24,10 +24,13 @@
 
 #include "../../include/adi.h"
 #include "line_pass.h"
+#include "problem.h"
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+namespace adi {
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -43,20 +46,17 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(ADI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                       \
-    do {                                          \
-        hipError_t e_ = (expr);                   \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+}  // namespace adi
+
+namespace {
+
+using adi::fail;
+using adi::hip_fail;
+using adi::Plan;
+
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kDelta = 3.7320508075688772935;   // 2 + sqrt 3, interior pivot of (1, 4, 1)
-
-struct Plan {
-    int n = 0, ns = 0, nlines = 0, nlg = 0, nwin = 0, S = 0, H = 0, deep = 0;
-    int ver = 1;   // 1: single-window kernel (line_pass.hip), 2: multi-window (line_pass2.hip)
-    int seg = 0;   // slots per lane segment of the multi-window kernel
-};
 
 int64_t pad_to(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -67,7 +67,11 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
     p.nlines = nlines;
     p.H = adi::line_halo(dtype, method, sweeps);
     if (p.ns <= adi::LINE_WS) {
+        // single window: the smallest tile shape whose window holds the line
         p.ver = 1;
+        p.cfg = 0;
+        for (int c = adi::LINE_NCFG - 1; c >= 0; --c)
+            if (p.ns <= adi::line_ws(c)) { p.cfg = c; break; }
         p.nwin = 1;
         p.S = p.ns;
         p.deep = 1;
@@ -78,7 +82,7 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.nwin = (p.ns + p.S - 1) / p.S;
         p.deep = 0;
     }
-    const int lw = p.ver == 1 ? adi::line_lanes(dtype) : adi::line2_lanes(dtype);
+    const int lw = p.ver == 1 ? adi::line_lanes(dtype, p.cfg) : adi::line2_lanes(dtype);
     p.nlg = (nlines + lw - 1) / lw;
     return p;
 }
@@ -126,64 +130,10 @@ double coef_Pbar(int r, int which, int n) {
     return which == 1 ? 4.0 : 1.0;
 }
 
-// Multi-window tables: per window and kind (P, Pbar) six arrays of LINE_WS:
-// multiplier m, inverse pivot / alpha, sup * inverse pivot, and per lane
-// segment of `seg` slots the responses a_k (to the forward carry), b_k (to
-// the first value of the next segment) and, at the segment's first slot, the
-// product G of -m over the segment; all in the scaled variables of the
-// multi-window kernel.
-void build_tables2(const Plan& p, std::vector<double>& out) {
-    const int WS = adi::LINE_WS, R = p.seg;
-    constexpr double alpha = 0.26794919243112270647;
-    std::vector<double> one;
-    out.assign((size_t)p.nwin * 12 * WS, 0.0);
-    Plan p1 = p;
-    for (int g = 0; g < p.nwin; ++g) {
-        // factors of the window-restricted matrices (same as the single-window tables)
-        std::vector<double> t((size_t)6 * WS, 0.0);
-        const int w0 = window_start(p, g);
-        const int wl = std::min(w0 + WS, p.ns) - 1;
-        factor_rows(std::max(w0, 0), std::min(wl, p.n), 0, p.n, w0, coef_P, p.n, t.data(), t.data() + WS,
-                    t.data() + 2 * WS);
-        factor_rows(std::max(w0, 1), std::min(wl, p.n - 1), 1, p.n - 1, w0, coef_Pbar, p.n, t.data() + 3 * WS,
-                    t.data() + 4 * WS, t.data() + 5 * WS);
-        for (int kind = 0; kind < 2; ++kind) {
-            const double* m = t.data() + kind * 3 * WS;
-            const double* dinv = m + WS;
-            const double* e = m + 2 * WS;
-            double* o = out.data() + ((size_t)g * 12 + (size_t)kind * 6) * WS;
-            double *om = o, *od = o + WS, *oe = o + 2 * WS, *oa = o + 3 * WS, *ob = o + 4 * WS, *oG = o + 5 * WS;
-            for (int i = 0; i < WS; ++i) {
-                om[i] = m[i];
-                od[i] = dinv[i] / alpha;
-                oe[i] = e[i];
-            }
-            for (int s0 = 0; s0 < WS; s0 += R) {
-                std::vector<double> gk(R);
-                double gg = 1.0;
-                for (int k = 0; k < R; ++k) {
-                    gg *= -m[s0 + k];
-                    gk[k] = gg;
-                }
-                oG[s0] = gk[R - 1];
-                double an = 0.0, bn = 1.0;
-                for (int k = R - 1; k >= 0; --k) {
-                    const double ak = gk[k] * od[s0 + k] - (k == R - 1 ? 0.0 : oe[s0 + k] * an);
-                    const double bk = -oe[s0 + k] * bn;
-                    oa[s0 + k] = ak;
-                    ob[s0 + k] = bk;
-                    an = ak;
-                    bn = bk;
-                }
-            }
-        }
-    }
-    (void)p1;
-    (void)one;
-}
-
+// Factor tables of the single-window kernel: [6][WS], WS = window of the
+// plan's tile shape.
 void build_tables(const Plan& p, std::vector<double>& out) {
-    const int WS = adi::LINE_WS;
+    const int WS = adi::line_ws(p.cfg);
     out.assign((size_t)p.nwin * 6 * WS, 0.0);
     for (int g = 0; g < p.nwin; ++g) {
         double* t = out.data() + (size_t)g * 6 * WS;
@@ -202,29 +152,6 @@ double ricker(const adi_params& p, double t) {
 }
 
 }  // namespace
-
-struct adi_problem {
-    adi_params p{};
-    hipStream_t st = nullptr;
-    int dev = 0;
-    int nix = 0, niy = 0;
-    double a = 0.0;
-    int64_t step = 0;
-    bool bound = false;
-    void *U = nullptr, *V = nullptr, *W = nullptr;
-    int64_t ldU = 0, ldV = 0, ldW = 0;
-    bool hasK = false, hasRv = false, hasRw = false;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
-    bool own_ws = false;
-    size_t esz = 4;
-    int64_t ldx = 0, ldy = 0;
-    void *UAT = nullptr, *UC = nullptr, *VT[2] = {nullptr, nullptr}, *WSb[2] = {nullptr, nullptr};
-    void *aK = nullptr, *aKT = nullptr, *aRvT = nullptr, *aRw = nullptr, *coefX = nullptr, *coefY = nullptr;
-    void *UATlo = nullptr, *UClo = nullptr, *VTlo[2] = {nullptr, nullptr}, *WSblo[2] = {nullptr, nullptr};
-    int vcur = 0, wcur = 0;
-    Plan px, py;
-};
 
 namespace {
 
@@ -254,7 +181,7 @@ Layout layout(const adi_problem& pb) {
     put(8, pb.hasRv ? (size_t)(p.nx + 1) * ldy : 0);     // aRvT
     put(9, pb.hasRw ? (size_t)(p.ny + 1) * ldx : 0);     // aRw
     const bool cfd = p.method == ADI_CFD;
-    auto tabs = [&](const Plan& pl) { return (size_t)pl.nwin * (pl.ver == 1 ? 6 : 12) * adi::LINE_WS; };
+    auto tabs = [&](const Plan& pl) { return pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : (size_t)0; };
     put(10, cfd ? tabs(pb.px) : 0);   // coefX
     put(11, cfd ? tabs(pb.py) : 0);   // coefY
     const bool comp = p.dtype == ADI_FP32C;   // low words of the carried state
@@ -332,6 +259,9 @@ adi::LinePassArgs<T> base_args(const adi_problem& pb, const Plan& pl, const void
     a.deep = pl.deep;
     a.coef = (const T*)coef;
     a.src_q = a.src_s = -1;
+    a.gbase = 0;
+    a.gstride = 1;
+    a.gcount = pl.nwin;
     return a;
 }
 
@@ -343,113 +273,185 @@ template <typename T> struct Buf {
     int64_t ld;
 };
 
+// The state buffers of a problem, in the dtype of its arrays.
+template <typename T> struct State {
+    Buf<T> UAT, UC, VT[2], WSb[2], Uu, Wu;
+    explicit State(const adi_problem* pb) {
+        const bool comp = pb->p.dtype == ADI_FP32C;
+        auto lo = [&](void* x) -> T* { return comp ? (T*)x : nullptr; };
+        UAT = {(T*)pb->UAT, lo(pb->UATlo), pb->ldy};
+        UC = {(T*)pb->UC, lo(pb->UClo), pb->ldx};
+        for (int i = 0; i < 2; ++i) {
+            VT[i] = {(T*)pb->VT[i], lo(pb->VTlo[i]), pb->ldy};
+            WSb[i] = {(T*)pb->WSb[i], lo(pb->WSblo[i]), pb->ldx};
+        }
+        Uu = {(T*)pb->U + pb->ldU + 1, nullptr, pb->ldU};   // interior pressure, natural layout
+        Wu = {(T*)pb->W + 1, nullptr, pb->ldW};             // W, interior columns
+    }
+};
+
+template <typename T> Buf<T> nolo(const Buf<T>& b) { return Buf<T>{b.hi, nullptr, b.ld}; }
+
+// Pass along x (dir 0: lines = interior rows, layouts UAT / VT) or along y
+// (dir 1: lines = interior columns, layouts UC / WSb).
 template <typename T>
-int run_impl(adi_problem* pb, int64_t nsteps) {
+adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, const Buf<T>& vin,
+                           const Buf<T>& vout, const Buf<T>& uout, int utrans, T f, const T* aFtab, int mode) {
     const auto& p = pb->p;
-    const int method = p.method;
+    const Plan& pl = dir == 0 ? pb->px : pb->py;
+    adi::PassDesc<T> d{};
+    auto& a = d.a;
+    a = base_args<T>(*pb, pl, dir == 0 ? pb->coefX : pb->coefY);
+    a.uin = uin.hi; a.uin_lo = uin.lo; a.uin_ld = uin.ld;
+    a.vin = vin.hi; a.vin_lo = vin.lo; a.vin_ld = vin.ld;
+    if (dir == 0) {
+        a.ak = pb->hasK ? (const T*)pb->aKT : nullptr;   a.ak_ld = pb->ldy;
+        a.ar = pb->hasRv ? (const T*)pb->aRvT : nullptr; a.ar_ld = pb->ldy;
+    } else {
+        a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = pb->ldx;
+        a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = pb->ldx;
+    }
+    a.vout = vout.hi; a.vout_lo = vout.lo; a.vout_ld = vout.ld;
+    a.uout = uout.hi; a.uout_lo = uout.lo; a.uout_ld = uout.ld;
+    a.utrans = utrans;
+    if (p.src_i >= 0) {
+        a.src_q = dir == 0 ? p.src_j - 1 : p.src_i - 1;
+        a.src_s = dir == 0 ? p.src_i : p.src_j;
+        a.aF = f;
+        a.aFtab = mode == adi::LINE_SWEEP ? aFtab : nullptr;
+    }
+    d.ver = pl.ver;
+    d.cfg = pl.ver == 1 ? pl.cfg : 0;
+    d.method = p.method;
+    d.mode = mode;
+    d.comp = p.dtype == ADI_FP32C;
+    return d;
+}
+
+}  // namespace
+
+namespace adi {
+
+double source_term(const adi_problem& pb, int64_t m) {
+    const auto& p = pb.p;
+    if (p.src_i < 0) return 0.0;
+    return pb.a * ricker(p, p.t0 + (double)m * p.dt) / (p.h * p.h);
+}
+
+template <typename T>
+hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st) {
+    return d.ver == 1 ? launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg)
+                      : launch_line_pass2<T>(d.a, d.method, d.mode, st, d.comp);
+}
+
+template <typename T>
+int run_begin(adi_problem* pb, hipStream_t st) {
+    const auto& p = pb->p;
     const bool comp = p.dtype == ADI_FP32C;
-    hipStream_t st = pb->st;
+    State<T> S(pb);
     T* U = (T*)pb->U;
     T* V = (T*)pb->V;
     T* W = (T*)pb->W;
-    const bool has_src = p.src_i >= 0;
-    const double h2 = p.h * p.h;
-    auto aF = [&](int64_t m) -> T {
-        if (!has_src) return T(0);
-        return (T)(pb->a * ricker(p, p.t0 + (double)m * p.dt) / h2);
-    };
-    const int64_t ldx = pb->ldx, ldy = pb->ldy;
-    auto lo = [&](void* x) -> T* { return comp ? (T*)x : nullptr; };
-    const Buf<T> UAT{(T*)pb->UAT, lo(pb->UATlo), ldy}, UC{(T*)pb->UC, lo(pb->UClo), ldx};
-    const Buf<T> VT[2] = {{(T*)pb->VT[0], lo(pb->VTlo[0]), ldy}, {(T*)pb->VT[1], lo(pb->VTlo[1]), ldy}};
-    const Buf<T> WSb[2] = {{(T*)pb->WSb[0], lo(pb->WSblo[0]), ldx}, {(T*)pb->WSb[1], lo(pb->WSblo[1]), ldx}};
-    const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
-
-    // Pass along x (lines = interior rows, layouts UAT / VT) and along y
-    // (lines = interior columns, layouts UC / WSb).
-    auto pass = [&](int dir, const Buf<T>& uin, const Buf<T>& vin, const Buf<T>& vout, const Buf<T>& uout,
-                    int utrans, T f, int mode) -> int {
-        const Plan& pl = dir == 0 ? pb->px : pb->py;
-        auto a = base_args<T>(*pb, pl, dir == 0 ? pb->coefX : pb->coefY);
-        a.uin = uin.hi; a.uin_lo = uin.lo; a.uin_ld = uin.ld;
-        a.vin = vin.hi; a.vin_lo = vin.lo; a.vin_ld = vin.ld;
-        if (dir == 0) {
-            a.ak = pb->hasK ? (const T*)pb->aKT : nullptr;   a.ak_ld = ldy;
-            a.ar = pb->hasRv ? (const T*)pb->aRvT : nullptr; a.ar_ld = ldy;
-        } else {
-            a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = ldx;
-            a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = ldx;
-        }
-        a.vout = vout.hi; a.vout_lo = vout.lo; a.vout_ld = vout.ld;
-        a.uout = uout.hi; a.uout_lo = uout.lo; a.uout_ld = uout.ld;
-        a.utrans = utrans;
-        if (has_src) {
-            a.src_q = dir == 0 ? p.src_j - 1 : p.src_i - 1;
-            a.src_s = dir == 0 ? p.src_i : p.src_j;
-            a.aF = f;
-        }
-        hipError_t e = pl.ver == 1 ? adi::launch_line_pass<T>(a, method, mode, st, comp)
-                                   : adi::launch_line_pass2<T>(a, method, mode, st, comp);
-        if (e != hipSuccess) return hip_fail(e, dir == 0 ? "row pass" : "column pass");
-        return ADI_OK;
-    };
-    auto nolo = [](const Buf<T>& b) { return Buf<T>{b.hi, nullptr, b.ld}; };
-    int rc;
-#define PASS(...) do { rc = pass(__VA_ARGS__); if (rc != ADI_OK) return rc; } while (0)
-
+    const T f0 = (T)source_term(*pb, pb->step);
     // V (interior rows) -> VT; low words start at zero
-    HIP_TRY(adi::launch_scaled_copy<T>(VT[pb->vcur].hi, ldy, V + pb->ldV, 1, pb->ldV, p.nx + 1, pb->niy, T(1), st),
+    HIP_TRY(launch_scaled_copy<T>(S.VT[pb->vcur].hi, pb->ldy, V + pb->ldV, 1, pb->ldV, p.nx + 1, pb->niy, T(1), st),
             "transpose V");
-    if (comp) HIP_TRY(adi::launch_fill_zero<T>(VT[pb->vcur].lo, ldy, p.nx + 1, pb->niy, st), "zero V low words");
+    if (comp) HIP_TRY(launch_fill_zero<T>(S.VT[pb->vcur].lo, pb->ldy, p.nx + 1, pb->niy, st), "zero V low words");
     if (p.order == 0) {
         // explicit y part of stage 1: A and W* of step m
-        PASS(1, Uu, Wu, WSb[pb->wcur], UAT, 1, aF(pb->step), adi::LINE_EXPLICIT);
-        for (int64_t s = 0; s < nsteps; ++s) {
-            const int64_t m = pb->step + s;
-            const T f1 = aF(m + 1);
+        auto d = make_pass<T>(pb, 1, S.Uu, S.Wu, S.WSb[pb->wcur], S.UAT, 1, f0, nullptr, LINE_EXPLICIT);
+        HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
+    } else {
+        // y-implicit stage first: U -> UAT, W -> WSb, explicit x part of stage 1
+        HIP_TRY(launch_scaled_copy<T>(S.UAT.hi, pb->ldy, U + pb->ldU + 1, 1, pb->ldU, pb->nix, pb->niy, T(1), st),
+                "transpose U");
+        HIP_TRY(launch_scaled_copy<T>(S.WSb[pb->wcur].hi, pb->ldx, W + 1, pb->ldW, 1, p.ny + 1, pb->nix, T(1), st),
+                "copy W");
+        if (comp) HIP_TRY(launch_fill_zero<T>(S.WSb[pb->wcur].lo, pb->ldx, p.ny + 1, pb->nix, st), "zero W low words");
+        auto d = make_pass<T>(pb, 0, nolo(S.UAT), nolo(S.VT[pb->vcur]), S.VT[1 - pb->vcur], S.UC, 1, f0, nullptr,
+                              LINE_EXPLICIT);
+        HIP_TRY(launch_pass<T>(d, st), "explicit row pass");
+        pb->vcur ^= 1;
+    }
+    return ADI_OK;
+}
+
+template <typename T>
+PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab) {
+    State<T> S(pb);
+    const bool last = s == nsteps - 1;
+    const T f1 = (T)source_term(*pb, pb->step + s + 1);
+    PassDesc<T> d;
+    if (pb->p.order == 0) {
+        if (half == 0) {
             // rows: stage-1 sweeps along x, then C and V^{m+1}
-            PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], UC, 1, f1, adi::LINE_SWEEP);
+            d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.UC, 1, f1, aFtab, LINE_SWEEP);
             pb->vcur ^= 1;
+        } else if (last) {
+            // columns, last step: U^{m+n}, W^{m+n} into the caller's arrays
+            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.Wu, S.Uu, 0, T(0), nullptr, LINE_FINAL);
+        } else {
             // columns: stage-2 sweeps along y, then the next step's A and W*
-            if (s == nsteps - 1) {
-                PASS(1, UC, WSb[pb->wcur], Wu, Uu, 0, T(0), adi::LINE_FINAL);
-            } else {
-                PASS(1, UC, WSb[pb->wcur], WSb[1 - pb->wcur], UAT, 1, f1, adi::LINE_SWEEP);
-                pb->wcur ^= 1;
-            }
+            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.WSb[1 - pb->wcur], S.UAT, 1, f1, aFtab, LINE_SWEEP);
+            pb->wcur ^= 1;
         }
     } else {
-        // y-implicit stage first: the same passes in the other order
-        HIP_TRY(adi::launch_scaled_copy<T>(UAT.hi, ldy, U + pb->ldU + 1, 1, pb->ldU, pb->nix, pb->niy, T(1), st),
-                "transpose U");
-        HIP_TRY(adi::launch_scaled_copy<T>(WSb[pb->wcur].hi, ldx, W + 1, pb->ldW, 1, p.ny + 1, pb->nix, T(1), st),
-                "copy W");
-        if (comp) HIP_TRY(adi::launch_fill_zero<T>(WSb[pb->wcur].lo, ldx, p.ny + 1, pb->nix, st), "zero W low words");
-        // explicit x part of stage 1: A and V* of step m
-        PASS(0, nolo(UAT), nolo(VT[pb->vcur]), VT[1 - pb->vcur], UC, 1, aF(pb->step), adi::LINE_EXPLICIT);
-        pb->vcur ^= 1;
-        for (int64_t s = 0; s < nsteps; ++s) {
-            const int64_t m = pb->step + s;
-            const T f1 = aF(m + 1);
-            PASS(1, UC, WSb[pb->wcur], WSb[1 - pb->wcur], UAT, 1, f1, adi::LINE_SWEEP);
+        if (half == 0) {
+            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.WSb[1 - pb->wcur], S.UAT, 1, f1, aFtab, LINE_SWEEP);
             pb->wcur ^= 1;
-            if (s == nsteps - 1)
-                PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], Buf<T>{U + pb->ldU + 1, nullptr, pb->ldU}, 1, T(0),
-                     adi::LINE_FINAL);
+        } else {
+            if (last)
+                d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.Uu, 1, T(0), nullptr,
+                                 LINE_FINAL);
             else
-                PASS(0, UAT, VT[pb->vcur], VT[1 - pb->vcur], UC, 1, f1, adi::LINE_SWEEP);
+                d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.UC, 1, f1, aFtab, LINE_SWEEP);
             pb->vcur ^= 1;
         }
-        // W^{m+n} (interior columns) back to the caller
-        HIP_TRY(adi::launch_scaled_copy<T>(W + 1, pb->ldW, WSb[pb->wcur].hi, ldx, 1, p.ny + 1, pb->nix, T(1), st,
-                                           WSb[pb->wcur].lo), "copy W back");
     }
-#undef PASS
+    return d;
+}
+
+template <typename T>
+int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps) {
+    const auto& p = pb->p;
+    State<T> S(pb);
+    T* V = (T*)pb->V;
+    T* W = (T*)pb->W;
+    if (p.order == 1) {
+        // W^{m+n} (interior columns) back to the caller
+        HIP_TRY(launch_scaled_copy<T>(W + 1, pb->ldW, S.WSb[pb->wcur].hi, pb->ldx, 1, p.ny + 1, pb->nix, T(1), st,
+                                      S.WSb[pb->wcur].lo), "copy W back");
+    }
     // VT -> V (interior rows)
-    HIP_TRY(adi::launch_scaled_copy<T>(V + pb->ldV, pb->ldV, VT[pb->vcur].hi, 1, ldy, pb->niy, p.nx + 1, T(1), st,
-                                       VT[pb->vcur].lo), "transpose V back");
+    HIP_TRY(launch_scaled_copy<T>(V + pb->ldV, pb->ldV, S.VT[pb->vcur].hi, 1, pb->ldy, pb->niy, p.nx + 1, T(1), st,
+                                  S.VT[pb->vcur].lo), "transpose V back");
     pb->step += nsteps;
     return ADI_OK;
+}
+
+template int run_begin<float>(adi_problem*, hipStream_t);
+template int run_begin<double>(adi_problem*, hipStream_t);
+template PassDesc<float> run_pass<float>(adi_problem*, int64_t, int, int64_t, const float*);
+template PassDesc<double> run_pass<double>(adi_problem*, int64_t, int, int64_t, const double*);
+template int run_end<float>(adi_problem*, hipStream_t, int64_t);
+template int run_end<double>(adi_problem*, hipStream_t, int64_t);
+template hipError_t launch_pass<float>(const PassDesc<float>&, hipStream_t);
+template hipError_t launch_pass<double>(const PassDesc<double>&, hipStream_t);
+
+}  // namespace adi
+
+namespace {
+
+template <typename T>
+int run_impl(adi_problem* pb, int64_t nsteps) {
+    int rc = adi::run_begin<T>(pb, pb->st);
+    if (rc != ADI_OK) return rc;
+    for (int64_t s = 0; s < nsteps; ++s)
+        for (int half = 0; half < 2; ++half) {
+            const auto d = adi::run_pass<T>(pb, s, half, nsteps, nullptr);
+            HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
+        }
+    return adi::run_end<T>(pb, pb->st, nsteps);
 }
 
 template <typename T>
@@ -466,12 +468,16 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
     if (Rw)
         HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aRw, pb->ldx, Rw + 1, ldRw, 1, p.ny + 1, pb->nix, a, st), "aRw");
     if (p.method == ADI_CFD) {
+        // factor tables of the single-window kernel (the multi-window kernel
+        // uses compile-time constants)
         std::vector<double> tx, ty;
-        if (pb->px.ver == 1) build_tables(pb->px, tx); else build_tables2(pb->px, tx);
-        if (pb->py.ver == 1) build_tables(pb->py, ty); else build_tables2(pb->py, ty);
+        if (pb->px.ver == 1) build_tables(pb->px, tx);
+        if (pb->py.ver == 1) build_tables(pb->py, ty);
         std::vector<T> cx(tx.begin(), tx.end()), cy(ty.begin(), ty.end());
-        HIP_TRY(hipMemcpyAsync(pb->coefX, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefX");
-        HIP_TRY(hipMemcpyAsync(pb->coefY, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefY");
+        if (!cx.empty())
+            HIP_TRY(hipMemcpyAsync(pb->coefX, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefX");
+        if (!cy.empty())
+            HIP_TRY(hipMemcpyAsync(pb->coefY, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefY");
         HIP_TRY(hipStreamSynchronize(st), "bind sync");
         return ADI_OK;
     }

@@ -7,7 +7,8 @@ namespace adi {
 
 enum { LINE_CFD = 0, LINE_MFD = 1 };
 enum { LINE_SWEEP = 0, LINE_FINAL = 1, LINE_EXPLICIT = 2 };
-enum { LINE_WS = 512 };   // slots per window (both dtypes)
+enum { LINE_WS = 512 };   // slots per window of the multi-window kernel
+enum { LINE_NCFG = 3 };   // single-window tile shapes: windows of 512, 256, 128 slots
 
 // Arguments of one line pass.  Along a line, slot s holds the pressure value
 // of index s (interior slots 1..n-1 for CFD, 1..n for MFD) and the velocity
@@ -34,10 +35,26 @@ struct LinePassArgs {
     // compensated FP32 state: low words of the inputs (NULL = zero) and of
     // the outputs (NULL = store the rounded sum only)
     const T* uin_lo; const T* vin_lo; T* vout_lo; T* uout_lo;
+    // grouped launches: when set, aF = aFtab[tick] (tick read from device memory)
+    const T* aFtab;
 };
 
+// A grouped launch: the passes items[0..nitems) (any problems, any
+// directions, one kernel variant) in one grid; starts[i] is the first tile
+// of item i (prefix sums of nlg * nwin, starts[nitems] = total).
 template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
+struct GroupArgs {
+    const LinePassArgs<T>* items;
+    const int* starts;
+    const int* tick;
+    int nitems, total;
+};
+
+// Single-window kernel (line_pass.hip), tile shape cfg (window line_ws(cfg)).
+template <typename T>
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg);
+template <typename T>
+hipError_t launch_line_group(const GroupArgs<T>& g, int cfg, int method, int mode, hipStream_t st, bool comp);
 
 // dst[r*dld + c] = scale * (src[r*srs + c*scs] + src2[same])   (src2 may be NULL)
 template <typename T>
@@ -48,13 +65,16 @@ hipError_t launch_scaled_copy(T* dst, int64_t dld, const T* src, int64_t srs, in
 template <typename T>
 hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t st);
 
-int line_lanes(int dtype);
+int line_lanes(int dtype, int cfg);
+int line_ws(int cfg);
 int line_halo(int dtype, int method, int sweeps);
 
 // Multi-window variant (line_pass2.hip): lines per workgroup and slots per
-// lane segment; compact factor tables hold 12 arrays of LINE_WS per window.
+// lane segment.
 template <typename T>
 hipError_t launch_line_pass2(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
+template <typename T>
+hipError_t launch_line_group2(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp);
 int line2_lanes(int dtype);
 int line2_seg(int dtype);
 

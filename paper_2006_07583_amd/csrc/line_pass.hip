@@ -48,16 +48,19 @@
 
 namespace adi {
 
-template <typename T> struct Tile;
-template <> struct Tile<float> {
-    static constexpr int LW = 32, R = 16, NW = 16, TS = 2;
-};
-template <> struct Tile<double> {
-    static constexpr int LW = 16, R = 8, NW = 16, TS = 4;
-};
+// Tile shapes (lines per workgroup LW, slots per lane R, waves NW, carry
+// reach TS in segments) for windows of 512, 256 and 128 slots.  Short lines
+// take the smallest window that holds them, with more lines per workgroup.
+template <typename T, int CF> struct Tile;
+template <> struct Tile<float, 0> { static constexpr int LW = 32, R = 16, NW = 16, TS = 2; };
+template <> struct Tile<float, 1> { static constexpr int LW = 64, R = 16, NW = 16, TS = 2; };
+template <> struct Tile<float, 2> { static constexpr int LW = 64, R = 8, NW = 16, TS = 4; };
+template <> struct Tile<double, 0> { static constexpr int LW = 16, R = 8, NW = 16, TS = 4; };
+template <> struct Tile<double, 1> { static constexpr int LW = 32, R = 8, NW = 16, TS = 4; };
+template <> struct Tile<double, 2> { static constexpr int LW = 64, R = 8, NW = 16, TS = 4; };
 
-template <typename T> struct K {
-    static constexpr int LW = Tile<T>::LW, R = Tile<T>::R, NW = Tile<T>::NW, TS = Tile<T>::TS;
+template <typename T, int CF> struct K {
+    static constexpr int LW = Tile<T, CF>::LW, R = Tile<T, CF>::R, NW = Tile<T, CF>::NW, TS = Tile<T, CF>::TS;
     static constexpr int SPW = 64 / LW;
     static constexpr int NSEG = NW * SPW;
     static constexpr int WS = NSEG * R;
@@ -65,8 +68,9 @@ template <typename T> struct K {
     static constexpr int SL = NSEG * LW;   // one LDS field: a value per lane
 };
 
-static_assert(K<float>::WS == LINE_WS, "window size");
-static_assert(K<double>::WS == LINE_WS, "window size");
+static_assert(K<float, 0>::WS == LINE_WS && K<double, 0>::WS == LINE_WS, "window size");
+static_assert(K<float, 1>::WS == 256 && K<double, 1>::WS == 256, "window size");
+static_assert(K<float, 2>::WS == 128 && K<double, 2>::WS == 128, "window size");
 
 template <int METHOD> struct Halo;
 template <> struct Halo<LINE_CFD> { static constexpr int N = 1, DEEP = 3; };
@@ -79,8 +83,8 @@ __device__ __forceinline__ T xv(const T (&x)[R], const T (&hl)[D], const T (&hr)
     return p < -D ? T(0) : (p < 0 ? hl[D + p] : (p < R ? x[p] : (p < R + D ? hr[p - R] : T(0))));
 }
 
-template <typename T, int METHOD> struct Pass {
-    using C = K<T>;
+template <typename T, int CF, int METHOD> struct Pass {
+    using C = K<T, CF>;
     static constexpr int LW = C::LW, R = C::R, NSEG = C::NSEG, WS = C::WS, SL = C::SL, TS = C::TS;
     static constexpr int DN = Halo<METHOD>::N, DD = Halo<METHOD>::DEEP;
     static constexpr int HF = (4 * DN > 2 * DD ? 4 * DN : 2 * DD) / 2;   // fields per ring half
@@ -325,18 +329,19 @@ template <typename T, int METHOD> struct Pass {
     }
 };
 
-template <typename T, int METHOD, int MODE, bool COMP>
-__global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<T> a) {
-    using P = Pass<T, METHOD>;
-    constexpr int LW = K<T>::LW, R = K<T>::R, SPW = K<T>::SPW, WS = K<T>::WS;
-    __shared__ T smem[P::SMEM];
+// One workgroup's share of a pass: line group `tile` (one window per line).
+template <typename T, int CF, int METHOD, int MODE, bool COMP>
+__device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* smem) {
+    using P = Pass<T, CF, METHOD>;
+    using C = K<T, CF>;
+    constexpr int LW = C::LW, R = C::R, SPW = C::SPW, WS = C::WS;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lq = lane % LW;
     const int seg = wave * SPW + lane / LW;
-    const int lg = blockIdx.x % a.nlg;
-    const int g = blockIdx.x / a.nlg;
+    const int lg = tile % a.nlg;
+    const int g = tile / a.nlg;
     const int c0 = g * a.S;
     const int c1 = min(c0 + a.S, a.ns);
     int w0 = 0;
@@ -352,7 +357,7 @@ __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<
 
     if (METHOD == LINE_CFD) {
         const T* src = a.coef + (size_t)g * 6 * WS;
-        for (int i = tid; i < 6 * WS; i += K<T>::NT) smem[P::RING + i] = src[i];
+        for (int i = tid; i < 6 * WS; i += C::NT) smem[P::RING + i] = src[i];
     }
 
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
@@ -420,8 +425,27 @@ __global__ void __launch_bounds__(K<T>::NT) line_pass_kernel(const LinePassArgs<
         }
     }
 
-    pass_outputs<T, R, LW, K<T>::NT, P::TILEP, COMP>(a, smem, Tt, U, s0, q, qok, lq, lg, c0, c1, uhi, vhi,
-                                                    tid, MODE != LINE_FINAL);
+    pass_outputs<T, R, LW, C::NT, P::TILEP, COMP>(a, smem, Tt, U, s0, q, qok, lq, lg, c0, c1, uhi, vhi,
+                                                  tid, MODE != LINE_FINAL);
+}
+
+template <typename T, int CF, int METHOD, int MODE, bool COMP>
+__global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_kernel(const LinePassArgs<T> a) {
+    __shared__ T smem[Pass<T, CF, METHOD>::SMEM];
+    lp_body<T, CF, METHOD, MODE, COMP>(a, (int)blockIdx.x, smem);
+}
+
+// Several passes (of several problems) in one launch: each workgroup finds
+// its pass in the prefix sums of the block counts.
+template <typename T, int CF, int METHOD, int MODE, bool COMP>
+__global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_group_kernel(const GroupArgs<T> ga) {
+    __shared__ T smem[Pass<T, CF, METHOD>::SMEM];
+    int tile;
+    const int it = group_item(ga, tile);
+    if (it < 0) return;
+    LinePassArgs<T> a = ga.items[it];
+    if (a.aFtab) a.aF = a.aFtab[*ga.tick];
+    lp_body<T, CF, METHOD, MODE, COMP>(a, tile, smem);
 }
 
 // ------------------------------------------------------------------------
@@ -464,13 +488,18 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, i
     }
 }
 
-template <typename T, bool COMP>
-hipError_t launch_lp(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
-    dim3 grid((unsigned)(a.nlg * a.nwin)), block(K<T>::NT);
-#define LP_CASE(M, MD)                                                                 \
-    if (method == M && mode == MD) {                                                   \
-        hipLaunchKernelGGL((line_pass_kernel<T, M, MD, COMP>), grid, block, 0, st, a); \
-        return hipGetLastError();                                                      \
+template <typename T, int CF, bool COMP>
+hipError_t launch_lp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st) {
+    const unsigned nb = a ? (unsigned)(a->nlg * a->nwin) : (unsigned)(((ga->total + 7) / 8) * 8);
+    if (nb == 0) return hipSuccess;
+    dim3 grid(nb), block(K<T, CF>::NT);
+#define LP_CASE(M, MD)                                                                                  \
+    if (method == M && mode == MD) {                                                                    \
+        if (a)                                                                                          \
+            hipLaunchKernelGGL((line_pass_kernel<T, CF, M, MD, COMP>), grid, block, 0, st, *a);        \
+        else                                                                                            \
+            hipLaunchKernelGGL((line_pass_group_kernel<T, CF, M, MD, COMP>), grid, block, 0, st, *ga); \
+        return hipGetLastError();                                                                       \
     }
     LP_CASE(LINE_CFD, LINE_SWEEP)
     LP_CASE(LINE_CFD, LINE_FINAL)
@@ -482,10 +511,29 @@ hipError_t launch_lp(const LinePassArgs<T>& a, int method, int mode, hipStream_t
     return hipErrorInvalidValue;
 }
 
+template <typename T, bool COMP>
+hipError_t launch_lp_cfg(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int cfg, int method, int mode,
+                         hipStream_t st) {
+    switch (cfg) {
+        case 0: return launch_lp<T, 0, COMP>(a, ga, method, mode, st);
+        case 1: return launch_lp<T, 1, COMP>(a, ga, method, mode, st);
+        case 2: return launch_lp<T, 2, COMP>(a, ga, method, mode, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp) {
-    if (!comp) return launch_lp<T, false>(a, method, mode, st);
-    if constexpr (std::is_same<T, float>::value) return launch_lp<T, true>(a, method, mode, st);
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg) {
+    if (!comp) return launch_lp_cfg<T, false>(&a, nullptr, cfg, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_lp_cfg<T, true>(&a, nullptr, cfg, method, mode, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_line_group(const GroupArgs<T>& ga, int cfg, int method, int mode, hipStream_t st, bool comp) {
+    if (ga.total <= 0) return hipSuccess;
+    if (!comp) return launch_lp_cfg<T, false>(nullptr, &ga, cfg, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_lp_cfg<T, true>(nullptr, &ga, cfg, method, mode, st);
     return hipErrorInvalidValue;
 }
 
@@ -514,7 +562,15 @@ hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t
     return hipGetLastError();
 }
 
-int line_lanes(int dtype) { return dtype == 0 ? K<float>::LW : K<double>::LW; }
+int line_lanes(int dtype, int cfg) {
+    static const int lw[2][LINE_NCFG] = {{K<float, 0>::LW, K<float, 1>::LW, K<float, 2>::LW},
+                                         {K<double, 0>::LW, K<double, 1>::LW, K<double, 2>::LW}};
+    return lw[dtype == 1 ? 1 : 0][cfg];
+}
+int line_ws(int cfg) {
+    static const int ws[LINE_NCFG] = {K<float, 0>::WS, K<float, 1>::WS, K<float, 2>::WS};
+    return ws[cfg];
+}
 
 // Overlap of neighbouring windows, in slots.  Mimetic: the dependence cone
 // of K sweeps plus the final derivative is 3K + 2 slots; two slots spare.
@@ -525,8 +581,10 @@ int line_halo(int dtype, int method, int sweeps) {
     return dtype == 0 ? 20 + 2 * sweeps : 40 + 3 * sweeps;
 }
 
-template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool);
-template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, int);
+template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool, int);
+template hipError_t launch_line_group<float>(const GroupArgs<float>&, int, int, int, hipStream_t, bool);
+template hipError_t launch_line_group<double>(const GroupArgs<double>&, int, int, int, hipStream_t, bool);
 template hipError_t launch_scaled_copy<float>(float*, int64_t, const float*, int64_t, int64_t, int, int, float,
                                              hipStream_t, const float*);
 template hipError_t launch_scaled_copy<double>(double*, int64_t, const double*, int64_t, int64_t, int, int, double,

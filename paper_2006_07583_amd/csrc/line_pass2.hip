@@ -19,19 +19,20 @@
 //    combines the carries of its TS neighbouring segments:
 //        x''_k = x''^_k + a_k Y + b_k X
 //    with Y the incoming forward carry, X the true first value of the next
-//    segment and a_k, b_k the responses of the segment (compile-time
-//    constants for interior segments, host tables near the physical
-//    boundary).  The same data give the neighbours' edge values, so the
+//    segment and a_k, b_k the responses of a segment (compile-time
+//    constants).  The same data give the neighbours' edge values, so the
 //    stencil halos of the next derivative are recomputed redundantly
 //    instead of exchanged.
 //  * Mimetic stencils: with the neighbours' last 3 / first 3 pressure values
 //    a lane computes the velocity on its slots plus 2 left / 1 right, which
 //    is all the next D4 needs: one exchange per sweep.
 //
-// Segments touching the physical boundary rows (and their neighbours) take
-// the table path; the window placement keeps every boundary-row stencil
-// inside one lane (first window starts at slot 0, last window ends at the
-// last slot).
+//  * Physical boundary rows.  Every window solves with the same constant
+//    factors; the windows holding the first or last slot of the line then
+//    subtract a low-rank correction (Sherman-Morrison-Woodbury) that turns
+//    the constant matrix into P4 / Pbar4 (one more exchange per solve).
+//    The window placement keeps every boundary-row stencil inside one lane
+//    (first window starts at slot 0, last window ends at the last slot).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -65,6 +66,63 @@ template <int R> struct Resp {
     }
 };
 
+// Near a physical boundary the compact rows differ from the constant-factor
+// matrix Pc the kernel factorises (first row [2+sqrt3, 1], interior
+// (1, 4, 1), last row (1, 4)): P4 row 0 is [6, 18] and row n is [18, 6]; the
+// reduced Pbar4 has rows 1..n-1 with [6, 6] ends, handled as Pc-sized
+// systems with the trivial rows x_0 = 0, x_n = 0 added.  The exact solution
+// is the Pc solution minus a rank-1 (P) or rank-2 (Pbar) correction
+// (Sherman-Morrison-Woodbury):  x = xc - Z C^-1 E xc, with E the row
+// differences, Z = Pc^-1 [unit rows] (decaying like (2 - sqrt 3)^d from the
+// boundary) and C = I + E Z.  All of these are constants of Pc.
+struct BndResp {
+    static constexpr int NZ = 48;
+    double zl0[NZ], zl1[NZ];   // Pc^-1 e_0, Pc^-1 e_1, index = slot
+    double zr0[NZ], zr1[NZ];   // Pc^-1 e_n, Pc^-1 e_{n-1}, index = n - slot
+    double cl0, cr0;           // 1 / C for P at the left / right end
+    double cl1[4], cr1[4];     // C^-1 (row-major 2 x 2) for Pbar at the left / right end
+    constexpr BndResp() : zl0(), zl1(), zr0(), zr1(), cl0(0), cr0(0), cl1(), cr1() {
+        constexpr int M = 160;
+        constexpr double de = 3.7320508075688772935;
+        // LU of Pc (multiplier alpha, pivots 2 + sqrt3) solving Pc x = e_j
+        auto solve = [](int j, double* out) {
+            double y[M] = {}, x[M] = {};
+            for (int k = 0; k < M; ++k) y[k] = (k == j ? 1.0 : 0.0) - (k > 0 ? kAlpha * y[k - 1] : 0.0);
+            x[M - 1] = y[M - 1] / de;
+            for (int k = M - 2; k >= 0; --k) x[k] = (y[k] - x[k + 1]) / de;
+            for (int k = 0; k < M; ++k) out[k] = x[k];
+        };
+        double a0[M] = {}, a1[M] = {}, b0[M] = {}, b1[M] = {};
+        solve(0, a0);
+        solve(1, a1);
+        solve(M - 1, b0);
+        solve(M - 2, b1);
+        for (int k = 0; k < NZ; ++k) {
+            zl0[k] = a0[k];
+            zl1[k] = a1[k];
+            zr0[k] = b0[M - 1 - k];
+            zr1[k] = b1[M - 1 - k];
+        }
+        cl0 = 1.0 / (1.0 + (6.0 - de) * zl0[0] + 17.0 * zl0[1]);
+        cr0 = 1.0 / (1.0 + 17.0 * zr0[1] + 2.0 * zr0[0]);
+        // left Pbar: E rows [(1 - de), -1, 0] and [-1, 2, 5] on slots 0..2
+        double L[4] = {1.0 + (1.0 - de) * zl0[0] - zl0[1], (1.0 - de) * zl1[0] - zl1[1],
+                       -zl0[0] + 2.0 * zl0[1] + 5.0 * zl0[2], 1.0 - zl1[0] + 2.0 * zl1[1] + 5.0 * zl1[2]};
+        double dl = L[0] * L[3] - L[1] * L[2];
+        cl1[0] = L[3] / dl; cl1[1] = -L[1] / dl; cl1[2] = -L[2] / dl; cl1[3] = L[0] / dl;
+        // right Pbar: E rows [5, 2, -1] on slots n-2, n-1, n and [-1, -3] on n-1, n;
+        // Z columns Pc^-1 e_{n-1}, Pc^-1 e_n (index = n - slot)
+        double Rm[4] = {1.0 + 5.0 * zr1[2] + 2.0 * zr1[1] - zr1[0], 5.0 * zr0[2] + 2.0 * zr0[1] - zr0[0],
+                        -zr1[1] - 3.0 * zr1[0], 1.0 - zr0[1] - 3.0 * zr0[0]};
+        double dr = Rm[0] * Rm[3] - Rm[1] * Rm[2];
+        cr1[0] = Rm[3] / dr; cr1[1] = -Rm[1] / dr; cr1[2] = -Rm[2] / dr; cr1[3] = Rm[0] / dr;
+    }
+};
+
+// Every column of Pc^-1 used above is geometric with ratio -alpha away from
+// its first entry, so a correction is fully described by its value at the
+// boundary row (W0) and at the next row (W1): w(d) = W1 (-alpha)^(d-1), d >= 1.
+
 template <typename T> struct K2 {
     static constexpr int LW = Cfg2<T>::LW, R = Cfg2<T>::R, NW = Cfg2<T>::NW, TS = Cfg2<T>::TS;
     static constexpr int SPW = 64 / LW, NSEG = NW * SPW, WS = NSEG * R, NT = NW * 64;
@@ -83,32 +141,30 @@ template <typename T, int METHOD> struct Pass2 {
     static constexpr int RING = 2 * HALF;
     static constexpr int TILEP = WS + 1;
     static constexpr int TILE = LW * TILEP;
-    static constexpr int SMEM = RING > TILE ? RING : TILE;
-    static constexpr int NTAB = 12;                          // table arrays per window (6 per kind)
+    static constexpr int CB = 4 * LW;                        // boundary correction coefficients
+    static constexpr int WORK = RING + CB;
+    static constexpr int SMEM = WORK > TILE ? WORK : TILE;
 
     const LinePassArgs<T>& a;
     T* ring;
+    T* cbuf;
     int seg, lq, s0, n, xc;
     T yend;
-    bool fast;               // segment and neighbours use the interior constants
-    const T* tab;            // this window's tables (table path)
+    bool bnd;                // lane holds physical boundary rows
+    bool lwin, rwin;         // window holds the first / last slot of the line (block-uniform)
 
-    __device__ Pass2(const LinePassArgs<T>& args, T* smem, int seg_, int lq_, int s0_, bool fast_,
-                     const T* tab_)
-        : a(args), ring(smem), seg(seg_), lq(lq_), s0(s0_), n(args.n), xc(0), fast(fast_), tab(tab_) {}
+    __device__ Pass2(const LinePassArgs<T>& args, T* smem, int seg_, int lq_, int s0_, bool bnd_, bool lwin_,
+                     bool rwin_)
+        : a(args), ring(smem), cbuf(smem + RING), seg(seg_), lq(lq_), s0(s0_), n(args.n), xc(0), bnd(bnd_),
+          lwin(lwin_), rwin(rwin_) {}
 
     __device__ __forceinline__ T* half() { return ring + (xc & 1) * HALF; }
     __device__ __forceinline__ int at(int f, int sg) const { return f * FIELD + (sg + PADS) * LW + lq; }
 
     // ================= compact scheme =================
-    // Table layout per window, kind k (0: P, 1: Pbar), 6 arrays of WS:
-    //   m (multiplier), dd (inverse pivot / alpha), e (sup * inverse pivot),
-    //   a, b (segment responses), G (product of -m over the segment, at its
-    //   first slot).  Rows outside the operator hold zeros.
-    __device__ __forceinline__ const T* tk(int kind, int arr) const { return tab + (kind * 6 + arr) * WS; }
-
     // Right-hand side (scaled by 1/c) of the compact derivative of kind
-    // `kind` (0: Q4 on pressure, 1: Qbar4 on velocity) into o.
+    // `kind` (0: Q4 on pressure, 1: Qbar4 on velocity) into o.  Boundary rows
+    // use the closures of Appendix A; the trivial rows added to Pbar get 0.
     __device__ __forceinline__ void rhs(int kind, const T (&f)[R], T fl, T fr, T (&o)[R]) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -116,7 +172,7 @@ template <typename T, int METHOD> struct Pass2 {
             const T fm = k > 0 ? f[k - 1] : fl;
             o[k] = fp - fm;
         }
-        if (!fast) {
+        if (bnd) {
             const T third = T(1.0 / 3.0);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -127,6 +183,7 @@ template <typename T, int METHOD> struct Pass2 {
                     if (s == n && k >= 3)
                         o[k] = third * (f[k - 3] - T(9) * f[k - 2] - T(9) * f[k - 1] + T(17) * f[k]);
                 } else {
+                    if (s == 0 || s == n) o[k] = T(0);
                     if (s == 1 && k >= 1 && k + 2 < R)
                         o[k] = third * (-f[k - 1] - T(9) * f[k] + T(9) * f[k + 1] + f[k + 2]);
                     if (s == n - 1 && k >= 2 && k + 1 < R)
@@ -137,26 +194,13 @@ template <typename T, int METHOD> struct Pass2 {
     }
 
     // Local forward + backward sweeps with zero carries, then publish.
-    __device__ __forceinline__ void local_solve(int kind, T (&o)[R]) {
-        if (fast) {
-            const T al = T(kAlpha);
+    __device__ __forceinline__ void local_solve(T (&o)[R]) {
+        const T al = T(kAlpha);
 #pragma unroll
-            for (int k = 1; k < R; ++k) o[k] = fma(-al, o[k - 1], o[k]);
-            yend = o[R - 1];
+        for (int k = 1; k < R; ++k) o[k] = fma(-al, o[k - 1], o[k]);
+        yend = o[R - 1];
 #pragma unroll
-            for (int k = R - 2; k >= 0; --k) o[k] = fma(-al, o[k + 1], o[k]);
-        } else {
-            const int sl = seg * R;
-            const T* m = tk(kind, 0) + sl;
-            const T* dd = tk(kind, 1) + sl;
-            const T* e = tk(kind, 2) + sl;
-#pragma unroll
-            for (int k = 1; k < R; ++k) o[k] = fma(-m[k], o[k - 1], o[k]);
-            yend = o[R - 1];
-            o[R - 1] = o[R - 1] * dd[R - 1];
-#pragma unroll
-            for (int k = R - 2; k >= 0; --k) o[k] = fma(-e[k], o[k + 1], o[k] * dd[k]);
-        }
+        for (int k = R - 2; k >= 0; --k) o[k] = fma(-al, o[k + 1], o[k]);
         T* h = half();
         h[at(0, seg)] = yend;
         h[at(1, seg)] = o[0];
@@ -164,55 +208,106 @@ template <typename T, int METHOD> struct Pass2 {
     }
 
     // After the barrier: combine carries, correct the segment, produce the
-    // neighbours' edge values xl (slot -1) and xr (slot R) of the solution.
+    // neighbours' edge values xl (slot -1) and xr (slot R) of the solution;
+    // then, in the windows holding a physical boundary, apply the boundary-row
+    // correction (one more exchange).
     __device__ __forceinline__ void finish_solve(int kind, T (&o)[R], T& xl, T& xr) {
         const T* h = half();
         ++xc;
         const bool has_next = seg + 1 < NSEG, has_prev = seg > 0;
-        if (fast) {
-            constexpr Resp<R> rs{};
-            const T G = T(rs.G);
-            T Y = h[at(0, seg - 1)];
-            if (TS > 1) Y = fma(G, h[at(0, seg - 2)], Y);
-            T Yv = fma(G, Y, yend);                 // forward carry into seg + 1
-            T X = has_next ? fma(T(rs.a[0]), Yv, h[at(1, seg + 1)]) : T(0);
-            if (TS > 1 && seg + 2 < NSEG) {
-                const T Yv2 = fma(G, Yv, h[at(0, seg + 1)]);
-                X = fma(T(rs.b[0]), fma(T(rs.a[0]), Yv2, h[at(1, seg + 2)]), X);
-            }
-#pragma unroll
-            for (int k = 0; k < R; ++k) o[k] = fma(T(rs.a[k]), Y, fma(T(rs.b[k]), X, o[k]));
-            const T Ym = TS > 1 ? h[at(0, seg - 2)] : T(0);   // forward carry into seg - 1
-            xl = has_prev ? fma(T(rs.b[R - 1]), o[0], fma(T(rs.a[R - 1]), Ym, h[at(2, seg - 1)])) : T(0);
-            xr = X;
-        } else {
-            const int sl = seg * R;
-            const T* A = tk(kind, 3);
-            const T* B = tk(kind, 4);
-            const T* Gt = tk(kind, 5);
-            const int sp = sl - R, sn = sl + R, sn2 = sl + 2 * R;
-            const T Gp = seg > 0 ? Gt[sp] : T(0);
-            const T Gs = Gt[sl];
-            T Y = h[at(0, seg - 1)];
-            if (TS > 1) Y = fma(Gp, h[at(0, seg - 2)], Y);
-            T Yv = fma(Gs, Y, yend);
-            const T an = has_next ? A[sn] : T(0);
-            T X = has_next ? fma(an, Yv, h[at(1, seg + 1)]) : T(0);
-            if (TS > 1 && seg + 2 < NSEG) {
-                const T Gn = seg + 1 < NSEG ? Gt[sn] : T(0);
-                const T bn = seg + 1 < NSEG ? B[sn] : T(0);
-                const T an2 = seg + 2 < NSEG ? A[sn2] : T(0);
-                const T Yv2 = fma(Gn, Yv, h[at(0, seg + 1)]);
-                X = fma(bn, fma(an2, Yv2, h[at(1, seg + 2)]), X);
-            }
-#pragma unroll
-            for (int k = 0; k < R; ++k) o[k] = fma(A[sl + k], Y, fma(B[sl + k], X, o[k]));
-            const T Ym = TS > 1 ? h[at(0, seg - 2)] : T(0);
-            const T ap = has_prev ? A[sl - 1] : T(0);
-            const T bp = has_prev ? B[sl - 1] : T(0);
-            xl = has_prev ? fma(bp, o[0], fma(ap, Ym, h[at(2, seg - 1)])) : T(0);
-            xr = X;
+        constexpr Resp<R> rs{};
+        const T G = T(rs.G);
+        T Y = h[at(0, seg - 1)];
+        if (TS > 1) Y = fma(G, h[at(0, seg - 2)], Y);
+        T Yv = fma(G, Y, yend);                 // forward carry into seg + 1
+        T X = has_next ? fma(T(rs.a[0]), Yv, h[at(1, seg + 1)]) : T(0);
+        if (TS > 1 && seg + 2 < NSEG) {
+            const T Yv2 = fma(G, Yv, h[at(0, seg + 1)]);
+            X = fma(T(rs.b[0]), fma(T(rs.a[0]), Yv2, h[at(1, seg + 2)]), X);
         }
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = fma(T(rs.a[k]), Y, fma(T(rs.b[k]), X, o[k]));
+        const T Ym = TS > 1 ? h[at(0, seg - 2)] : T(0);   // forward carry into seg - 1
+        xl = has_prev ? fma(T(rs.b[R - 1]), o[0], fma(T(rs.a[R - 1]), Ym, h[at(2, seg - 1)])) : T(0);
+        xr = X;
+        if (lwin || rwin) correct(kind, o, xl, xr);
+    }
+
+    // Value of a boundary correction at distance d from the boundary row.
+    __device__ static T corr_at(int d, T W0, T W1) {
+        if (d < 0 || d >= BndResp::NZ) return T(0);
+        if (d == 0) return W0;
+        T w = W1;
+        for (int i = 1; i < d; ++i) w *= T(-kAlpha);
+        return w;
+    }
+
+    __device__ void correct(int kind, T (&o)[R], T& xl, T& xr) {
+        constexpr BndResp kb{};
+        constexpr double de = 3.7320508075688772935;
+        constexpr int NZ = BndResp::NZ;
+        // correction values at the boundary row and the next, from the lane
+        // holding the boundary rows
+        if (lwin && seg == 0) {
+            T W0, W1;
+            if (kind == 0) {
+                const T c = T(kb.cl0) * fma(T(6.0 - de), o[0], T(17) * o[1]);
+                W0 = T(kb.zl0[0]) * c;
+                W1 = T(kb.zl0[1]) * c;
+            } else {
+                const T e0 = fma(T(1.0 - de), o[0], -o[1]);
+                const T e1 = fma(T(2), o[1], fma(T(5), o[2], -o[0]));
+                const T c0 = fma(T(kb.cl1[0]), e0, T(kb.cl1[1]) * e1);
+                const T c1 = fma(T(kb.cl1[2]), e0, T(kb.cl1[3]) * e1);
+                W0 = fma(T(kb.zl0[0]), c0, T(kb.zl1[0]) * c1);
+                W1 = fma(T(kb.zl0[1]), c0, T(kb.zl1[1]) * c1);
+            }
+            cbuf[lq] = W0;
+            cbuf[LW + lq] = W1;
+        }
+        if (rwin && seg == NSEG - 1) {
+            // slot n is the last slot of the window (position R - 1)
+            T V0, V1;
+            if (kind == 0) {
+                const T c = T(kb.cr0) * fma(T(17), o[R - 2], T(2) * o[R - 1]);
+                V0 = T(kb.zr0[0]) * c;
+                V1 = T(kb.zr0[1]) * c;
+            } else {
+                const T e0 = fma(T(5), o[R - 3], fma(T(2), o[R - 2], -o[R - 1]));
+                const T e1 = fma(T(-3), o[R - 1], -o[R - 2]);
+                const T c0 = fma(T(kb.cr1[0]), e0, T(kb.cr1[1]) * e1);
+                const T c1 = fma(T(kb.cr1[2]), e0, T(kb.cr1[3]) * e1);
+                V0 = fma(T(kb.zr1[0]), c0, T(kb.zr0[0]) * c1);
+                V1 = fma(T(kb.zr1[1]), c0, T(kb.zr0[1]) * c1);
+            }
+            cbuf[2 * LW + lq] = V0;
+            cbuf[3 * LW + lq] = V1;
+        }
+        __syncthreads();
+        if (lwin && s0 - 1 < NZ) {
+            const T W0 = cbuf[lq], W1 = cbuf[LW + lq];
+            T w = s0 == 0 ? W0 : corr_at(s0, W0, W1);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                o[k] -= w;
+                w = (s0 + k == 0) ? W1 : w * T(-kAlpha);
+            }
+            if (seg > 0) xl -= corr_at(s0 - 1, W0, W1);
+            xr -= w;
+        }
+        if (rwin && n - (s0 + R) < NZ) {
+            const T V0 = cbuf[2 * LW + lq], V1 = cbuf[3 * LW + lq];
+            const int dlast = n - (s0 + R - 1);          // distance of the lane's last slot
+            T w = corr_at(dlast, V0, V1);
+#pragma unroll
+            for (int k = R - 1; k >= 0; --k) {
+                o[k] -= w;
+                w = (n - (s0 + k) == 0) ? V1 : w * T(-kAlpha);
+            }
+            xl -= w;
+            if (seg + 1 < NSEG) xr -= corr_at(dlast - 1, V0, V1);
+        }
+        __syncthreads();   // values read before the next correction writes them
     }
 
     // ================= mimetic scheme =================
@@ -249,24 +344,12 @@ __device__ __forceinline__ T md(T vm2, T vm1, T v0, T v1) {
     return fma(T(-1.0 / 27.0), v1 - vm2, v0 - vm1);
 }
 
-// BND = false: windows away from the physical boundary (every segment uses
-// the interior constants).  BND = true: the windows holding the boundary
-// rows; segments near those rows use the host tables.
-template <typename T, int METHOD, int MODE, bool BND, bool COMP>
-__global__ void __launch_bounds__(K2<T>::NT)
-__attribute__((amdgpu_waves_per_eu(BND ? 1 : Cfg2<T>::WPE, BND ? 8 : Cfg2<T>::WPE)))
-line_pass2_kernel(const LinePassArgs<T> a) {
+// One workgroup's share of a pass: line group tile % nlg of window tile / nlg.
+template <typename T, int METHOD, int MODE, bool COMP>
+__device__ __forceinline__ void lp2_body(const LinePassArgs<T>& a, int tile, T* smem) {
     using C = K2<T>;
     using P = Pass2<T, METHOD>;
     constexpr int LW = C::LW, R = C::R, SPW = C::SPW, WS = C::WS, NSEG = C::NSEG;
-    __shared__ T smem[P::SMEM];
-
-    // XCD-aware tile order: consecutive blocks of one XCD take neighbouring
-    // line groups of the same window.
-    const int nb = a.nlg * a.gcount;
-    const int per = (nb + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (tile >= nb) return;
     const int lg = tile % a.nlg, g = a.gbase + (tile / a.nlg) * a.gstride;
 
     const int tid = threadIdx.x;
@@ -282,23 +365,11 @@ line_pass2_kernel(const LinePassArgs<T> a) {
     const int n = a.n;
     const int uhi = METHOD == LINE_CFD ? n - 1 : n;
 
-    // table path near the physical boundary rows
-    bool fast;
-    {
-        const int zlo = 2 * R;
-        auto cst = [&](int sg) {
-            const int ss = w0 + sg * R;
-            if (sg < 0 || sg >= NSEG) return true;
-            const bool left_ok = (w0 > 0) || ss >= zlo;
-            const bool right_ok = ss + R - 1 <= n - 2;
-            return left_ok && right_ok;
-        };
-        fast = cst(seg - 1) && cst(seg) && cst(seg + 1);
-        if (METHOD == LINE_MFD) fast = (s0 - 2 >= 2) && (s0 + R <= n - 2);
-        if (!BND) fast = true;
-    }
-    const T* tab = METHOD == LINE_CFD ? a.coef + (size_t)g * P::NTAB * WS : nullptr;
-    P p(a, smem, seg, lq, s0, fast, tab);
+    // lanes holding physical boundary rows (closure stencils), and windows
+    // holding the first / last slot of the line (boundary-row correction)
+    const bool bnd = s0 <= 1 || s0 + R - 1 >= n - 1;
+    const bool lwin = w0 == 0, rwin = w0 + WS >= a.ns;
+    P p(a, smem, seg, lq, s0, bnd, lwin, rwin);
 
     // zero the padding segments of both ring halves
     for (int i = tid; i < 2 * P::NF * 2 * C::PADS * LW; i += C::NT) {
@@ -349,12 +420,12 @@ line_pass2_kernel(const LinePassArgs<T> a) {
         if (MODE == LINE_EXPLICIT || COMP) {
             // derivatives of the state: G(A) into Tt, D(B) into U
             p.rhs(0, A, Al, Ar, Tt);
-            p.local_solve(0, Tt);
+            p.local_solve(Tt);
             __syncthreads();
             p.finish_solve(0, Tt, xl, xr);
             const T gl = -Rl * xl, gr = -Rr * xr;
             p.rhs(1, B, Bl, Br, U);
-            p.local_solve(1, U);
+            p.local_solve(U);
             __syncthreads();
             p.finish_solve(1, U, xl, xr);
             const T dl = -Kl * xl, dr = -Kr * xr;
@@ -382,7 +453,7 @@ line_pass2_kernel(const LinePassArgs<T> a) {
             if (!COMP) {
                 // u_1 = A - aK D(B)
                 p.rhs(1, B, Bl, Br, U);
-                p.local_solve(1, U);
+                p.local_solve(U);
                 __syncthreads();
                 p.finish_solve(1, U, xl, xr);
 #pragma unroll
@@ -395,7 +466,7 @@ line_pass2_kernel(const LinePassArgs<T> a) {
             }
             for (int it = 1; it < a.sweeps; ++it) {
                 p.rhs(0, U, Ul, Ur, Tt);
-                p.local_solve(0, Tt);
+                p.local_solve(Tt);
                 __syncthreads();
                 p.finish_solve(0, Tt, xl, xr);
 #pragma unroll
@@ -403,7 +474,7 @@ line_pass2_kernel(const LinePassArgs<T> a) {
                 Tl = fma(-Rl, xl, Bl);
                 Tr = fma(-Rr, xr, Br);
                 p.rhs(1, Tt, Tl, Tr, U);
-                p.local_solve(1, U);
+                p.local_solve(U);
                 __syncthreads();
                 p.finish_solve(1, U, xl, xr);
 #pragma unroll
@@ -412,7 +483,7 @@ line_pass2_kernel(const LinePassArgs<T> a) {
                 Ur = fma(-Kr, xr, Ar);
             }
             p.rhs(0, U, Ul, Ur, Tt);
-            p.local_solve(0, Tt);
+            p.local_solve(Tt);
             __syncthreads();
             p.finish_solve(0, Tt, xl, xr);
 #pragma unroll
@@ -425,7 +496,7 @@ line_pass2_kernel(const LinePassArgs<T> a) {
                     for (int k = 0; k < R; ++k) U[k] += A[k];
                 }
                 p.rhs(1, Tt, Tl, Tr, A);
-                p.local_solve(1, A);
+                p.local_solve(A);
                 __syncthreads();
                 p.finish_solve(1, A, xl, xr);
 #pragma unroll
@@ -441,7 +512,6 @@ line_pass2_kernel(const LinePassArgs<T> a) {
         T Bm2 = ldV(a.vin, a.vin_ld, s0 - 2), Bm1 = ldV(a.vin, a.vin_ld, s0 - 1),
           Bp = ldV(a.vin, a.vin_ld, s0 + R);
         const T Rm2 = ldR(s0 - 2), Rm1 = ldR(s0 - 1), Rp = ldR(s0 + R);
-        const bool bnd = !fast;
         const T ih8 = T(8.0 / 9.0);   // boundary rows are divided by the folded 9/8
         const T d0c[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
                           T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
@@ -591,15 +661,45 @@ line_pass2_kernel(const LinePassArgs<T> a) {
                                                  MODE != LINE_FINAL);
 }
 
-template <typename T, bool BND, bool COMP>
-hipError_t launch_part(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
+template <typename T, int METHOD, int MODE, bool COMP>
+__global__ void __launch_bounds__(K2<T>::NT)
+__attribute__((amdgpu_waves_per_eu(Cfg2<T>::WPE, Cfg2<T>::WPE)))
+line_pass2_kernel(const LinePassArgs<T> a) {
+    __shared__ T smem[Pass2<T, METHOD>::SMEM];
+    // XCD-aware tile order: consecutive blocks of one XCD take neighbouring
+    // line groups of the same window.
     const int nb = a.nlg * a.gcount;
+    const int per = (nb + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= nb) return;
+    lp2_body<T, METHOD, MODE, COMP>(a, tile, smem);
+}
+
+template <typename T, int METHOD, int MODE, bool COMP>
+__global__ void __launch_bounds__(K2<T>::NT)
+__attribute__((amdgpu_waves_per_eu(Cfg2<T>::WPE, Cfg2<T>::WPE)))
+line_pass2_group_kernel(const GroupArgs<T> ga) {
+    __shared__ T smem[Pass2<T, METHOD>::SMEM];
+    int tile;
+    const int it = group_item(ga, tile);
+    if (it < 0) return;
+    LinePassArgs<T> a = ga.items[it];
+    if (a.aFtab) a.aF = a.aFtab[*ga.tick];
+    lp2_body<T, METHOD, MODE, COMP>(a, tile, smem);
+}
+
+template <typename T, bool COMP>
+hipError_t launch_all(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st) {
+    const int nb = a ? a->nlg * a->gcount : ga->total;
     if (nb <= 0) return hipSuccess;
     dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K2<T>::NT);
-#define LP2_CASE(M, MD)                                                                  \
-    if (method == M && mode == MD) {                                                     \
-        hipLaunchKernelGGL((line_pass2_kernel<T, M, MD, BND, COMP>), grid, block, 0, st, a);   \
-        return hipGetLastError();                                                        \
+#define LP2_CASE(M, MD)                                                                                  \
+    if (method == M && mode == MD) {                                                                     \
+        if (a)                                                                                           \
+            hipLaunchKernelGGL((line_pass2_kernel<T, M, MD, COMP>), grid, block, 0, st, *a);            \
+        else                                                                                             \
+            hipLaunchKernelGGL((line_pass2_group_kernel<T, M, MD, COMP>), grid, block, 0, st, *ga);     \
+        return hipGetLastError();                                                                        \
     }
     LP2_CASE(LINE_CFD, LINE_SWEEP)
     LP2_CASE(LINE_CFD, LINE_FINAL)
@@ -611,26 +711,22 @@ hipError_t launch_part(const LinePassArgs<T>& a, int method, int mode, hipStream
     return hipErrorInvalidValue;
 }
 
-// The windows holding the physical boundary rows (first and last) run the
-// table variant; the others run the constant-coefficient variant.
-template <typename T, bool COMP>
-hipError_t launch_split(const LinePassArgs<T>& a0, int method, int mode, hipStream_t st) {
+template <typename T>
+hipError_t launch_line_pass2(const LinePassArgs<T>& a0, int method, int mode, hipStream_t st, bool comp) {
     LinePassArgs<T> a = a0;
     a.gbase = 0;
-    a.gstride = a0.nwin - 1;
-    a.gcount = a0.nwin >= 2 ? 2 : 1;
-    hipError_t e = launch_part<T, true, COMP>(a, method, mode, st);
-    if (e != hipSuccess) return e;
-    a.gbase = 1;
     a.gstride = 1;
-    a.gcount = a0.nwin - 2;
-    return launch_part<T, false, COMP>(a, method, mode, st);
+    a.gcount = a0.nwin;
+    if (!comp) return launch_all<T, false>(&a, nullptr, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_all<T, true>(&a, nullptr, method, mode, st);
+    return hipErrorInvalidValue;
 }
 
+// Items must have gbase = 0, gstride = 1, gcount = nwin.
 template <typename T>
-hipError_t launch_line_pass2(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp) {
-    if (!comp) return launch_split<T, false>(a, method, mode, st);
-    if constexpr (std::is_same<T, float>::value) return launch_split<T, true>(a, method, mode, st);
+hipError_t launch_line_group2(const GroupArgs<T>& ga, int method, int mode, hipStream_t st, bool comp) {
+    if (!comp) return launch_all<T, false>(nullptr, &ga, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_all<T, true>(nullptr, &ga, method, mode, st);
     return hipErrorInvalidValue;
 }
 
@@ -639,5 +735,7 @@ int line2_seg(int dtype) { return dtype == 0 ? K2<float>::R : K2<double>::R; }
 
 template hipError_t launch_line_pass2<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool);
 template hipError_t launch_line_pass2<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_group2<float>(const GroupArgs<float>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_group2<double>(const GroupArgs<double>&, int, int, hipStream_t, bool);
 
 }  // namespace adi

@@ -6,6 +6,23 @@
 
 namespace adi {
 
+// Item and tile of this workgroup in a grouped launch (-1: idle block).
+// Consecutive tiles go to the same XCD: block b runs on XCD b % 8.
+template <typename T>
+__device__ __forceinline__ int group_item(const GroupArgs<T>& g, int& tile) {
+    const int b = (int)blockIdx.x;
+    const int per = (g.total + 7) / 8;
+    tile = (b % 8) * per + b / 8;
+    if (tile >= g.total) return -1;
+    int lo = 0, hi = g.nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.starts[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    tile -= g.starts[lo];
+    return lo;
+}
+
 // hi + lo + inc as a new (hi, lo) pair: TwoSum of hi and the increment, its
 // rounding error folded into the low word, then renormalised.
 template <typename T>

@@ -1,0 +1,83 @@
+// Internal state of a problem and the pieces of a run, shared by the
+// single-problem entry points (adi.hip) and the batched ones (batch.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/adi.h"
+#include "line_pass.h"
+
+namespace adi {
+
+// Launch plan of the passes along one direction.
+struct Plan {
+    int n = 0, ns = 0, nlines = 0, nlg = 0, nwin = 0, S = 0, H = 0, deep = 0;
+    int ver = 1;   // 1: single-window kernel (line_pass.hip), 2: multi-window (line_pass2.hip)
+    int cfg = 0;   // tile shape of the single-window kernel
+    int seg = 0;   // slots per lane segment of the multi-window kernel
+};
+
+// One pass, ready to launch.
+template <typename T>
+struct PassDesc {
+    LinePassArgs<T> a;
+    int ver, cfg, method, mode;
+    bool comp;
+    int tiles() const { return a.nlg * a.nwin; }
+    // kernel variant: passes with equal keys can share a grouped launch
+    int key() const { return ((ver * 4 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0); }
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define HIP_TRY(expr, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return adi::hip_fail(e_, what); \
+    } while (0)
+
+}  // namespace adi
+
+struct adi_problem {
+    adi_params p{};
+    hipStream_t st = nullptr;
+    int dev = 0;
+    int nix = 0, niy = 0;
+    double a = 0.0;
+    int64_t step = 0;
+    bool bound = false;
+    void *U = nullptr, *V = nullptr, *W = nullptr;
+    int64_t ldU = 0, ldV = 0, ldW = 0;
+    bool hasK = false, hasRv = false, hasRw = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    size_t esz = 4;
+    int64_t ldx = 0, ldy = 0;
+    void *UAT = nullptr, *UC = nullptr, *VT[2] = {nullptr, nullptr}, *WSb[2] = {nullptr, nullptr};
+    void *aK = nullptr, *aKT = nullptr, *aRvT = nullptr, *aRw = nullptr, *coefX = nullptr, *coefY = nullptr;
+    void *UATlo = nullptr, *UClo = nullptr, *VTlo[2] = {nullptr, nullptr}, *WSblo[2] = {nullptr, nullptr};
+    int vcur = 0, wcur = 0;
+    adi::Plan px, py;
+};
+
+namespace adi {
+
+// A run of nsteps steps of one problem is
+//   run_begin, then for s = 0..nsteps-1 the passes run_pass(s, 0) and
+//   run_pass(s, 1), then run_end.
+// run_begin queues the set-up copies and the explicit pass of step m on st;
+// run_pass returns the pass (and advances the ping-pong buffers); its source
+// term is aF(m + s + 1), taken from aFtab[tick] when aFtab is given (grouped
+// launches) and computed on the host otherwise.
+template <typename T> int run_begin(adi_problem* pb, hipStream_t st);
+template <typename T>
+PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab);
+template <typename T> int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps);
+template <typename T> hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st);
+
+// a * s(t) / h^2 at time level m (0 without a source)
+double source_term(const adi_problem& pb, int64_t m);
+
+}  // namespace adi

@@ -186,3 +186,20 @@ def test_compensated_error_not_above_plain_fp32(method, nsteps):
     log(f"  fp32 {e[adi.FP32]:.3e}  fp32c {e[adi.FP32C]:.3e}")
     assert e[adi.FP32C] <= e[adi.FP32] * 1.05
     assert e[adi.FP32C] <= TOL32
+
+
+# Lines whose slot count sits at either side of each single-window tile shape
+# (128, 256, 512 slots) and just past the multi-window threshold; slots per
+# line are n + 1 (compact) and n + 2 (mimetic).
+_EDGES = {adi.CFD: [127, 128, 255, 256, 511, 512], adi.MFD: [126, 127, 254, 255, 510, 511]}
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
+def test_window_shape_boundaries(method, k, dtype):
+    n = _EDGES[method][k]
+    tol = TOL64 if dtype == adi.FP64 else TOL32
+    for nx, ny in ((n, 12), (12, n)):
+        errs = compare(method, dtype, nx, ny, seed=70 + k, nsteps=3, cfl=0.6)
+        assert max(errs) <= tol, (nx, ny, errs)

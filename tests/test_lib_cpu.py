@@ -92,3 +92,23 @@ def test_null_arguments():
     assert L.adi_bind(None, None, None, None, None, None, None, None, None, 0) == -1
     assert L.adi_destroy(None) == 0
     assert L.adi_status_string(-5) == b"ADI_ENOTREADY"
+
+
+def test_batch_create_validates_arguments_on_the_host():
+    L = adi.lib()
+    out = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    assert L.adi_batch_create(None, 1, None, 0, ctypes.byref(out)) == -1
+    arr = (vp * 1)(None)
+    assert L.adi_batch_create(arr, 0, None, 0, ctypes.byref(out)) == -1
+    assert b"at least one" in L.adi_last_error()
+    assert L.adi_batch_create(arr, 1, None, 4, ctypes.byref(out)) == -1
+    assert b"flags" in L.adi_last_error()
+    assert L.adi_batch_create(arr, 1, None, adi.BATCH_GRAPH, ctypes.byref(out)) == -1
+    assert b"stream" in L.adi_last_error()
+    assert L.adi_batch_create(arr, 1, None, 0, None) == -1
+    assert L.adi_batch_run(None, 1) == -1
+    assert L.adi_batch_sync(None) == -1
+    n = ctypes.c_int64()
+    assert L.adi_batch_launches(None, ctypes.byref(n)) == -1
+    assert L.adi_batch_destroy(None) == 0
