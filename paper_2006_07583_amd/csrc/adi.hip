@@ -78,8 +78,11 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
     } else {
         p.ver = 2;
         p.seg = adi::line2_seg(dtype);
+        // windows of LINE_WS slots overlapping by 2H; the first and last own
+        // LINE_WS - H central slots, the others S = LINE_WS - 2H
         p.S = adi::LINE_WS - 2 * p.H;
-        p.nwin = (p.ns + p.S - 1) / p.S;
+        const int F = adi::LINE_WS - p.H;
+        p.nwin = p.ns <= 2 * F ? 2 : 2 + (p.ns - 2 * F + p.S - 1) / p.S;
         p.deep = 0;
     }
     const int lw = p.ver == 1 ? adi::line_lanes(dtype, p.cfg) : adi::line2_lanes(dtype);
@@ -87,10 +90,6 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
     return p;
 }
 
-int window_start(const Plan& p, int g) {
-    if (p.nwin == 1) return 0;
-    return std::max(0, std::min(g * p.S - p.H, p.ns - adi::LINE_WS));
-}
 
 // No-pivot LU of the tridiagonal matrix restricted to rows [r0, r1]; rows
 // r0 > first / r1 < last are window edges inside the line: the coupling to
@@ -130,19 +129,14 @@ double coef_Pbar(int r, int which, int n) {
     return which == 1 ? 4.0 : 1.0;
 }
 
-// Factor tables of the single-window kernel: [6][WS], WS = window of the
-// plan's tile shape.
+// Factor tables of the single-window kernel (one window per line): [6][WS],
+// WS = window of the plan's tile shape.
 void build_tables(const Plan& p, std::vector<double>& out) {
     const int WS = adi::line_ws(p.cfg);
-    out.assign((size_t)p.nwin * 6 * WS, 0.0);
-    for (int g = 0; g < p.nwin; ++g) {
-        double* t = out.data() + (size_t)g * 6 * WS;
-        const int w0 = window_start(p, g);
-        const int wl = std::min(w0 + WS, p.ns) - 1;
-        factor_rows(std::max(w0, 0), std::min(wl, p.n), 0, p.n, w0, coef_P, p.n, t, t + WS, t + 2 * WS);
-        factor_rows(std::max(w0, 1), std::min(wl, p.n - 1), 1, p.n - 1, w0, coef_Pbar, p.n,
-                    t + 3 * WS, t + 4 * WS, t + 5 * WS);
-    }
+    out.assign((size_t)6 * WS, 0.0);
+    double* t = out.data();
+    factor_rows(0, p.n, 0, p.n, 0, coef_P, p.n, t, t + WS, t + 2 * WS);
+    factor_rows(1, p.n - 1, 1, p.n - 1, 0, coef_Pbar, p.n, t + 3 * WS, t + 4 * WS, t + 5 * WS);
 }
 
 double ricker(const adi_params& p, double t) {

@@ -356,8 +356,10 @@ __device__ __forceinline__ void lp2_body(const LinePassArgs<T>& a, int tile, T* 
     const int lane = tid & 63, wave = tid >> 6;
     const int lq = lane % LW;
     const int seg = wave * SPW + lane / LW;
-    const int c0 = g * a.S;
-    const int c1 = min(c0 + a.S, a.ns);
+    // central slots written by window g: the end windows need no margin on
+    // their physical side, so the first one owns WS - H slots
+    const int c0 = g == 0 ? 0 : (WS - a.H) + (g - 1) * a.S;
+    const int c1 = g == a.nwin - 1 ? a.ns : (WS - a.H) + g * a.S;
     const int w0 = max(0, min(c0 - a.H, a.ns - WS));
     const int s0 = w0 + seg * R;
     const int q = lg * LW + lq;
@@ -392,13 +394,16 @@ __device__ __forceinline__ void lp2_body(const LinePassArgs<T>& a, int tile, T* 
     };
     // scale folded into the material arrays
     const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
+    // raw material values; the scale is applied after every load has been
+    // issued (arithmetic on a loaded value inside its predicated branch would
+    // make each load wait for all earlier ones)
     auto ldK = [&](int s) -> T {
         if (!(qok && s >= 1 && s <= uhi)) return T(0);
-        return sc * (a.ak ? a.ak[(int64_t)(s - 1) * a.ak_ld + q] : a.ak0);
+        return a.ak ? a.ak[(int64_t)(s - 1) * a.ak_ld + q] : a.ak0;
     };
     auto ldR = [&](int s) -> T {
         if (!(qok && s >= 0 && s <= n)) return T(0);
-        return sc * (a.ar ? a.ar[(int64_t)s * a.ar_ld + q] : a.ar0);
+        return a.ar ? a.ar[(int64_t)s * a.ar_ld + q] : a.ar0;
     };
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -412,9 +417,15 @@ __device__ __forceinline__ void lp2_body(const LinePassArgs<T>& a, int tile, T* 
     if (METHOD == LINE_CFD) {
         // halo inputs at slots s0-1 and s0+R
         T Al = ldU(a.uin, a.uin_ld, s0 - 1), Ar = ldU(a.uin, a.uin_ld, s0 + R);
-        const T Kl = ldK(s0 - 1), Kr = ldK(s0 + R);
+        T Kl = ldK(s0 - 1), Kr = ldK(s0 + R);
         T Bl = ldV(a.vin, a.vin_ld, s0 - 1), Br = ldV(a.vin, a.vin_ld, s0 + R);
-        const T Rl = ldR(s0 - 1), Rr = ldR(s0 + R);
+        T Rl = ldR(s0 - 1), Rr = ldR(s0 + R);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            KK[k] *= sc;
+            RR[k] *= sc;
+        }
+        Kl *= sc; Kr *= sc; Rl *= sc; Rr *= sc;
         __syncthreads();   // padding zeros visible
         T xl, xr;
         if (MODE == LINE_EXPLICIT || COMP) {
@@ -511,7 +522,13 @@ __device__ __forceinline__ void lp2_body(const LinePassArgs<T>& a, int tile, T* 
         // ---- mimetic ----
         T Bm2 = ldV(a.vin, a.vin_ld, s0 - 2), Bm1 = ldV(a.vin, a.vin_ld, s0 - 1),
           Bp = ldV(a.vin, a.vin_ld, s0 + R);
-        const T Rm2 = ldR(s0 - 2), Rm1 = ldR(s0 - 1), Rp = ldR(s0 + R);
+        T Rm2 = ldR(s0 - 2), Rm1 = ldR(s0 - 1), Rp = ldR(s0 + R);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            KK[k] *= sc;
+            RR[k] *= sc;
+        }
+        Rm2 *= sc; Rm1 *= sc; Rp *= sc;
         const T ih8 = T(8.0 / 9.0);   // boundary rows are divided by the folded 9/8
         const T d0c[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
                           T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
