@@ -76,7 +76,10 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.S = p.ns;
         p.deep = 1;
     } else {
-        p.ver = 2;
+        // multi-window: the wave-per-line kernel for the compact scheme (its
+        // barrier-free solves pay for the staged loads); the segment kernel for
+        // the mimetic scheme and the compensated mode
+        p.ver = (dtype == ADI_FP32C || method == ADI_MFD) ? 2 : 3;
         p.seg = adi::line2_seg(dtype);
         // windows of LINE_WS slots overlapping by 2H; the first and last own
         // LINE_WS - H central slots, the others S = LINE_WS - 2H
@@ -85,7 +88,8 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.nwin = p.ns <= 2 * F ? 2 : 2 + (p.ns - 2 * F + p.S - 1) / p.S;
         p.deep = 0;
     }
-    const int lw = p.ver == 1 ? adi::line_lanes(dtype, p.cfg) : adi::line2_lanes(dtype);
+    const int lw = p.ver == 1 ? adi::line_lanes(dtype, p.cfg)
+                              : (p.ver == 2 ? adi::line2_lanes(dtype) : adi::line3_lanes(dtype));
     p.nlg = (nlines + lw - 1) / lw;
     return p;
 }
@@ -334,8 +338,9 @@ double source_term(const adi_problem& pb, int64_t m) {
 
 template <typename T>
 hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st) {
-    return d.ver == 1 ? launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg)
-                      : launch_line_pass2<T>(d.a, d.method, d.mode, st, d.comp);
+    if (d.ver == 1) return launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg);
+    if (d.ver == 2) return launch_line_pass2<T>(d.a, d.method, d.mode, st, d.comp);
+    return launch_line_pass3<T>(d.a, d.method, d.mode, st);
 }
 
 template <typename T>

@@ -174,8 +174,9 @@ hipError_t launch_group(adi_batch* b, TypedPart<T>& part, const Group& g) {
     ga.nitems = g.count;
     ga.total = g.total;
     ++b->launches;
-    return g.ver == 1 ? adi::launch_line_group<T>(ga, g.cfg, g.method, g.mode, b->st, g.comp)
-                      : adi::launch_line_group2<T>(ga, g.method, g.mode, b->st, g.comp);
+    if (g.ver == 1) return adi::launch_line_group<T>(ga, g.cfg, g.method, g.mode, b->st, g.comp);
+    if (g.ver == 2) return adi::launch_line_group2<T>(ga, g.method, g.mode, b->st, g.comp);
+    return adi::launch_line_group3<T>(ga, g.method, g.mode, b->st);
 }
 
 int launch_step(adi_batch* b, int k) {

@@ -1,0 +1,630 @@
+// Multi-window line pass with one grid line per half wave (lines longer than
+// one window; FP32 and FP64).
+//
+// Same arithmetic as the other line-pass kernels: one launch performs the
+// fixed-point sweeps of a Peaceman-Rachford stage along every line of one
+// direction, fused with the explicit half of the following stage
+// (Algorithms 1-4).  The difference is where a line lives:
+//
+//  * A line's window of 512 slots is held by 32 lanes of one wave, R = 16
+//    consecutive slots per lane, two lines per wave.  Everything the
+//    segmented solves and stencils exchange between neighbouring segments
+//    moves between neighbouring lanes with DPP wave shifts: the sweep loop
+//    has no workgroup barrier and no LDS traffic, and the waves of a
+//    workgroup progress independently.
+//  * Global memory is read and written through an LDS tile per array, so
+//    that every access runs along the lines (the fast index of all the
+//    layouts): LW lines per workgroup, one contiguous run per slot.
+//  * Compact scheme: scaled unknowns, zero-carry segment solves, one
+//    carry combination per solve (constants of the interior factors), and a
+//    low-rank correction in the windows holding the first or last slot of
+//    the line that turns the constant-factor matrix into P4 / Pbar4; the
+//    correction values are broadcast from the lane holding the boundary
+//    rows with readlane.
+//  * Mimetic scheme: the 4-tap stencils need the last / first 3 values of
+//    the neighbouring lanes: 6 lane shifts per velocity evaluation.
+//
+// Lanes at the window edges see zeros beyond the window; the windows overlap
+// by H slots on each side and only the central slots are written (the
+// margins H are the ones the other kernels use).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "line_consts.h"
+#include "line_pass.h"
+#include "pass_common.h"
+
+namespace adi {
+
+template <typename T> struct Cfg3;
+// waves per workgroup, lines per wave, slots per lane, carry reach (segments), waves per SIMD
+template <> struct Cfg3<float> { static constexpr int NWV = 8, LPW = 2, R = 16, TS = 1, WPE = 4; };
+template <> struct Cfg3<double> { static constexpr int NWV = 4, LPW = 2, R = 16, TS = 2, WPE = 2; };
+
+template <typename T> struct K3 {
+    static constexpr int NWV = Cfg3<T>::NWV, LPW = Cfg3<T>::LPW, R = Cfg3<T>::R, TS = Cfg3<T>::TS;
+    static constexpr int LPL = 64 / LPW;          // lanes per line
+    static constexpr int WS = LPL * R;             // slots per window
+    static constexpr int LW = NWV * LPW;           // lines per workgroup
+    static constexpr int NT = NWV * 64;
+    static constexpr int TP = WS + 4;              // LDS tile row pitch (elements)
+    static constexpr int TILE = LW * TP;
+    static constexpr int SPJ = NT / LW;            // slots covered by one staging step
+    static constexpr int EPT = WS / SPJ;           // staging steps per array
+};
+static_assert(K3<float>::WS == LINE_WS && K3<double>::WS == LINE_WS, "window size");
+static_assert(K3<float>::EPT * K3<float>::SPJ == K3<float>::WS, "staging");
+static_assert(K3<double>::EPT * K3<double>::SPJ == K3<double>::WS, "staging");
+
+// Lane shifts across the whole wave: lane l receives lane l - 1 (shr) or
+// l + 1 (shl); lanes without a source receive 0.
+__device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float wshr(float x) { return __int_as_float(dpp_shr1(__float_as_int(x))); }
+__device__ __forceinline__ float wshl(float x) { return __int_as_float(dpp_shl1(__float_as_int(x))); }
+__device__ __forceinline__ double wshr(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_shr1((int)(b & 0xffffffffLL)), hi = dpp_shr1((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wshl(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_shl1((int)(b & 0xffffffffLL)), hi = dpp_shl1((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// value of lane `src` (uniform) of the wave
+__device__ __forceinline__ float rlane(float x, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ __forceinline__ double rlane(double x, int src) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr double pow_na(int e) {   // (-alpha)^e
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= -kAlpha;
+    return r;
+}
+
+template <typename T, int METHOD> struct Line3 {
+    using C = K3<T>;
+    static constexpr int R = C::R, LPL = C::LPL, TS = C::TS;
+    int i, h, s0, n;
+    bool first, last, bnd, lwin, rwin;
+
+    // neighbour values within the line (0 beyond the window)
+    __device__ __forceinline__ T prev(T x) const {
+        const T y = wshr(x);
+        return first ? T(0) : y;
+    }
+    __device__ __forceinline__ T next(T x) const {
+        const T y = wshl(x);
+        return last ? T(0) : y;
+    }
+    // value of lane-in-line `src` of this line
+    __device__ __forceinline__ T from_lane(T x, int src) const {
+        const T v0 = rlane(x, src), v1 = rlane(x, LPL + src);
+        return h ? v1 : v0;
+    }
+
+    // ================= compact scheme =================
+    // Scaled right-hand side of the derivative of kind `kind` (0: Q4 on
+    // pressure, 1: Qbar4 on velocity) into o; closures of Appendix A on the
+    // boundary rows, zero on the trivial rows added to Pbar.
+    __device__ __forceinline__ void rhs(int kind, const T (&f)[R], T fl, T fr, T (&o)[R]) const {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T fp = k + 1 < R ? f[k + 1] : fr;
+            const T fm = k > 0 ? f[k - 1] : fl;
+            o[k] = fp - fm;
+        }
+        if (bnd) {
+            const T third = T(1.0 / 3.0);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int s = s0 + k;
+                if (kind == 0) {
+                    if (s == 0 && k + 3 < R)
+                        o[k] = third * (T(-17) * f[k] + T(9) * f[k + 1] + T(9) * f[k + 2] - f[k + 3]);
+                    if (s == n && k >= 3)
+                        o[k] = third * (f[k - 3] - T(9) * f[k - 2] - T(9) * f[k - 1] + T(17) * f[k]);
+                } else {
+                    if (s == 0 || s == n) o[k] = T(0);
+                    if (s == 1 && k >= 1 && k + 2 < R)
+                        o[k] = third * (-f[k - 1] - T(9) * f[k] + T(9) * f[k + 1] + f[k + 2]);
+                    if (s == n - 1 && k >= 2 && k + 1 < R)
+                        o[k] = third * (-f[k - 2] - T(9) * f[k - 1] + T(9) * f[k] + f[k + 1]);
+                }
+            }
+        }
+    }
+
+    // Tridiagonal solve of the right-hand side in o (in place), and the
+    // solution's values on the neighbouring lanes' edge slots: xl at slot
+    // s0 - 1, xr at slot s0 + R.
+    __device__ __forceinline__ void solve(int kind, T (&o)[R], T& xl, T& xr) const {
+        const T al = T(kAlpha);
+#pragma unroll
+        for (int k = 1; k < R; ++k) o[k] = fma(-al, o[k - 1], o[k]);
+        const T yend = o[R - 1];
+#pragma unroll
+        for (int k = R - 2; k >= 0; --k) o[k] = fma(-al, o[k + 1], o[k]);
+        constexpr Resp<R> rs{};
+        const T G = T(rs.G);
+        const T rawf = o[0], rawl = o[R - 1];
+        const T y1 = prev(yend);
+        T Y = y1, Ym = T(0);
+        if (TS > 1) {
+            Ym = prev(y1);                       // forward carry into the previous lane
+            Y = fma(G, Ym, Y);
+        }
+        const T Yv = fma(G, Y, yend);            // forward carry into the next lane
+        const T nf = next(rawf);
+        T X = last ? T(0) : fma(T(rs.a[0]), Yv, nf);
+        if (TS > 1) {
+            const T Yv2 = fma(G, Yv, next(yend));
+            const T nf2 = next(nf);
+            X = i < LPL - 2 ? fma(T(rs.b[0]), fma(T(rs.a[0]), Yv2, nf2), X) : X;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) o[k] = fma(T(rs.a[k]), Y, fma(T(rs.b[k]), X, o[k]));
+        const T pl = prev(rawl);
+        xl = first ? T(0) : fma(T(rs.b[R - 1]), o[0], fma(T(rs.a[R - 1]), Ym, pl));
+        xr = X;
+        if (lwin || rwin) correct(kind, o, xl, xr);
+    }
+
+    // Boundary-row correction (Sherman-Morrison-Woodbury) in the windows
+    // holding the first or last slot of the line.  The correction is
+    // geometric with ratio -alpha away from the boundary row:
+    // w(0) = W0, w(d) = W1 (-alpha)^(d-1).
+    __device__ void correct(int kind, T (&o)[R], T& xl, T& xr) const {
+        constexpr BndResp kb{};
+        constexpr double de = 3.7320508075688772935;
+        constexpr int NZ = BndResp::NZ;
+        const T na = T(-kAlpha);
+        if (lwin) {
+            // computed by every lane, meaningful in lane 0 (slots 0, 1, 2)
+            T W0, W1;
+            if (kind == 0) {
+                const T c = T(kb.cl0) * fma(T(6.0 - de), o[0], T(17) * o[1]);
+                W0 = T(kb.zl0[0]) * c;
+                W1 = T(kb.zl0[1]) * c;
+            } else {
+                const T e0 = fma(T(1.0 - de), o[0], -o[1]);
+                const T e1 = fma(T(2), o[1], fma(T(5), o[2], -o[0]));
+                const T c0 = fma(T(kb.cl1[0]), e0, T(kb.cl1[1]) * e1);
+                const T c1 = fma(T(kb.cl1[2]), e0, T(kb.cl1[3]) * e1);
+                W0 = fma(T(kb.zl0[0]), c0, T(kb.zl1[0]) * c1);
+                W1 = fma(T(kb.zl0[1]), c0, T(kb.zl1[1]) * c1);
+            }
+            W0 = from_lane(W0, 0);
+            W1 = from_lane(W1, 0);
+            if (s0 - 1 < NZ) {
+                // lane i holds slots i R .. i R + R - 1
+                T w;
+                if (i == 0) w = W0;
+                else if (i == 1) w = W1 * T(pow_na(R - 1));
+                else if (i == 2) w = W1 * T(pow_na(2 * R - 1));
+                else w = W1 * T(pow_na(3 * R - 1));
+                // correction at slot s0 - 1 (last slot of the previous lane)
+                const T wl = W1 * (i == 1 ? T(pow_na(R - 2)) : (i == 2 ? T(pow_na(2 * R - 2)) : T(pow_na(3 * R - 2))));
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    o[k] -= w;
+                    w = (i == 0 && k == 0) ? W1 : w * na;
+                }
+                if (i > 0) xl -= wl;
+                xr -= w;
+            }
+        }
+        if (rwin) {
+            // slot n is the last slot of the window: lane LPL - 1, position R - 1
+            T V0, V1;
+            if (kind == 0) {
+                const T c = T(kb.cr0) * fma(T(17), o[R - 2], T(2) * o[R - 1]);
+                V0 = T(kb.zr0[0]) * c;
+                V1 = T(kb.zr0[1]) * c;
+            } else {
+                const T e0 = fma(T(5), o[R - 3], fma(T(2), o[R - 2], -o[R - 1]));
+                const T e1 = fma(T(-3), o[R - 1], -o[R - 2]);
+                const T c0 = fma(T(kb.cr1[0]), e0, T(kb.cr1[1]) * e1);
+                const T c1 = fma(T(kb.cr1[2]), e0, T(kb.cr1[3]) * e1);
+                V0 = fma(T(kb.zr1[0]), c0, T(kb.zr0[0]) * c1);
+                V1 = fma(T(kb.zr1[1]), c0, T(kb.zr0[1]) * c1);
+            }
+            V0 = from_lane(V0, LPL - 1);
+            V1 = from_lane(V1, LPL - 1);
+            const int j = LPL - 1 - i;            // lanes from the right end
+            if (n - (s0 + R) < NZ) {
+                // distance of the lane's last slot from slot n: j R
+                T w;
+                if (j == 0) w = V0;
+                else if (j == 1) w = V1 * T(pow_na(R - 1));
+                else if (j == 2) w = V1 * T(pow_na(2 * R - 1));
+                else w = V1 * T(pow_na(3 * R - 1));
+                // correction at slot s0 + R (first slot of the next lane)
+                const T wr = V1 * (j == 1 ? T(pow_na(R - 2)) : (j == 2 ? T(pow_na(2 * R - 2)) : T(pow_na(3 * R - 2))));
+#pragma unroll
+                for (int k = R - 1; k >= 0; --k) {
+                    o[k] -= w;
+                    w = (j == 0 && k == R - 1) ? V1 : w * na;
+                }
+                xl -= w;
+                if (j > 0) xr -= wr;
+            }
+        }
+    }
+};
+
+// One workgroup's share of a pass: LW lines (line group tile % nlg) over
+// window tile / nlg.
+template <typename T, int METHOD, int MODE>
+__device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
+    using C = K3<T>;
+    constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW, NT = C::NT, TP = C::TP, SPJ = C::SPJ,
+                  EPT = C::EPT;
+    const int lg = tile % a.nlg, g = tile / a.nlg;
+    const int n = a.n, ns = a.ns;
+    const int uhi = METHOD == LINE_CFD ? n - 1 : n;
+    // central slots written by window g (the end windows need no margin on
+    // their physical side)
+    const int c0 = g == 0 ? 0 : (WS - a.H) + (g - 1) * a.S;
+    const int c1 = g == a.nwin - 1 ? ns : (WS - a.H) + g * a.S;
+    const int w0 = max(0, min(c0 - a.H, ns - WS));
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    Line3<T, METHOD> L;
+    L.i = lane % LPL;
+    L.h = lane / LPL;
+    L.n = n;
+    L.s0 = w0 + L.i * R;
+    L.first = L.i == 0;
+    L.last = L.i == LPL - 1;
+    L.bnd = L.s0 <= 1 || L.s0 + R - 1 >= n - 1;
+    L.lwin = w0 == 0;
+    L.rwin = w0 + WS >= ns;
+    const int s0 = L.s0;
+    const int ln = wave * C::LPW + L.h;          // line of this lane within the workgroup
+    const int q = lg * LW + ln;
+    const bool qok = q < a.nlines;
+
+    // staging map: thread -> line st_ln, slots st_sl + j SPJ
+    const int st_ln = tid % LW, st_sl = tid / LW;
+    const int st_q = lg * LW + st_ln;
+    const bool st_qok = st_q < a.nlines;
+    const int st_qc = st_qok ? st_q : a.nlines - 1;
+
+    // ---- loads: every global read issued first, then one LDS round per array ----
+    auto fetch = [&](const T* base, int64_t ld, bool ptype, T (&v)[EPT]) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int s = w0 + st_sl + j * SPJ;
+            const bool ok = st_qok && (ptype ? (s >= 1 && s <= uhi) : (s <= n));
+            const int row = ok ? (ptype ? s - 1 : s) : 0;
+            const T x = base[(int64_t)row * ld + st_qc];
+            v[j] = ok ? x : T(0);
+        }
+    };
+    auto spread = [&](const T (&v)[EPT], T (&dst)[R]) {
+        __syncthreads();   // earlier readers of the tile are done
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) smem[st_ln * TP + st_sl + j * SPJ] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k) dst[k] = smem[ln * TP + L.i * R + k];
+    };
+    T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
+    {
+        T va[EPT], vb[EPT], vk[EPT], vr[EPT];
+        fetch(a.uin, a.uin_ld, true, va);
+        fetch(a.vin, a.vin_ld, false, vb);
+        if (a.ak) fetch(a.ak, a.ak_ld, true, vk);
+        if (a.ar) fetch(a.ar, a.ar_ld, false, vr);
+        spread(va, A);
+        spread(vb, B);
+        if (a.ak) spread(vk, KK);
+        if (a.ar) spread(vr, RR);
+    }
+    // scale folded into the material values (compact: 3 alpha / h; mimetic: 9 / (8 h))
+    const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int s = s0 + k;
+        const bool uok = qok && s >= 1 && s <= uhi, vok = qok && s <= n;
+        KK[k] = uok ? sc * (a.ak ? KK[k] : a.ak0) : T(0);
+        RR[k] = vok ? sc * (a.ar ? RR[k] : a.ar0) : T(0);
+    }
+
+    if (METHOD == LINE_CFD) {
+        // neighbours' edge values of the inputs
+        T Al = L.prev(A[R - 1]), Ar = L.next(A[0]);
+        const T Kl = L.prev(KK[R - 1]), Kr = L.next(KK[0]);
+        const T Bl = L.prev(B[R - 1]), Br = L.next(B[0]);
+        const T Rl = L.prev(RR[R - 1]), Rr = L.next(RR[0]);
+        T xl, xr;
+        if (MODE == LINE_EXPLICIT) {
+            L.rhs(0, A, Al, Ar, Tt);
+            L.solve(0, Tt, xl, xr);
+            L.rhs(1, B, Bl, Br, U);
+            L.solve(1, U, xl, xr);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                Tt[k] = fma(-RR[k], Tt[k], B[k]);     // W* = B - aR G(A)
+                U[k] = fma(-KK[k], U[k], A[k]);       // A - aK D(B)
+            }
+        } else {
+            // u_1 = A - aK D(B)
+            L.rhs(1, B, Bl, Br, U);
+            L.solve(1, U, xl, xr);
+#pragma unroll
+            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            T Ul = fma(-Kl, xl, Al), Ur = fma(-Kr, xr, Ar);
+            T Tl, Tr;
+            for (int it = 1; it < a.sweeps; ++it) {
+                L.rhs(0, U, Ul, Ur, Tt);
+                L.solve(0, Tt, xl, xr);
+#pragma unroll
+                for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
+                Tl = fma(-Rl, xl, Bl);
+                Tr = fma(-Rr, xr, Br);
+                L.rhs(1, Tt, Tl, Tr, U);
+                L.solve(1, U, xl, xr);
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                Ul = fma(-Kl, xl, Al);
+                Ur = fma(-Kr, xr, Ar);
+            }
+            L.rhs(0, U, Ul, Ur, Tt);
+            L.solve(0, Tt, xl, xr);
+#pragma unroll
+            for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);       // v_K
+            if (MODE == LINE_SWEEP) {
+                Tl = fma(-Rl, xl, Bl);
+                Tr = fma(-Rr, xr, Br);
+                L.rhs(1, Tt, Tl, Tr, A);
+                L.solve(1, A, xl, xr);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T vk = Tt[k];
+                    Tt[k] = vk + (vk - B[k]);                                   // 2 v_K - B
+                    U[k] = fma(-KK[k], A[k], U[k]);                             // u_K - aK D(v_K)
+                }
+            }
+        }
+    } else {
+        // ---- mimetic ----
+        const T Bm2 = L.prev(B[R - 2]), Bm1 = L.prev(B[R - 1]), Bp = L.next(B[0]);
+        const T Rm2 = L.prev(RR[R - 2]), Rm1 = L.prev(RR[R - 1]), Rp = L.next(RR[0]);
+        const T ih8 = T(8.0 / 9.0);   // boundary rows are divided by the folded 9/8
+        const T d0c[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
+                          T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
+        const T g0c[6] = {T(-47888.0 / 14245.0), T(1790.0 / 407.0), T(-14545.0 / 9768.0),
+                          T(8997.0 / 16280.0), T(-2335.0 / 22792.0), T(25.0 / 9768.0)};
+        const T g1c[5] = {T(16.0 / 105.0), T(-31.0 / 24.0), T(29.0 / 24.0), T(-3.0 / 40.0),
+                          T(1.0 / 168.0)};
+        const bool bnd = L.bnd;
+        // D'(v) on own slots; v given on positions -2..R
+        auto applyD = [&](const T (&v)[R], T vm2, T vm1, T vp, T (&o)[R]) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T a2 = k >= 2 ? v[k - 2] : (k == 1 ? vm1 : vm2);
+                const T a1 = k >= 1 ? v[k - 1] : vm1;
+                const T a3 = k + 1 < R ? v[k + 1] : vp;
+                o[k] = md(a2, a1, v[k], a3);
+            }
+            if (bnd) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 1 && k >= 1 && k + 4 < R) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[k - 1 + c], acc);
+                        o[k] = acc * ih8;
+                    }
+                    if (s == n && k >= 5) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[k - c], acc);
+                        o[k] = -acc * ih8;
+                    }
+                }
+            }
+        };
+        // G'(u) on own slots, u given on positions -3..R+2
+        auto applyG = [&](const T (&u)[R], const T (&ul)[3], const T (&ur)[3], T (&o)[R]) {
+            auto U_ = [&](int p) -> T { return p < 0 ? ul[3 + p] : (p < R ? u[p] : ur[p - R]); };
+#pragma unroll
+            for (int k = 0; k < R; ++k) o[k] = mg(U_(k - 1), U_(k), U_(k + 1), U_(k + 2));
+            if (bnd) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int s = s0 + k;
+                    if (s == 0 && k + 5 < R) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc = fma(g0c[c], u[k + c], acc);
+                        o[k] = acc * ih8;
+                    }
+                    if (s == 1 && k >= 1 && k + 3 < R) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) acc = fma(g1c[c], u[k - 1 + c], acc);
+                        o[k] = acc * ih8;
+                    }
+                    if (s == n - 1 && k >= 2 && k + 2 < R) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) acc = fma(g1c[c], u[k + 2 - c], acc);
+                        o[k] = -acc * ih8;
+                    }
+                    if (s == n && k >= 4 && k + 1 < R) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc = fma(g0c[c], u[k + 1 - c], acc);
+                        o[k] = -acc * ih8;
+                    }
+                }
+            }
+        };
+        auto halo_u = [&](const T (&u)[R], T (&ul)[3], T (&ur)[3]) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                ul[j] = L.prev(u[R - 3 + j]);
+                ur[j] = L.next(u[j]);
+            }
+        };
+        // velocity on own slots and on -2, -1, R
+        auto velocity = [&](const T (&u)[R], T (&o)[R], T& om2, T& om1, T& op) {
+            T ul[3], ur[3];
+            halo_u(u, ul, ur);
+            applyG(u, ul, ur, o);
+#pragma unroll
+            for (int k = 0; k < R; ++k) o[k] = fma(-RR[k], o[k], B[k]);
+            om2 = fma(-Rm2, mg(ul[0], ul[1], ul[2], u[0]), Bm2);
+            om1 = fma(-Rm1, mg(ul[1], ul[2], u[0], u[1]), Bm1);
+            op = fma(-Rp, mg(u[R - 1], ur[0], ur[1], ur[2]), Bp);
+        };
+        if (MODE == LINE_EXPLICIT) {
+            T ul[3], ur[3];
+            halo_u(A, ul, ur);
+            applyG(A, ul, ur, Tt);
+            applyD(B, Bm2, Bm1, Bp, U);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                Tt[k] = fma(-RR[k], Tt[k], B[k]);
+                U[k] = fma(-KK[k], U[k], A[k]);
+            }
+        } else {
+            T Tm2, Tm1, Tp;
+            applyD(B, Bm2, Bm1, Bp, U);
+#pragma unroll
+            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            for (int it = 1; it < a.sweeps; ++it) {
+                velocity(U, Tt, Tm2, Tm1, Tp);
+                applyD(Tt, Tm2, Tm1, Tp, U);
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            }
+            velocity(U, Tt, Tm2, Tm1, Tp);                                   // v_K
+            if (MODE == LINE_SWEEP) {
+                applyD(Tt, Tm2, Tm1, Tp, A);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T vk = Tt[k];
+                    Tt[k] = vk + (vk - B[k]);
+                    U[k] = fma(-KK[k], A[k], U[k]);
+                }
+            }
+        }
+    }
+
+    // ---- stores through the LDS tile: velocity, then pressure ----
+    if (MODE != LINE_FINAL) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (q == a.src_q && s0 + k == a.src_s) U[k] += a.aF;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) smem[ln * TP + L.i * R + k] = Tt[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int sl = st_sl + j * SPJ, s = w0 + sl;
+        if (st_qok && s >= c0 && s < c1 && s <= n) a.vout[(int64_t)s * a.vout_ld + st_q] = smem[st_ln * TP + sl];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) smem[ln * TP + L.i * R + k] = U[k];
+    __syncthreads();
+    const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
+    if (a.utrans) {
+        // uout[q * ld + (s - 1)]: consecutive threads along the slots of a line
+        const int nv = hi - lo + 1;
+        for (int idx = tid; idx < LW * nv; idx += NT) {
+            const int l2 = idx / nv, jj = idx - l2 * nv;
+            const int qq = lg * LW + l2;
+            if (qq < a.nlines) a.uout[(int64_t)qq * a.uout_ld + (lo + jj - 1)] = smem[l2 * TP + (lo - w0) + jj];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int sl = st_sl + j * SPJ, s = w0 + sl;
+            if (st_qok && s >= lo && s <= hi) a.uout[(int64_t)(s - 1) * a.uout_ld + st_q] = smem[st_ln * TP + sl];
+        }
+    }
+}
+
+template <typename T, int METHOD, int MODE>
+__global__ void __launch_bounds__(K3<T>::NT)
+__attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
+line_pass3_kernel(const LinePassArgs<T> a) {
+    __shared__ __align__(16) T smem[K3<T>::TILE];
+    const int nb = a.nlg * a.nwin;
+    const int per = (nb + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= nb) return;
+    lp3_body<T, METHOD, MODE>(a, tile, smem);
+}
+
+template <typename T, int METHOD, int MODE>
+__global__ void __launch_bounds__(K3<T>::NT)
+__attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
+line_pass3_group_kernel(const GroupArgs<T> ga) {
+    __shared__ __align__(16) T smem[K3<T>::TILE];
+    int tile;
+    const int it = group_item(ga, tile);
+    if (it < 0) return;
+    LinePassArgs<T> a = ga.items[it];
+    if (a.aFtab) a.aF = a.aFtab[*ga.tick];
+    lp3_body<T, METHOD, MODE>(a, tile, smem);
+}
+
+template <typename T>
+hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st) {
+    const int nb = a ? a->nlg * a->nwin : ga->total;
+    if (nb <= 0) return hipSuccess;
+    dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
+#define LP3_CASE(M, MD)                                                                                  \
+    if (method == M && mode == MD) {                                                                     \
+        if (a)                                                                                           \
+            hipLaunchKernelGGL((line_pass3_kernel<T, M, MD>), grid, block, 0, st, *a);                  \
+        else                                                                                             \
+            hipLaunchKernelGGL((line_pass3_group_kernel<T, M, MD>), grid, block, 0, st, *ga);           \
+        return hipGetLastError();                                                                        \
+    }
+    LP3_CASE(LINE_CFD, LINE_SWEEP)
+    LP3_CASE(LINE_CFD, LINE_FINAL)
+    LP3_CASE(LINE_CFD, LINE_EXPLICIT)
+    LP3_CASE(LINE_MFD, LINE_SWEEP)
+    LP3_CASE(LINE_MFD, LINE_FINAL)
+    LP3_CASE(LINE_MFD, LINE_EXPLICIT)
+#undef LP3_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
+    return launch3<T>(&a, nullptr, method, mode, st);
+}
+
+template <typename T>
+hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipStream_t st) {
+    return launch3<T>(nullptr, &ga, method, mode, st);
+}
+
+int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW; }
+
+template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_line_group3<float>(const GroupArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_line_group3<double>(const GroupArgs<double>&, int, int, hipStream_t);
+
+}  // namespace adi

@@ -12,7 +12,8 @@ namespace adi {
 // Launch plan of the passes along one direction.
 struct Plan {
     int n = 0, ns = 0, nlines = 0, nlg = 0, nwin = 0, S = 0, H = 0, deep = 0;
-    int ver = 1;   // 1: single-window kernel (line_pass.hip), 2: multi-window (line_pass2.hip)
+    int ver = 1;   // 1: single-window kernel (line_pass.hip); multi-window: 2 (line_pass2.hip,
+                   // compensated mode) or 3 (line_pass3.hip)
     int cfg = 0;   // tile shape of the single-window kernel
     int seg = 0;   // slots per lane segment of the multi-window kernel
 };
