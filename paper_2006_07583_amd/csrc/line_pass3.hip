@@ -49,14 +49,23 @@ template <typename T> struct K3 {
     static constexpr int WS = LPL * R;             // slots per window
     static constexpr int LW = NWV * LPW;           // lines per workgroup
     static constexpr int NT = NWV * 64;
-    static constexpr int TP = WS + 4;              // LDS tile row pitch (elements)
+    // LDS tile row pitch: rows stay 16-byte aligned so that a lane moves its
+    // segment with 128-bit LDS accesses
+    static constexpr int TP = WS + 4;
     static constexpr int TILE = LW * TP;
+    static constexpr int TPL = NT / LW;            // threads per line in the transposed store
     static constexpr int SPJ = NT / LW;            // slots covered by one staging step
     static constexpr int EPT = WS / SPJ;           // staging steps per array
 };
 static_assert(K3<float>::WS == LINE_WS && K3<double>::WS == LINE_WS, "window size");
 static_assert(K3<float>::EPT * K3<float>::SPJ == K3<float>::WS, "staging");
 static_assert(K3<double>::EPT * K3<double>::SPJ == K3<double>::WS, "staging");
+
+// element (line, slot) of the LDS tile
+template <typename T>
+__device__ __forceinline__ int tix(int line, int slot) {
+    return line * K3<T>::TP + slot;
+}
 
 // Lane shifts across the whole wave: lane l receives lane l - 1 (shr) or
 // l + 1 (shl); lanes without a source receive 0.
@@ -267,8 +276,7 @@ template <typename T, int METHOD> struct Line3 {
 template <typename T, int METHOD, int MODE>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
     using C = K3<T>;
-    constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW, NT = C::NT, TP = C::TP, SPJ = C::SPJ,
-                  EPT = C::EPT;
+    constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW, SPJ = C::SPJ, EPT = C::EPT;
     const int lg = tile % a.nlg, g = tile / a.nlg;
     const int n = a.n, ns = a.ns;
     const int uhi = METHOD == LINE_CFD ? n - 1 : n;
@@ -301,7 +309,17 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     const int st_qc = st_qok ? st_q : a.nlines - 1;
 
     // ---- loads: every global read issued first, then one LDS round per array ----
+    // Blocks away from the line ends and with a full line group read every
+    // row unconditionally (rows w0 - 1 .. w0 + WS - 1 all exist there).
+    const bool inner = !L.lwin && !L.rwin && (lg + 1) * LW <= a.nlines;
     auto fetch = [&](const T* base, int64_t ld, bool ptype, T (&v)[EPT]) {
+        if (inner) {
+            const T* p = base + (int64_t)(w0 + st_sl - (ptype ? 1 : 0)) * ld + st_q;
+            const int64_t step = (int64_t)SPJ * ld;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) v[j] = p[j * step];
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int s = w0 + st_sl + j * SPJ;
@@ -314,10 +332,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     auto spread = [&](const T (&v)[EPT], T (&dst)[R]) {
         __syncthreads();   // earlier readers of the tile are done
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) smem[st_ln * TP + st_sl + j * SPJ] = v[j];
+        for (int j = 0; j < EPT; ++j) smem[tix<T>(st_ln, st_sl + j * SPJ)] = v[j];
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < R; ++k) dst[k] = smem[ln * TP + L.i * R + k];
+        for (int k = 0; k < R; ++k) dst[k] = smem[tix<T>(ln, L.i * R + k)];
     };
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
     {
@@ -533,31 +551,38 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < R; ++k) smem[ln * TP + L.i * R + k] = Tt[k];
+    for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = Tt[k];
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int sl = st_sl + j * SPJ, s = w0 + sl;
-        if (st_qok && s >= c0 && s < c1 && s <= n) a.vout[(int64_t)s * a.vout_ld + st_q] = smem[st_ln * TP + sl];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < R; ++k) smem[ln * TP + L.i * R + k] = U[k];
-    __syncthreads();
-    const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
-    if (a.utrans) {
-        // uout[q * ld + (s - 1)]: consecutive threads along the slots of a line
-        const int nv = hi - lo + 1;
-        for (int idx = tid; idx < LW * nv; idx += NT) {
-            const int l2 = idx / nv, jj = idx - l2 * nv;
-            const int qq = lg * LW + l2;
-            if (qq < a.nlines) a.uout[(int64_t)qq * a.uout_ld + (lo + jj - 1)] = smem[l2 * TP + (lo - w0) + jj];
-        }
-    } else {
+    {
+        T* p = a.vout + (int64_t)(w0 + st_sl) * a.vout_ld + st_q;
+        const int64_t step = (int64_t)SPJ * a.vout_ld;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int sl = st_sl + j * SPJ, s = w0 + sl;
-            if (st_qok && s >= lo && s <= hi) a.uout[(int64_t)(s - 1) * a.uout_ld + st_q] = smem[st_ln * TP + sl];
+            if (st_qok && s >= c0 && s < c1 && s <= n) p[j * step] = smem[tix<T>(st_ln, sl)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = U[k];
+    __syncthreads();
+    const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
+    if (a.utrans) {
+        // uout[q * ld + (s - 1)]: TPL consecutive threads along the slots of a line
+        constexpr int TPL = C::TPL;
+        const int l2 = tid / TPL, t2 = tid % TPL;
+        const int qq = lg * LW + l2;
+        if (qq < a.nlines) {
+            T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
+            for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, s - w0)];
+        }
+    } else {
+        T* p = a.uout + (int64_t)(w0 + st_sl - 1) * a.uout_ld + st_q;
+        const int64_t step = (int64_t)SPJ * a.uout_ld;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int sl = st_sl + j * SPJ, s = w0 + sl;
+            if (st_qok && s >= lo && s <= hi) p[j * step] = smem[tix<T>(st_ln, sl)];
         }
     }
 }
