@@ -181,6 +181,70 @@ int adi_batch_launches(const adi_batch* b, int64_t* n);
 /* Free the batch (not its problems). */
 int adi_batch_destroy(adi_batch* b);
 
+/* ---- Served problems ---------------------------------------------------
+ * A server takes requests (a problem description, host arrays and a step
+ * count) at any time and returns each result in the request's own host
+ * arrays.  Every tick advances all admitted problems by one step with the
+ * grouped launches of the batched form (bit-for-bit the result of running
+ * the problem alone).  Device memory is one arena of hbm_budget_bytes
+ * allocated by adi_server_create; a request is admitted, first come first
+ * served, once its arrays and workspace fit and fewer than max_active are
+ * running.  The server owns two HIP streams and two host threads (a
+ * scheduler and a transfer thread); every adi_server_* call and adi_submit /
+ * adi_poll / adi_wait may come from any host thread. */
+typedef struct adi_server adi_server;
+
+typedef struct adi_server_params {
+    uint32_t struct_size;
+    int32_t max_active;          /* problems advanced together, at most */
+    uint64_t hbm_budget_bytes;   /* device arena (arrays + workspaces) */
+} adi_server_params;
+
+typedef struct adi_request {
+    uint32_t struct_size;        /* sizeof(adi_request) */
+    int32_t reserved0;
+    adi_params params;           /* as for adi_create; order, sweeps, source included */
+    int64_t nsteps;              /* >= 1 */
+    void *U, *V, *W;             /* host arrays (shapes of adi_bind), overwritten with
+                                    time level nsteps when the request completes */
+    const void *K, *Rv, *Rw;     /* host arrays or NULL (kappa0 / rinv0) */
+    int64_t ld[6];               /* leading dimensions (elements) of U, V, W, K, Rv, Rw;
+                                    0 = densely packed */
+} adi_request;
+
+typedef struct adi_server_stats {
+    int64_t queued, active, done, peak_active, ticks, launches;
+    uint64_t arena_used;         /* bytes */
+} adi_server_stats;
+
+/* Defaults: 16 GiB budget, 256 active problems. */
+int adi_server_params_init(adi_server_params* p);
+
+/* Create a server on the current device (allocates the arena). */
+int adi_server_create(const adi_server_params* p, adi_server** out);
+
+/* Queue a request; *ticket identifies it.  The host arrays must stay valid
+ * and untouched until the request is done.  Validation is that of
+ * adi_create plus: the arrays and workspace must fit in the budget. */
+int adi_submit(adi_server* s, const adi_request* r, uint64_t* ticket);
+
+/* *state: 0 queued, 1 running, 2 done.  Returns the request's status once
+ * done (ADI_OK or the error that failed it). */
+int adi_poll(adi_server* s, uint64_t ticket, int* state);
+
+/* Block until the request is done; returns its status. */
+int adi_wait(adi_server* s, uint64_t ticket);
+
+/* Seconds since the server's creation (steady clock) at submission, at the
+ * first step and at completion (results in the host arrays). */
+int adi_request_times(adi_server* s, uint64_t ticket, double* t_submit, double* t_start, double* t_done);
+
+int adi_server_get_stats(adi_server* s, adi_server_stats* st);
+
+/* Wait for every submitted request, then stop the threads and free the
+ * arena, streams and staging buffers. */
+int adi_server_destroy(adi_server* s);
+
 #ifdef __cplusplus
 }
 #endif

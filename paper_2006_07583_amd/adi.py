@@ -22,7 +22,9 @@ EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync",
            "adi_get_step", "adi_set_step", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
-           "adi_batch_destroy")
+           "adi_batch_destroy",
+           "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait",
+           "adi_request_times", "adi_server_get_stats", "adi_server_destroy")
 
 BATCH_GRAPH = 1
 
@@ -37,6 +39,25 @@ class AdiParams(ctypes.Structure):
         ("c_max", ctypes.c_double), ("kappa0", ctypes.c_double), ("rinv0", ctypes.c_double),
         ("src_f0", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_amp", ctypes.c_double),
     ]
+
+
+class AdiServerParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_active", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class AdiRequest(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved0", ctypes.c_int32), ("params", AdiParams),
+                ("nsteps", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("K", ctypes.c_void_p), ("Rv", ctypes.c_void_p), ("Rw", ctypes.c_void_p),
+                ("ld", ctypes.c_int64 * 6)]
+
+
+class AdiServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("active", ctypes.c_int64), ("done", ctypes.c_int64),
+                ("peak_active", ctypes.c_int64), ("ticks", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("arena_used", ctypes.c_uint64)]
 
 
 class AdiError(RuntimeError):
@@ -76,6 +97,15 @@ def lib():
         L.adi_batch_sync.argtypes = [vp]
         L.adi_batch_launches.argtypes = [vp, ctypes.POINTER(i64)]
         L.adi_batch_destroy.argtypes = [vp]
+        L.adi_server_params_init.argtypes = [ctypes.POINTER(AdiServerParams)]
+        L.adi_server_create.argtypes = [ctypes.POINTER(AdiServerParams), ctypes.POINTER(vp)]
+        L.adi_submit.argtypes = [vp, ctypes.POINTER(AdiRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.adi_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.adi_wait.argtypes = [vp, ctypes.c_uint64]
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.adi_request_times.argtypes = [vp, ctypes.c_uint64, dp, dp, dp]
+        L.adi_server_get_stats.argtypes = [vp, ctypes.POINTER(AdiServerStats)]
+        L.adi_server_destroy.argtypes = [vp]
         for name in EXPORTS[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -206,6 +236,73 @@ class Batch:
         if self._h:
             lib().adi_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Served problems (``adi_server_*``): requests with host (numpy) arrays,
+    results written back into those arrays; one grouped step of every
+    admitted problem per tick, device memory from a fixed arena."""
+
+    def __init__(self, hbm_budget_bytes=16 << 30, max_active=256):
+        p = AdiServerParams()
+        _check(lib().adi_server_params_init(ctypes.byref(p)))
+        p.hbm_budget_bytes, p.max_active = int(hbm_budget_bytes), int(max_active)
+        self._h = ctypes.c_void_p()
+        _check(lib().adi_server_create(ctypes.byref(p), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, params: AdiParams, U, V, W, K=None, Rv=None, Rw=None, nsteps=1) -> int:
+        """Queue a request; U, V, W (numpy, C-ordered rows, the params' dtype)
+        receive the result.  The arrays are kept referenced until done."""
+        import numpy as np
+        want = np.float64 if params.dtype == FP64 else np.float32
+        r = AdiRequest()
+        r.struct_size = ctypes.sizeof(AdiRequest)
+        r.params = params
+        r.nsteps = int(nsteps)
+        arrs = (U, V, W, K, Rv, Rw)
+        for i, (name, a) in enumerate(zip(("U", "V", "W", "K", "Rv", "Rw"), arrs)):
+            if a is None:
+                continue
+            if a.dtype != want or a.ndim != 2 or a.strides[1] != a.itemsize:
+                raise ValueError(f"{name}: 2-D {want.__name__} array with contiguous rows required")
+            setattr(r, name, a.ctypes.data)
+            r.ld[i] = a.strides[0] // a.itemsize
+        t = ctypes.c_uint64()
+        _check(lib().adi_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = arrs
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int()
+        _check(lib().adi_poll(self._h, int(ticket), ctypes.byref(st)))
+        return st.value
+
+    def wait(self, ticket: int):
+        _check(lib().adi_wait(self._h, int(ticket)))
+        self._keep.pop(int(ticket), None)
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().adi_request_times(self._h, int(ticket), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def stats(self) -> dict:
+        st = AdiServerStats()
+        _check(lib().adi_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in AdiServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().adi_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = {}
 
     def __del__(self):
         try:

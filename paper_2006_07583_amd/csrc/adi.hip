@@ -428,6 +428,15 @@ int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps) {
     return ADI_OK;
 }
 
+template <typename T>
+hipError_t launch_grouped(const PassDesc<T>& d, const GroupArgs<T>& ga, hipStream_t st) {
+    if (d.ver == 1) return launch_line_group<T>(ga, d.cfg, d.method, d.mode, st, d.comp);
+    if (d.ver == 2) return launch_line_group2<T>(ga, d.method, d.mode, st, d.comp);
+    return launch_line_group3<T>(ga, d.method, d.mode, st);
+}
+
+template hipError_t launch_grouped<float>(const PassDesc<float>&, const GroupArgs<float>&, hipStream_t);
+template hipError_t launch_grouped<double>(const PassDesc<double>&, const GroupArgs<double>&, hipStream_t);
 template int run_begin<float>(adi_problem*, hipStream_t);
 template int run_begin<double>(adi_problem*, hipStream_t);
 template PassDesc<float> run_pass<float>(adi_problem*, int64_t, int, int64_t, const float*);

@@ -33,8 +33,7 @@ __global__ void tick_kernel(int* tick, int set, int value) {
 
 // One grouped launch: passes [first, first + count) of a sorted set.
 struct Group {
-    int key, ver, cfg, method, mode;
-    bool comp;
+    int key;
     int first, count, total;
     size_t starts_off;   // offset (ints) of its prefix sums in the starts array
 };
@@ -43,6 +42,7 @@ template <typename T>
 struct TypedPart {
     std::vector<adi::PassDesc<T>> set[3][2];   // [even, odd, last][half]
     std::vector<Group> groups[3][2];
+    std::vector<adi::PassDesc<T>> proto[3][2];  // kernel variant of each group
     std::vector<adi::LinePassArgs<T>> items;   // all sets, grouped, for upload
     std::vector<T> aF;                         // [problem][step]
     size_t items_off[3][2] = {};               // first item of each set
@@ -127,17 +127,14 @@ void build_groups(TypedPart<T>& part, std::vector<int>& starts) {
             std::stable_sort(v.begin(), v.end(),
                              [](const adi::PassDesc<T>& x, const adi::PassDesc<T>& y) { return x.key() < y.key(); });
             part.groups[k][h].clear();
+            part.proto[k][h].clear();
             part.items_off[k][h] = part.items.size();
             size_t i = 0;
             while (i < v.size()) {
                 size_t j = i;
                 Group g{};
                 g.key = v[i].key();
-                g.ver = v[i].ver;
-                g.cfg = v[i].cfg;
-                g.method = v[i].method;
-                g.mode = v[i].mode;
-                g.comp = v[i].comp;
+                part.proto[k][h].push_back(v[i]);
                 g.first = (int)part.items.size();
                 g.starts_off = starts.size();
                 int tot = 0;
@@ -166,7 +163,8 @@ void drop_graph(adi_batch* b) {
 }
 
 template <typename T>
-hipError_t launch_group(adi_batch* b, TypedPart<T>& part, const Group& g) {
+hipError_t launch_group(adi_batch* b, TypedPart<T>& part, int k, int h, size_t gi) {
+    const Group& g = part.groups[k][h][gi];
     adi::GroupArgs<T> ga;
     ga.items = part.ditems + g.first;
     ga.starts = b->dstarts + g.starts_off;
@@ -174,15 +172,15 @@ hipError_t launch_group(adi_batch* b, TypedPart<T>& part, const Group& g) {
     ga.nitems = g.count;
     ga.total = g.total;
     ++b->launches;
-    if (g.ver == 1) return adi::launch_line_group<T>(ga, g.cfg, g.method, g.mode, b->st, g.comp);
-    if (g.ver == 2) return adi::launch_line_group2<T>(ga, g.method, g.mode, b->st, g.comp);
-    return adi::launch_line_group3<T>(ga, g.method, g.mode, b->st);
+    return adi::launch_grouped<T>(part.proto[k][h][gi], ga, b->st);
 }
 
 int launch_step(adi_batch* b, int k) {
     for (int h = 0; h < 2; ++h) {
-        for (const auto& g : b->f32.groups[k][h]) HIP_TRY(launch_group<float>(b, b->f32, g), "grouped line pass");
-        for (const auto& g : b->f64.groups[k][h]) HIP_TRY(launch_group<double>(b, b->f64, g), "grouped line pass");
+        for (size_t gi = 0; gi < b->f32.groups[k][h].size(); ++gi)
+            HIP_TRY(launch_group<float>(b, b->f32, k, h, gi), "grouped line pass");
+        for (size_t gi = 0; gi < b->f64.groups[k][h].size(); ++gi)
+            HIP_TRY(launch_group<double>(b, b->f64, k, h, gi), "grouped line pass");
     }
     hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, b->st, b->dtick, 0, 0);
     HIP_TRY(hipGetLastError(), "step counter");

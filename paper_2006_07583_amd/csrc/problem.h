@@ -77,6 +77,8 @@ template <typename T>
 PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab);
 template <typename T> int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps);
 template <typename T> hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st);
+// One grouped launch of passes sharing the kernel variant of `proto`.
+template <typename T> hipError_t launch_grouped(const PassDesc<T>& proto, const GroupArgs<T>& ga, hipStream_t st);
 
 // a * s(t) / h^2 at time level m (0 without a source)
 double source_term(const adi_problem& pb, int64_t m);

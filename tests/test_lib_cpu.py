@@ -112,3 +112,24 @@ def test_batch_create_validates_arguments_on_the_host():
     n = ctypes.c_int64()
     assert L.adi_batch_launches(None, ctypes.byref(n)) == -1
     assert L.adi_batch_destroy(None) == 0
+
+
+def test_server_validates_arguments_on_the_host():
+    L = adi.lib()
+    out = ctypes.c_void_p()
+    p = adi.AdiServerParams()
+    assert L.adi_server_params_init(ctypes.byref(p)) == 0
+    assert p.struct_size == ctypes.sizeof(adi.AdiServerParams) and p.max_active == 256
+    assert L.adi_server_create(None, ctypes.byref(out)) == -1
+    bad = adi.AdiServerParams(p.struct_size, 0, p.hbm_budget_bytes)
+    assert L.adi_server_create(ctypes.byref(bad), ctypes.byref(out)) == -1
+    assert b"max_active" in L.adi_last_error()
+    bad = adi.AdiServerParams(p.struct_size, 4, 1024)
+    assert L.adi_server_create(ctypes.byref(bad), ctypes.byref(out)) == -1
+    assert L.adi_server_create(ctypes.byref(p), None) == -1
+    t = ctypes.c_uint64()
+    assert L.adi_submit(None, None, ctypes.byref(t)) == -1
+    st = ctypes.c_int()
+    assert L.adi_poll(None, 1, ctypes.byref(st)) == -1
+    assert L.adi_wait(None, 1) == -1
+    assert L.adi_server_destroy(None) == 0
