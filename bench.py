@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the batched 256-problem workload (0 = skip it)")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served workload (0 = skip it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -134,6 +138,123 @@ def batch_case(steps, count):
             "grouped_launches": launches}
 
 
+class PinnedPool:
+    """First-fit pool over one pinned host allocation (request arrays of the
+    served workload: allocated once, outside the timed stream)."""
+
+    def __init__(self, nbytes):
+        import torch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True).numpy()
+        self.free = {0: nbytes}
+
+    def alloc(self, shape, dtype):
+        n = (int(np.prod(shape)) * np.dtype(dtype).itemsize + 255) // 256 * 256
+        for off in sorted(self.free):
+            size = self.free[off]
+            if size >= n:
+                del self.free[off]
+                if size > n:
+                    self.free[off + n] = size - n
+                a = self.buf[off:off + n].view(dtype)[: int(np.prod(shape))].reshape(shape)
+                a.fill(0)
+                return off, n, a
+        return None
+
+    def release(self, off, n):
+        self.free[off] = n
+        keys = sorted(self.free)
+        merged = {}
+        cur = None
+        for k in keys:
+            if cur is not None and cur[0] + cur[1] == k:
+                cur = (cur[0], cur[1] + self.free[k])
+            else:
+                if cur is not None:
+                    merged[cur[0]] = cur[1]
+                cur = (k, self.free[k])
+        if cur is not None:
+            merged[cur[0]] = cur[1]
+        self.free = merged
+
+
+def serve_case(count, rate, budget_gb, pool_gb=24.0):
+    """The served workload: a Poisson stream of requests (sizes 128-2048,
+    100-2000 steps, CFD / MFD and FP32 / FP64 uniform, layered media cut
+    from one seeded 2048^2 field, Ricker source, CFL 0.8) submitted in real
+    time to one server; latency = submission to results in host memory.
+    Request arrays live in a pinned host pool; when it is full the submitter
+    waits for the oldest request (reported as submit_s beyond the arrival
+    window)."""
+    import torch
+    from paper_2006_07583_amd import adi, inputs
+    mix = inputs.serve_mix(0, count=count, rate=rate)
+    h = 5.0
+    pinned = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory().numpy()
+    media = {}
+    for m in (0, 1):
+        c = inputs.layered_speed(m, 2048, 2048, h, 12345 + m)
+        media[m] = {"K32": pinned((c * c).astype(np.float32)), "K64": pinned(c * c), "cmax": float(c.max())}
+    pool = PinnedPool(int(pool_gb * (1 << 30)))
+    srv = adi.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=512)
+    pending, tickets, cells_steps, waited = {}, [], 0, 0
+
+    def reap(block_oldest=False):
+        nonlocal waited
+        if block_oldest and pending:
+            t = next(iter(pending))
+            srv.wait(t)
+            waited += 1
+        for t in [t for t in pending if srv.poll(t) == 2]:
+            srv.wait(t)
+            for off, n in pending.pop(t):
+                pool.release(off, n)
+
+    t0 = time.perf_counter()
+    for i, rq in enumerate(mix):
+        while time.perf_counter() - t0 < rq["t"]:
+            time.sleep(min(0.001, max(0.0, rq["t"] - (time.perf_counter() - t0))))
+        m, nx, ny = rq["method"], rq["nx"], rq["ny"]
+        npdt = np.float64 if rq["fp64"] else np.float32
+        sh = inputs.shapes(m, nx, ny)
+        got = []
+        while True:
+            got = [pool.alloc(sh[k], npdt) for k in ("U", "V", "W")]
+            if all(g is not None for g in got):
+                break
+            for g in got:
+                if g is not None:
+                    pool.release(g[0], g[1])
+            reap(block_oldest=True)
+        U, V, W = (g[2] for g in got)
+        K = media[m]["K64" if rq["fp64"] else "K32"][:sh["U"][0], :sh["U"][1]]
+        cmax = media[m]["cmax"]
+        p = adi.make_params(m, adi.FP64 if rq["fp64"] else adi.FP32, nx, ny, h, 0.8 * h / cmax, cmax,
+                            src=inputs.ricker_source(rq["src_i"], rq["src_j"]))
+        tk = srv.submit(p, U, V, W, K, nsteps=rq["nsteps"])
+        tickets.append(tk)
+        pending[tk] = [(g[0], g[1]) for g in got]
+        cells_steps += nx * ny * rq["nsteps"]
+        if i % 32 == 31:
+            reap()
+    t_submitted = time.perf_counter() - t0
+    for t in list(pending):
+        srv.wait(t)
+    wall = time.perf_counter() - t0
+    times = np.array([srv.times(t) for t in tickets])
+    lat = times[:, 2] - times[:, 0]
+    span = times[:, 2].max() - times[:, 0].min()
+    st = srv.stats()
+    srv.close()
+    return {"requests": count, "rate_per_s": rate, "budget_GB": budget_gb,
+            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_mean_s": float(lat.mean()),
+            "queue_wait_p50_s": float(np.percentile(times[:, 1] - times[:, 0], 50)),
+            "pt_steps_s": cells_steps / span, "offered_pt_steps_s": cells_steps / mix[-1]["t"],
+            "arrival_window_s": mix[-1]["t"], "submit_s": t_submitted, "submitter_waits": waited,
+            "span_s": float(span), "wall_s": wall,
+            "peak_active": st["peak_active"], "ticks": st["ticks"], "grouped_launches": st["launches"]}
+
+
 def cpu_baseline(n, steps, methods):
     import oracle as O
     from paper_2006_07583_amd import inputs
@@ -217,6 +338,12 @@ def main():
               f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched, {bc['alone_pt_steps_s']:.4g} one at a time "
               f"({bc['speedup']:.2f}x), {bc['grouped_launches']} grouped launches", file=sys.stderr, flush=True)
         out["batched"] = bc
+    if args.serve_requests > 0:
+        sv = serve_case(args.serve_requests, args.serve_rate, args.serve_budget_gb)
+        print(f"# served {sv['requests']} requests at {sv['rate_per_s']:.0f}/s: latency p50 {sv['latency_p50_s']:.3f} s, "
+              f"p99 {sv['latency_p99_s']:.3f} s, {sv['pt_steps_s']:.4g} pt-steps/s served "
+              f"(offered {sv['offered_pt_steps_s']:.4g}), peak {sv['peak_active']} active", file=sys.stderr, flush=True)
+        out["serving"] = sv
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_steps, methods)
     print(json.dumps(out), flush=True)

@@ -189,9 +189,11 @@ int adi_batch_destroy(adi_batch* b);
  * the problem alone).  Device memory is one arena of hbm_budget_bytes
  * allocated by adi_server_create; a request is admitted, first come first
  * served, once its arrays and workspace fit and fewer than max_active are
- * running.  The server owns two HIP streams and two host threads (a
- * scheduler and a transfer thread); every adi_server_* call and adi_submit /
- * adi_poll / adi_wait may come from any host thread. */
+ * running.  The server owns three HIP streams and three host threads (a
+ * scheduler, an uploader and a downloader); every adi_server_* call and
+ * adi_submit / adi_poll / adi_wait may come from any host thread.  Pinned
+ * host arrays (hipHostMalloc, torch pin_memory) make the copies true DMA;
+ * pageable arrays work but keep the transfer threads busy longer. */
 typedef struct adi_server adi_server;
 
 typedef struct adi_server_params {

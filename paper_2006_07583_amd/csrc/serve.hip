@@ -1,8 +1,9 @@
 // Served form of the library (include/adi.h, adi_server_*): requests with
 // host arrays arrive at any time; a scheduler thread advances every active
 // problem by one step per tick with grouped launches (one grid per kernel
-// variant and half-step, as in batch.hip) while a transfer thread uploads
-// admitted requests and downloads finished ones on a stream of its own.
+// variant and half-step, as in batch.hip) while an upload thread admits and
+// uploads requests and a download thread returns finished ones, each on a
+// stream of its own.
 //
 // Device memory comes from an arena of hbm_budget_bytes allocated once at
 // creation: admission is first come, first served, as soon as the request's
@@ -124,7 +125,7 @@ struct Slot {
 struct adi_server {
     adi_server_params prm{};
     int dev = 0;
-    hipStream_t cs = nullptr, ts = nullptr;   // compute, transfer
+    hipStream_t cs = nullptr, us = nullptr, ds = nullptr;   // compute, upload, download
     char* mem = nullptr;
     Arena arena;
     std::chrono::steady_clock::time_point t0;
@@ -139,7 +140,7 @@ struct adi_server {
     bool sched_done = false;
     int fatal = ADI_OK;
     int64_t admitted = 0;   // admitted and not yet done (bounded by max_active)
-    std::thread sched, xfer;
+    std::thread sched, up, down;
     // tick staging
     static constexpr int NSLOT = 4;
     Slot slot[NSLOT];
@@ -294,7 +295,7 @@ void scheduler(adi_server* S) {
     }
 }
 
-// Upload one admitted request and bind its problem (transfer stream).
+// Upload one admitted request and bind its problem (upload stream).
 int start_request(adi_server* S, Req* r) {
     const adi_params& p = r->r.params;
     const size_t esz = p.dtype == ADI_FP64 ? 8 : 4;
@@ -306,10 +307,10 @@ int start_request(adi_server* S, Req* r) {
         if (!src[i]) continue;
         dptr[i] = S->mem + r->off + r->arr_off[i];
         HIP_TRY(hipMemcpy2DAsync(dptr[i], cols[i] * esz, src[i], r->ld[i] * esz, cols[i] * esz, rows[i],
-                                 hipMemcpyHostToDevice, S->ts), "request upload");
+                                 hipMemcpyHostToDevice, S->us), "request upload");
     }
-    HIP_TRY(hipStreamSynchronize(S->ts), "hipStreamSynchronize");
-    int rc = adi_create(&p, S->ts, &r->pb);
+    HIP_TRY(hipStreamSynchronize(S->us), "hipStreamSynchronize");
+    int rc = adi_create(&p, S->us, &r->pb);
     if (rc != ADI_OK) return rc;
     const int64_t ld0[6] = {0, 0, 0, 0, 0, 0};
     rc = adi_bind(r->pb, dptr[0], dptr[1], dptr[2], dptr[3], dptr[4], dptr[5], ld0, S->mem + r->off + r->ws_off,
@@ -328,15 +329,15 @@ int finish_request(adi_server* S, Req* r) {
     void* dst[3] = {r->r.U, r->r.V, r->r.W};
     for (int i = 0; i < 3; ++i)
         HIP_TRY(hipMemcpy2DAsync(dst[i], r->ld[i] * esz, S->mem + r->off + r->arr_off[i], cols[i] * esz,
-                                 cols[i] * esz, rows[i], hipMemcpyDeviceToHost, S->ts), "result download");
-    HIP_TRY(hipStreamSynchronize(S->ts), "hipStreamSynchronize");
+                                 cols[i] * esz, rows[i], hipMemcpyDeviceToHost, S->ds), "result download");
+    HIP_TRY(hipStreamSynchronize(S->ds), "hipStreamSynchronize");
     return ADI_OK;
 }
 
-void transfer(adi_server* S) {
+// Admission and uploads, oldest request first.
+void uploader(adi_server* S) {
     (void)hipSetDevice(S->dev);
     for (;;) {
-        Req* fin = nullptr;
         Req* adm = nullptr;
         {
             std::unique_lock<std::mutex> lk(S->mu);
@@ -351,65 +352,66 @@ void transfer(adi_server* S) {
                 }
                 return true;
             };
-            S->cv.wait(lk, [&] {
-                return S->fatal || !S->finishing.empty() || admissible() ||
-                       (S->sched_done && S->finishing.empty());
-            });
-            if (S->fatal) return;
-            if (!S->finishing.empty()) {
-                fin = S->finishing.front();
-                S->finishing.pop_front();
-            } else if (!S->pending.empty() && S->pending.front()->off != (size_t)-1 &&
-                       S->admitted < S->prm.max_active) {
-                adm = S->pending.front();
-                S->pending.pop_front();
-                ++S->admitted;
-            } else if (S->sched_done) {
-                return;
-            } else {
-                continue;
-            }
+            S->cv.wait(lk, [&] { return S->fatal || admissible() || (S->stop && S->pending.empty()); });
+            if (S->fatal || !admissible()) return;
+            adm = S->pending.front();
+            S->pending.pop_front();
+            ++S->admitted;
         }
-        if (fin) {
-            const int rc = finish_request(S, fin);
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (rc != ADI_OK) {
-                fail_all(S, rc);
-                return;
-            }
-            adi_destroy(fin->pb);
-            fin->pb = nullptr;
-            S->arena.release(fin->off, fin->bytes);
-            fin->state = ST_DONE;
-            fin->t_done = now_s(S->t0);
-            ++S->done;
+        const int rc = start_request(S, adm);
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (rc != ADI_OK) {
+            // this request fails alone; its memory goes back
+            if (adm->pb) adi_destroy(adm->pb);
+            adm->pb = nullptr;
+            S->arena.release(adm->off, adm->bytes);
+            adm->state = ST_DONE;
+            adm->status = rc;
+            adm->t_done = now_s(S->t0);
             --S->admitted;
             S->cv.notify_all();
-        } else {
-            const int rc = start_request(S, adm);
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (rc != ADI_OK) {
-                // this request fails alone; its memory goes back
-                if (adm->pb) adi_destroy(adm->pb);
-                adm->pb = nullptr;
-                S->arena.release(adm->off, adm->bytes);
-                adm->state = ST_DONE;
-                adm->status = rc;
-                adm->t_done = now_s(S->t0);
-                --S->admitted;
-                S->cv.notify_all();
-                continue;
-            }
-            S->ready.push_back(adm);
-            S->cv.notify_all();
+            continue;
         }
+        S->ready.push_back(adm);
+        S->cv.notify_all();
+    }
+}
+
+// Downloads of finished requests, in completion order.
+void downloader(adi_server* S) {
+    (void)hipSetDevice(S->dev);
+    for (;;) {
+        Req* fin = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->fatal || !S->finishing.empty() || S->sched_done; });
+            if (S->fatal) return;
+            if (S->finishing.empty()) return;   // scheduler done and nothing left
+            fin = S->finishing.front();
+            S->finishing.pop_front();
+        }
+        const int rc = finish_request(S, fin);
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (rc != ADI_OK) {
+            fail_all(S, rc);
+            return;
+        }
+        adi_destroy(fin->pb);
+        fin->pb = nullptr;
+        S->arena.release(fin->off, fin->bytes);
+        fin->state = ST_DONE;
+        fin->t_done = now_s(S->t0);
+        ++S->done;
+        --S->admitted;
+        S->cv.notify_all();
     }
 }
 
 void release_server(adi_server* S) {
     (void)hipSetDevice(S->dev);
     if (S->cs) (void)hipStreamSynchronize(S->cs);
-    if (S->ts) (void)hipStreamSynchronize(S->ts);
+    if (S->us) (void)hipStreamSynchronize(S->us);
+    if (S->ds) (void)hipStreamSynchronize(S->ds);
     for (auto& kv : S->all) {
         Req* r = kv.second;
         if (r->pb) adi_destroy(r->pb);
@@ -424,7 +426,8 @@ void release_server(adi_server* S) {
     if (S->dzero) (void)hipFree(S->dzero);
     if (S->mem) (void)hipFree(S->mem);
     if (S->cs) (void)hipStreamDestroy(S->cs);
-    if (S->ts) (void)hipStreamDestroy(S->ts);
+    if (S->us) (void)hipStreamDestroy(S->us);
+    if (S->ds) (void)hipStreamDestroy(S->ds);
     delete S;
 }
 
@@ -453,7 +456,8 @@ int adi_server_create(const adi_server_params* p, adi_server** out) {
     S->t0 = std::chrono::steady_clock::now();
     hipError_t e = hipGetDevice(&S->dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->ts, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->us, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->ds, hipStreamNonBlocking);
     if (e != hipSuccess) {
         release_server(S);
         return hip_fail(e, "server streams");
@@ -486,7 +490,8 @@ int adi_server_create(const adi_server_params* p, adi_server** out) {
         return hip_fail(e, "server set-up");
     }
     S->sched = std::thread(scheduler, S);
-    S->xfer = std::thread(transfer, S);
+    S->up = std::thread(uploader, S);
+    S->down = std::thread(downloader, S);
     *out = S;
     return ADI_OK;
 }
@@ -593,10 +598,12 @@ int adi_server_destroy(adi_server* S) {
         S->stop = true;
         S->cv.notify_all();
     }
-    // the scheduler leaves once nothing is pending, ready or active; the
-    // transfer thread after the last download
+    // the uploader leaves once nothing is pending, the scheduler once nothing
+    // is pending, uploading, running or downloading, the downloader after the
+    // last download
     if (S->sched.joinable()) S->sched.join();
-    if (S->xfer.joinable()) S->xfer.join();
+    if (S->up.joinable()) S->up.join();
+    if (S->down.joinable()) S->down.join();
     release_server(S);
     return ADI_OK;
 }

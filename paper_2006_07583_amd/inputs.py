@@ -158,3 +158,23 @@ def batch_mix(seed: int = 0, count: int = 256, lo: int = 64, hi: int = 1024) -> 
         out.append({"method": method, "nx": nx, "ny": ny, "medium_seed": int(rng.integers(0, 2**31)),
                     "src_i": si, "src_j": sj})
     return out
+
+
+def serve_mix(seed: int = 0, count: int = 2000, rate: float = 200.0, lo: int = 128, hi: int = 2048,
+              steps_lo: int = 100, steps_hi: int = 2000) -> list:
+    """Request stream of the served workload: Poisson arrivals at `rate` per
+    second, Nx, Ny independent and log-uniform on [lo, hi], steps log-uniform
+    on [steps_lo, steps_hi], method and dtype (FP32 / FP64) uniform, Ricker
+    source at a uniform interior point at least 8 cells from the walls."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        nx = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        ny = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        nsteps = int(round(math.exp(rng.uniform(math.log(steps_lo), math.log(steps_hi)))))
+        out.append({"t": t, "nx": nx, "ny": ny, "nsteps": nsteps, "method": int(rng.integers(0, 2)),
+                    "fp64": bool(rng.integers(0, 2)), "src_i": int(rng.integers(8, nx - 8 + 1)),
+                    "src_j": int(rng.integers(8, ny - 8 + 1))})
+    return out
