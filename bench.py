@@ -21,6 +21,34 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+# HBM traffic of the compact FP32 line pass at 4096^2, from rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE per dispatch, scaled by a device copy of known
+# size); valid while the sources that define that kernel are unchanged.
+COUNTERS = os.path.join(HERE, "profiles", "line_pass3_cfd_fp32_4096_counters.txt")
+KERNEL_FILES = ["line_pass3.hip", "line_consts.h", "pass_common.h", "line_pass.h", "line_pass.hip", "adi.hip",
+                "problem.h"]
+
+
+def counter_traffic():
+    """Bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or the kernel sources changed."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith(("#", " ")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.split("(")[0].strip()
+    h = hashlib.sha256()
+    for n in sorted(KERNEL_FILES):
+        path = os.path.join(HERE, "paper_2006_07583_amd", "csrc", n)
+        h.update(path.rsplit("/", 1)[-1].encode())
+        h.update(open(path, "rb").read())
+    if kv.get("source_hash") != h.hexdigest()[:16]:
+        return None
+    return float(kv["traffic_bytes_per_dispatch"])
 
 
 def parse():
@@ -327,9 +355,12 @@ def main():
                                + " and ".join("CFD" if m == 0 else "MFD" for m in methods),
                    "grid": n, "methods": args.methods, "sweeps": args.sweeps},
         "roofline": {"bound": "hbm", "achieved": rd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rd["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"line_pass {'CFD' if dom == 0 else 'MFD'} "
-                               f"{'fp32' if head == adi.FP32 else 'fp64'}"},
+                     "frac": rd["gbs"] / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if (dom == adi.CFD and head == adi.FP32 and n == 4096) else None,
+                     "traffic_unit": "bytes per launch (counters)", "alg_bytes": rd["alg_bytes_pass"],
+                     "kernel": (f"{'line_pass3_kernel' if dom == 0 else 'line_pass2_kernel'}<"
+                                f"{'float' if head == adi.FP32 else 'double'}, {dom}, SWEEP> "
+                                f"({'compact' if dom == 0 else 'mimetic'} line pass)")},
         "variants": variants,
     }
     if args.batch_steps > 0:
