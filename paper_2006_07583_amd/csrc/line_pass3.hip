@@ -94,6 +94,28 @@ __device__ __forceinline__ double rlane(double x, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Raw buffer accesses: 32-bit byte offsets within one array (a descriptor
+// per array, range-checked by the hardware against the array's extent).
+// They replace the 64-bit address arithmetic of each access; the kernel
+// uses them only for accesses that are in range by construction.
+constexpr int64_t kBufMax = (int64_t)1 << 31;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(float, __amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(double, __amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(float x, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double x, __amdgpu_buffer_rsrc_t r, int off) {
+    using v2u = __attribute__((ext_vector_type(2))) unsigned;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, off, 0, 0);
+}
+
 constexpr double pow_na(int e) {   // (-alpha)^e
     double r = 1.0;
     for (int i = 0; i < e; ++i) r *= -kAlpha;
@@ -314,7 +336,16 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     const bool inner = !L.lwin && !L.rwin && (lg + 1) * LW <= a.nlines;
     auto fetch = [&](const T* base, int64_t ld, bool ptype, T (&v)[EPT]) {
         if (inner) {
-            const T* p = base + (int64_t)(w0 + st_sl - (ptype ? 1 : 0)) * ld + st_q;
+            const int64_t bytes = (int64_t)(ptype ? uhi : n + 1) * ld * (int64_t)sizeof(T);
+            const int row0 = w0 + st_sl - (ptype ? 1 : 0);
+            if (bytes < kBufMax) {
+                const auto rs = make_rsrc(base, bytes);
+                const int o0 = (row0 * (int)ld + st_q) * (int)sizeof(T), step = SPJ * (int)ld * (int)sizeof(T);
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) v[j] = bload(T(), rs, o0 + j * step);
+                return;
+            }
+            const T* p = base + (int64_t)row0 * ld + st_q;
             const int64_t step = (int64_t)SPJ * ld;
 #pragma unroll
             for (int j = 0; j < EPT; ++j) v[j] = p[j * step];
@@ -554,12 +585,24 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = Tt[k];
     __syncthreads();
     {
-        T* p = a.vout + (int64_t)(w0 + st_sl) * a.vout_ld + st_q;
-        const int64_t step = (int64_t)SPJ * a.vout_ld;
+        const int64_t bytes = (int64_t)(n + 1) * a.vout_ld * (int64_t)sizeof(T);
+        if (bytes < kBufMax) {
+            const auto rs = make_rsrc(a.vout, bytes);
+            const int o0 = ((w0 + st_sl) * (int)a.vout_ld + st_q) * (int)sizeof(T);
+            const int step = SPJ * (int)a.vout_ld * (int)sizeof(T);
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int sl = st_sl + j * SPJ, s = w0 + sl;
-            if (st_qok && s >= c0 && s < c1 && s <= n) p[j * step] = smem[tix<T>(st_ln, sl)];
+            for (int j = 0; j < EPT; ++j) {
+                const int sl = st_sl + j * SPJ, s = w0 + sl;
+                if (st_qok && s >= c0 && s < c1 && s <= n) bstore(smem[tix<T>(st_ln, sl)], rs, o0 + j * step);
+            }
+        } else {
+            T* p = a.vout + (int64_t)(w0 + st_sl) * a.vout_ld + st_q;
+            const int64_t step = (int64_t)SPJ * a.vout_ld;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const int sl = st_sl + j * SPJ, s = w0 + sl;
+                if (st_qok && s >= c0 && s < c1 && s <= n) p[j * step] = smem[tix<T>(st_ln, sl)];
+            }
         }
     }
     __syncthreads();
@@ -572,7 +615,12 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         constexpr int TPL = C::TPL;
         const int l2 = tid / TPL, t2 = tid % TPL;
         const int qq = lg * LW + l2;
-        if (qq < a.nlines) {
+        const int64_t bytes = (int64_t)a.nlines * a.uout_ld * (int64_t)sizeof(T);
+        if (qq < a.nlines && bytes < kBufMax) {
+            const auto rs = make_rsrc(a.uout, bytes);
+            int o = (qq * (int)a.uout_ld + lo + t2 - 1) * (int)sizeof(T);
+            for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, s - w0)], rs, o);
+        } else if (qq < a.nlines) {
             T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
             for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, s - w0)];
         }
