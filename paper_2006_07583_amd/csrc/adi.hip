@@ -77,9 +77,11 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.deep = 1;
     } else {
         // multi-window: the wave-per-line kernel for the compact scheme (its
-        // barrier-free solves pay for the staged loads); the segment kernel for
-        // the mimetic scheme and the compensated mode
-        p.ver = (dtype == ADI_FP32C || method == ADI_MFD) ? 2 : 3;
+        // barrier-free solves pay for the staged loads) and for the mimetic
+        // scheme in FP64; the segment kernel for the mimetic scheme in FP32
+        // (shorter margins, so fewer wasted slots than the wave layout's) and
+        // for the compensated mode
+        p.ver = (dtype == ADI_FP32C || (method == ADI_MFD && dtype == ADI_FP32)) ? 2 : 3;
         p.seg = adi::line2_seg(dtype);
         // windows of LINE_WS slots overlapping by 2H; the first and last own
         // LINE_WS - H central slots, the others S = LINE_WS - 2H
@@ -90,7 +92,8 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
     }
     const int lw = p.ver == 1 ? adi::line_lanes(dtype, p.cfg)
                               : (p.ver == 2 ? adi::line2_lanes(dtype) : adi::line3_lanes(dtype));
-    p.nlg = (nlines + lw - 1) / lw;
+    // the wave-per-line kernel indexes its rows r = q + 1 (row 0 all zeros)
+    p.nlg = (nlines + (p.ver == 3 ? 1 : 0) + lw - 1) / lw;
     return p;
 }
 
@@ -153,8 +156,9 @@ double ricker(const adi_params& p, double t) {
 
 namespace {
 
+// Workspace regions of one direction: P, V0, V1, K, R, Plo, V0lo, V1lo, coef.
 struct Layout {
-    size_t off[18];
+    size_t off[2][9];
     size_t total;
 };
 
@@ -163,32 +167,19 @@ Layout layout(const adi_problem& pb) {
     const auto& p = pb.p;
     Layout L{};
     size_t cur = 0;
-    auto put = [&](int idx, size_t elems) {
-        L.off[idx] = cur;
-        cur += (elems * pb.esz + 255) / 256 * 256;
-    };
-    const size_t nix = pb.nix, niy = pb.niy, ldx = pb.ldx, ldy = pb.ldy;
-    put(0, nix * ldy);                                   // UAT
-    put(1, niy * ldx);                                   // UC
-    put(2, (size_t)(p.nx + 1) * ldy);                    // VT0
-    put(3, (size_t)(p.nx + 1) * ldy);                    // VT1
-    put(4, (size_t)(p.ny + 1) * ldx);                    // WS0
-    put(5, (size_t)(p.ny + 1) * ldx);                    // WS1
-    put(6, pb.hasK ? niy * ldx : 0);                     // aK
-    put(7, pb.hasK ? nix * ldy : 0);                     // aKT
-    put(8, pb.hasRv ? (size_t)(p.nx + 1) * ldy : 0);     // aRvT
-    put(9, pb.hasRw ? (size_t)(p.ny + 1) * ldx : 0);     // aRw
-    const bool cfd = p.method == ADI_CFD;
-    auto tabs = [&](const Plan& pl) { return pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : (size_t)0; };
-    put(10, cfd ? tabs(pb.px) : 0);   // coefX
-    put(11, cfd ? tabs(pb.py) : 0);   // coefY
-    const bool comp = p.dtype == ADI_FP32C;   // low words of the carried state
-    put(12, comp ? nix * ldy : 0);
-    put(13, comp ? niy * ldx : 0);
-    put(14, comp ? (size_t)(p.nx + 1) * ldy : 0);
-    put(15, comp ? (size_t)(p.nx + 1) * ldy : 0);
-    put(16, comp ? (size_t)(p.ny + 1) * ldx : 0);
-    put(17, comp ? (size_t)(p.ny + 1) * ldx : 0);
+    const bool cfd = p.method == ADI_CFD, comp = p.dtype == ADI_FP32C;
+    for (int d = 0; d < 2; ++d) {
+        const auto& D = pb.d[d];
+        const Plan& pl = d == 0 ? pb.px : pb.py;
+        const size_t pe = (size_t)D.rows_p * D.ld, ve = (size_t)D.rows_v * D.ld;
+        const bool hasR = d == 0 ? pb.hasRv : pb.hasRw;
+        const size_t sizes[9] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
+                                 comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : 0};
+        for (int i = 0; i < 9; ++i) {
+            L.off[d][i] = cur;
+            cur += (sizes[i] * pb.esz + 255) / 256 * 256;
+        }
+    }
     L.total = cur;
     return L;
 }
@@ -234,10 +225,21 @@ void derive(adi_problem* pb) {
     pb->niy = p.method == ADI_CFD ? p.ny - 1 : p.ny;
     pb->a = 0.5 * p.dt;
     const int64_t padm = 256 / (int64_t)pb->esz;   // 256-byte rows
-    pb->ldx = pad_to(pb->nix, padm);
-    pb->ldy = pad_to(pb->niy, padm);
     pb->px = make_plan(p.method, p.dtype, p.nx, pb->niy, p.sweeps);
     pb->py = make_plan(p.method, p.dtype, p.ny, pb->nix, p.sweeps);
+    for (int d = 0; d < 2; ++d) {
+        const Plan& pl = d == 0 ? pb->px : pb->py;
+        auto& D = pb->d[d];
+        D.lm = pl.ver == 3;
+        if (D.lm) {
+            D.ld = pad_to(pl.ns, padm);
+            D.rows_p = D.rows_v = pad_to(pl.nlines + 1, adi::line3_lanes(p.dtype));   // row = line + 1
+        } else {
+            D.ld = pad_to(pl.nlines, padm);
+            D.rows_p = p.method == ADI_CFD ? pl.n - 1 : pl.n;   // interior slots
+            D.rows_v = pl.n + 1;
+        }
+    }
 }
 
 template <typename T>
@@ -271,47 +273,91 @@ template <typename T> struct Buf {
     int64_t ld;
 };
 
-// The state buffers of a problem, in the dtype of its arrays.
-template <typename T> struct State {
-    Buf<T> UAT, UC, VT[2], WSb[2], Uu, Wu;
-    explicit State(const adi_problem* pb) {
-        const bool comp = pb->p.dtype == ADI_FP32C;
-        auto lo = [&](void* x) -> T* { return comp ? (T*)x : nullptr; };
-        UAT = {(T*)pb->UAT, lo(pb->UATlo), pb->ldy};
-        UC = {(T*)pb->UC, lo(pb->UClo), pb->ldx};
-        for (int i = 0; i < 2; ++i) {
-            VT[i] = {(T*)pb->VT[i], lo(pb->VTlo[i]), pb->ldy};
-            WSb[i] = {(T*)pb->WSb[i], lo(pb->WSblo[i]), pb->ldx};
-        }
-        Uu = {(T*)pb->U + pb->ldU + 1, nullptr, pb->ldU};   // interior pressure, natural layout
-        Wu = {(T*)pb->W + 1, nullptr, pb->ldW};             // W, interior columns
-    }
-};
-
 template <typename T> Buf<T> nolo(const Buf<T>& b) { return Buf<T>{b.hi, nullptr, b.ld}; }
 
-// Pass along x (dir 0: lines = interior rows, layouts UAT / VT) or along y
-// (dir 1: lines = interior columns, layouts UC / WSb).
+template <typename T> Buf<T> pres(const adi_problem* pb, int d) {
+    const auto& D = pb->d[d];
+    return {(T*)D.P, (T*)D.Plo, D.ld};
+}
+template <typename T> Buf<T> vel(const adi_problem* pb, int d, int i) {
+    const auto& D = pb->d[d];
+    return {(T*)D.V[i], (T*)D.Vlo[i], D.ld};
+}
+// Pressure hand-off written by the passes along `from` for the passes along
+// the other direction, in that direction's layout: line-major target (rows
+// indexed by line + 1): element s * ld + (q + 1), i.e. (s - 1) * ld + q from
+// base + ld + 1 (utrans 0); slot-major target: element q * ld + (s - 1)
+// (utrans 1).
+template <typename T> Buf<T> pres_out(const adi_problem* pb, int from, int& utrans) {
+    const auto& O = pb->d[1 - from];
+    utrans = O.lm ? 0 : 1;
+    return O.lm ? Buf<T>{(T*)O.P + O.ld + 1, nullptr, O.ld} : Buf<T>{(T*)O.P, (T*)O.Plo, O.ld};
+}
+
+// Copies between the caller's natural arrays (row = y) and the arrays of
+// direction d: pressure-type (interior points) and velocity-type (V for
+// d = 0: interior rows, all x nodes; W for d = 1: interior columns, all y
+// nodes), scaled by `scale`.
+template <typename T>
+hipError_t pres_to_dir(const adi_problem* pb, int d, T* dst, const T* U, int64_t ldU, T scale, hipStream_t st) {
+    const auto& D = pb->d[d];
+    const T* src = U + ldU + 1;
+    T* lmd = dst + D.ld + 1;   // line-major: row q + 1, slot 1 first
+    if (d == 0)
+        return D.lm ? adi::launch_scaled_copy<T>(lmd, D.ld, src, ldU, 1, pb->niy, pb->nix, scale, st)
+                    : adi::launch_scaled_copy<T>(dst, D.ld, src, 1, ldU, pb->nix, pb->niy, scale, st);
+    return D.lm ? adi::launch_scaled_copy<T>(lmd, D.ld, src, 1, ldU, pb->nix, pb->niy, scale, st)
+                : adi::launch_scaled_copy<T>(dst, D.ld, src, ldU, 1, pb->niy, pb->nix, scale, st);
+}
+template <typename T>
+hipError_t vel_to_dir(const adi_problem* pb, int d, T* dst, const T* X, int64_t ldX, T scale, hipStream_t st) {
+    const auto& D = pb->d[d];
+    const auto& p = pb->p;
+    T* lmd = dst + D.ld;       // line-major: row q + 1
+    if (d == 0)
+        return D.lm ? adi::launch_scaled_copy<T>(lmd, D.ld, X + ldX, ldX, 1, pb->niy, p.nx + 1, scale, st)
+                    : adi::launch_scaled_copy<T>(dst, D.ld, X + ldX, 1, ldX, p.nx + 1, pb->niy, scale, st);
+    return D.lm ? adi::launch_scaled_copy<T>(lmd, D.ld, X + 1, 1, ldX, pb->nix, p.ny + 1, scale, st)
+                : adi::launch_scaled_copy<T>(dst, D.ld, X + 1, ldX, 1, p.ny + 1, pb->nix, scale, st);
+}
+template <typename T>
+hipError_t vel_from_dir(const adi_problem* pb, int d, T* X, int64_t ldX, const Buf<T>& b, hipStream_t st) {
+    const auto& D = pb->d[d];
+    const auto& p = pb->p;
+    const T* lms = b.hi + D.ld;   // line-major: row q + 1
+    if (d == 0)
+        return D.lm ? adi::launch_scaled_copy<T>(X + ldX, ldX, lms, D.ld, 1, pb->niy, p.nx + 1, T(1), st, b.lo)
+                    : adi::launch_scaled_copy<T>(X + ldX, ldX, b.hi, 1, D.ld, pb->niy, p.nx + 1, T(1), st, b.lo);
+    return D.lm ? adi::launch_scaled_copy<T>(X + 1, ldX, lms, 1, D.ld, p.ny + 1, pb->nix, T(1), st, b.lo)
+                : adi::launch_scaled_copy<T>(X + 1, ldX, b.hi, D.ld, 1, p.ny + 1, pb->nix, T(1), st, b.lo);
+}
+template <typename T>
+hipError_t zero_lo(const adi_problem* pb, int d, T* lo, bool ptype, hipStream_t st) {
+    const auto& D = pb->d[d];
+    return adi::launch_fill_zero<T>(lo, D.ld, (int)(ptype ? D.rows_p : D.rows_v), (int)D.ld, st);
+}
+
+// Pass along x (dir 0: lines = interior rows) or along y (dir 1: lines =
+// interior columns); the materials come from the direction's arrays.
 template <typename T>
 adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, const Buf<T>& vin,
                            const Buf<T>& vout, const Buf<T>& uout, int utrans, T f, const T* aFtab, int mode) {
     const auto& p = pb->p;
     const Plan& pl = dir == 0 ? pb->px : pb->py;
+    const auto& D = pb->d[dir];
     adi::PassDesc<T> d{};
     auto& a = d.a;
-    a = base_args<T>(*pb, pl, dir == 0 ? pb->coefX : pb->coefY);
+    a = base_args<T>(*pb, pl, D.coef);
     a.uin = uin.hi; a.uin_lo = uin.lo; a.uin_ld = uin.ld;
     a.vin = vin.hi; a.vin_lo = vin.lo; a.vin_ld = vin.ld;
-    if (dir == 0) {
-        a.ak = pb->hasK ? (const T*)pb->aKT : nullptr;   a.ak_ld = pb->ldy;
-        a.ar = pb->hasRv ? (const T*)pb->aRvT : nullptr; a.ar_ld = pb->ldy;
-    } else {
-        a.ak = pb->hasK ? (const T*)pb->aK : nullptr;   a.ak_ld = pb->ldx;
-        a.ar = pb->hasRw ? (const T*)pb->aRw : nullptr; a.ar_ld = pb->ldx;
-    }
+    a.ak = (const T*)D.K; a.ak_ld = D.ld;
+    a.ar = (const T*)D.R; a.ar_ld = D.ld;
     a.vout = vout.hi; a.vout_lo = vout.lo; a.vout_ld = vout.ld;
     a.uout = uout.hi; a.uout_lo = uout.lo; a.uout_ld = uout.ld;
     a.utrans = utrans;
+    // the wave-per-line kernel writes the natural-layout pressure at
+    // (s - 1) * ld + (q + 1): its base is one element lower
+    if (pl.ver == 3 && utrans == 0) a.uout = uout.hi - 1;
     if (p.src_i >= 0) {
         a.src_q = dir == 0 ? p.src_j - 1 : p.src_i - 1;
         a.src_s = dir == 0 ? p.src_i : p.src_j;
@@ -347,28 +393,39 @@ template <typename T>
 int run_begin(adi_problem* pb, hipStream_t st) {
     const auto& p = pb->p;
     const bool comp = p.dtype == ADI_FP32C;
-    State<T> S(pb);
     T* U = (T*)pb->U;
     T* V = (T*)pb->V;
     T* W = (T*)pb->W;
     const T f0 = (T)source_term(*pb, pb->step);
-    // V (interior rows) -> VT; low words start at zero
-    HIP_TRY(launch_scaled_copy<T>(S.VT[pb->vcur].hi, pb->ldy, V + pb->ldV, 1, pb->ldV, p.nx + 1, pb->niy, T(1), st),
-            "transpose V");
-    if (comp) HIP_TRY(launch_fill_zero<T>(S.VT[pb->vcur].lo, pb->ldy, p.nx + 1, pb->niy, st), "zero V low words");
+    int ut;
+    // V -> velocity arrays of the x passes; low words start at zero
+    HIP_TRY(vel_to_dir<T>(pb, 0, (T*)pb->d[0].V[pb->vcur], V, pb->ldV, T(1), st), "V in");
+    if (comp) HIP_TRY(zero_lo<T>(pb, 0, (T*)pb->d[0].Vlo[pb->vcur], false, st), "zero V low words");
     if (p.order == 0) {
         // explicit y part of stage 1: A and W* of step m
-        auto d = make_pass<T>(pb, 1, S.Uu, S.Wu, S.WSb[pb->wcur], S.UAT, 1, f0, nullptr, LINE_EXPLICIT);
-        HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
+        if (pb->d[1].lm) {
+            HIP_TRY(pres_to_dir<T>(pb, 1, (T*)pb->d[1].P, U, pb->ldU, T(1), st), "U in");
+            HIP_TRY(vel_to_dir<T>(pb, 1, (T*)pb->d[1].V[pb->wcur], W, pb->ldW, T(1), st), "W in");
+            const Buf<T> out = pres_out<T>(pb, 1, ut);
+            auto d = make_pass<T>(pb, 1, nolo(pres<T>(pb, 1)), nolo(vel<T>(pb, 1, pb->wcur)), vel<T>(pb, 1, 1 - pb->wcur),
+                                  out, ut, f0, nullptr, LINE_EXPLICIT);
+            HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
+            pb->wcur ^= 1;
+        } else {
+            const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
+            const Buf<T> out = pres_out<T>(pb, 1, ut);
+            auto d = make_pass<T>(pb, 1, Uu, Wu, vel<T>(pb, 1, pb->wcur), out, ut, f0, nullptr, LINE_EXPLICIT);
+            HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
+        }
     } else {
-        // y-implicit stage first: U -> UAT, W -> WSb, explicit x part of stage 1
-        HIP_TRY(launch_scaled_copy<T>(S.UAT.hi, pb->ldy, U + pb->ldU + 1, 1, pb->ldU, pb->nix, pb->niy, T(1), st),
-                "transpose U");
-        HIP_TRY(launch_scaled_copy<T>(S.WSb[pb->wcur].hi, pb->ldx, W + 1, pb->ldW, 1, p.ny + 1, pb->nix, T(1), st),
-                "copy W");
-        if (comp) HIP_TRY(launch_fill_zero<T>(S.WSb[pb->wcur].lo, pb->ldx, p.ny + 1, pb->nix, st), "zero W low words");
-        auto d = make_pass<T>(pb, 0, nolo(S.UAT), nolo(S.VT[pb->vcur]), S.VT[1 - pb->vcur], S.UC, 1, f0, nullptr,
-                              LINE_EXPLICIT);
+        // y-implicit stage first: U -> pressure of the x passes, W -> velocity
+        // of the y passes, explicit x part of stage 1
+        HIP_TRY(pres_to_dir<T>(pb, 0, (T*)pb->d[0].P, U, pb->ldU, T(1), st), "U in");
+        HIP_TRY(vel_to_dir<T>(pb, 1, (T*)pb->d[1].V[pb->wcur], W, pb->ldW, T(1), st), "W in");
+        if (comp) HIP_TRY(zero_lo<T>(pb, 1, (T*)pb->d[1].Vlo[pb->wcur], false, st), "zero W low words");
+        const Buf<T> out = pres_out<T>(pb, 0, ut);
+        auto d = make_pass<T>(pb, 0, nolo(pres<T>(pb, 0)), nolo(vel<T>(pb, 0, pb->vcur)), vel<T>(pb, 0, 1 - pb->vcur),
+                              out, ut, f0, nullptr, LINE_EXPLICIT);
         HIP_TRY(launch_pass<T>(d, st), "explicit row pass");
         pb->vcur ^= 1;
     }
@@ -377,53 +434,51 @@ int run_begin(adi_problem* pb, hipStream_t st) {
 
 template <typename T>
 PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab) {
-    State<T> S(pb);
     const bool last = s == nsteps - 1;
     const T f1 = (T)source_term(*pb, pb->step + s + 1);
+    T* U = (T*)pb->U;
+    T* W = (T*)pb->W;
+    int ut;
     PassDesc<T> d;
-    if (pb->p.order == 0) {
-        if (half == 0) {
-            // rows: stage-1 sweeps along x, then C and V^{m+1}
-            d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.UC, 1, f1, aFtab, LINE_SWEEP);
-            pb->vcur ^= 1;
-        } else if (last) {
-            // columns, last step: U^{m+n}, W^{m+n} into the caller's arrays
-            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.Wu, S.Uu, 0, T(0), nullptr, LINE_FINAL);
+    // dir: the direction of this half step
+    const int dir = pb->p.order == 0 ? half : 1 - half;
+    int& cur = dir == 0 ? pb->vcur : pb->wcur;
+    const Buf<T> uin = pres<T>(pb, dir), vin = vel<T>(pb, dir, cur), vout = vel<T>(pb, dir, 1 - cur);
+    if (half == 1 && last) {
+        // last pass of the run: U^{m+n} into the caller's array; the
+        // velocity into the caller's W directly when the y arrays are
+        // slot-major, else through the workspace (copied out by run_end)
+        if (dir == 1) {
+            const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
+            if (pb->d[1].lm) {
+                d = make_pass<T>(pb, 1, uin, vin, vout, Uu, 0, T(0), nullptr, LINE_FINAL);
+                cur ^= 1;
+            } else {
+                d = make_pass<T>(pb, 1, uin, vin, Wu, Uu, 0, T(0), nullptr, LINE_FINAL);
+            }
         } else {
-            // columns: stage-2 sweeps along y, then the next step's A and W*
-            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.WSb[1 - pb->wcur], S.UAT, 1, f1, aFtab, LINE_SWEEP);
-            pb->wcur ^= 1;
+            const Buf<T> Ux{U + pb->ldU + 1, nullptr, pb->ldU};
+            d = make_pass<T>(pb, 0, uin, vin, vout, Ux, 1, T(0), nullptr, LINE_FINAL);
+            cur ^= 1;
         }
-    } else {
-        if (half == 0) {
-            d = make_pass<T>(pb, 1, S.UC, S.WSb[pb->wcur], S.WSb[1 - pb->wcur], S.UAT, 1, f1, aFtab, LINE_SWEEP);
-            pb->wcur ^= 1;
-        } else {
-            if (last)
-                d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.Uu, 1, T(0), nullptr,
-                                 LINE_FINAL);
-            else
-                d = make_pass<T>(pb, 0, S.UAT, S.VT[pb->vcur], S.VT[1 - pb->vcur], S.UC, 1, f1, aFtab, LINE_SWEEP);
-            pb->vcur ^= 1;
-        }
+        return d;
     }
+    // sweeps of this stage, then the explicit part of the next stage
+    const Buf<T> out = pres_out<T>(pb, dir, ut);
+    d = make_pass<T>(pb, dir, uin, vin, vout, out, ut, f1, aFtab, LINE_SWEEP);
+    cur ^= 1;
     return d;
 }
 
 template <typename T>
 int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps) {
     const auto& p = pb->p;
-    State<T> S(pb);
     T* V = (T*)pb->V;
     T* W = (T*)pb->W;
-    if (p.order == 1) {
-        // W^{m+n} (interior columns) back to the caller
-        HIP_TRY(launch_scaled_copy<T>(W + 1, pb->ldW, S.WSb[pb->wcur].hi, pb->ldx, 1, p.ny + 1, pb->nix, T(1), st,
-                                      S.WSb[pb->wcur].lo), "copy W back");
-    }
-    // VT -> V (interior rows)
-    HIP_TRY(launch_scaled_copy<T>(V + pb->ldV, pb->ldV, S.VT[pb->vcur].hi, 1, pb->ldy, pb->niy, p.nx + 1, T(1), st,
-                                  S.VT[pb->vcur].lo), "transpose V back");
+    // W^{m+n} back to the caller unless the last pass wrote it
+    if (p.order == 1 || pb->d[1].lm)
+        HIP_TRY(vel_from_dir<T>(pb, 1, W, pb->ldW, vel<T>(pb, 1, pb->wcur), st), "W out");
+    HIP_TRY(vel_from_dir<T>(pb, 0, V, pb->ldV, vel<T>(pb, 0, pb->vcur), st), "V out");
     pb->step += nsteps;
     return ADI_OK;
 }
@@ -467,14 +522,14 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
     const auto& p = pb->p;
     hipStream_t st = pb->st;
     const T a = (T)pb->a;
-    if (K) {
-        HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aK, pb->ldx, K + ldK + 1, ldK, 1, pb->niy, pb->nix, a, st), "aK");
-        HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aKT, pb->ldy, K + ldK + 1, 1, ldK, pb->nix, pb->niy, a, st), "aKT");
+    // the workspace starts zeroed: line-major arrays keep zeros on the
+    // boundary slots and on the padding lines
+    HIP_TRY(hipMemsetAsync(pb->ws, 0, pb->ws_bytes, st), "workspace clear");
+    for (int d = 0; d < 2; ++d) {
+        if (K) HIP_TRY(pres_to_dir<T>(pb, d, (T*)pb->d[d].K, K, ldK, a, st), "a kappa");
+        const T* R = d == 0 ? Rv : Rw;
+        if (R) HIP_TRY(vel_to_dir<T>(pb, d, (T*)pb->d[d].R, R, d == 0 ? ldRv : ldRw, a, st), "a / rho");
     }
-    if (Rv)
-        HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aRvT, pb->ldy, Rv + ldRv, 1, ldRv, p.nx + 1, pb->niy, a, st), "aRvT");
-    if (Rw)
-        HIP_TRY(adi::launch_scaled_copy<T>((T*)pb->aRw, pb->ldx, Rw + 1, ldRw, 1, p.ny + 1, pb->nix, a, st), "aRw");
     if (p.method == ADI_CFD) {
         // factor tables of the single-window kernel (the multi-window kernel
         // uses compile-time constants)
@@ -483,9 +538,11 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
         if (pb->py.ver == 1) build_tables(pb->py, ty);
         std::vector<T> cx(tx.begin(), tx.end()), cy(ty.begin(), ty.end());
         if (!cx.empty())
-            HIP_TRY(hipMemcpyAsync(pb->coefX, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefX");
+            HIP_TRY(hipMemcpyAsync(pb->d[0].coef, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                    "x tables");
         if (!cy.empty())
-            HIP_TRY(hipMemcpyAsync(pb->coefY, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st), "coefY");
+            HIP_TRY(hipMemcpyAsync(pb->d[1].coef, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                    "y tables");
         HIP_TRY(hipStreamSynchronize(st), "bind sync");
         return ADI_OK;
     }
@@ -603,10 +660,21 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->own_ws = true;
     }
     pb->ws_bytes = L.total;
-    void** slots[18] = {&pb->UAT, &pb->UC, &pb->VT[0], &pb->VT[1], &pb->WSb[0], &pb->WSb[1],
-                        &pb->aK, &pb->aKT, &pb->aRvT, &pb->aRw, &pb->coefX, &pb->coefY,
-                        &pb->UATlo, &pb->UClo, &pb->VTlo[0], &pb->VTlo[1], &pb->WSblo[0], &pb->WSblo[1]};
-    for (int i = 0; i < 18; ++i) *slots[i] = pb->ws + L.off[i];
+    for (int d = 0; d < 2; ++d) {
+        auto& D = pb->d[d];
+        const bool hasR = d == 0 ? pb->hasRv : pb->hasRw;
+        const bool comp = p.dtype == ADI_FP32C;
+        char* w = pb->ws;
+        D.P = w + L.off[d][0];
+        D.V[0] = w + L.off[d][1];
+        D.V[1] = w + L.off[d][2];
+        D.K = pb->hasK ? w + L.off[d][3] : nullptr;
+        D.R = hasR ? w + L.off[d][4] : nullptr;
+        D.Plo = comp ? w + L.off[d][5] : nullptr;
+        D.Vlo[0] = comp ? w + L.off[d][6] : nullptr;
+        D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
+        D.coef = w + L.off[d][8];
+    }
     pb->U = U; pb->V = V; pb->W = W;
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];
     pb->vcur = pb->wcur = 0;

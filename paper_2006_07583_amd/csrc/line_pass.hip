@@ -577,12 +577,13 @@ int line_ws(int cfg) {
 // Compact: the window-edge error decays like (2 - sqrt 3)^d times a
 // polynomial in d of the degree of the number of chained solves (2K + 1).
 // For K = 6 a dense model of one line pass gives a relative error at
-// distance 31 of 4e-11 at CFL 0.8 and 1.3e-8 at the CFL limit 1.15, below
+// distance 30 of 7e-11 at CFL 0.8 and 2.8e-8 at the CFL limit 1.15, below
 // the FP32 rounding unit; FP64 (and the compensated mode) keep a wider
-// margin.
+// margin.  All margins are even (K is even): the windows of the
+// wave-per-line kernel then start on multiples of 4 slots.
 int line_halo(int dtype, int method, int sweeps) {
     if (method == LINE_MFD) return 3 * sweeps + 4;
-    return dtype == 0 ? 19 + 2 * sweeps : 40 + 3 * sweeps;
+    return dtype == 0 ? 18 + 2 * sweeps : 40 + 3 * sweeps;
 }
 
 template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, int);

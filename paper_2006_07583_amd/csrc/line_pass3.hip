@@ -36,15 +36,32 @@
 #include "line_pass.h"
 #include "pass_common.h"
 
+#ifndef STAGE_IN_F32
+#define STAGE_IN_F32 true
+#define STAGE_OUT_F32 true
+#define STAGE_IN_F64 false
+#define STAGE_OUT_F64 false
+#endif
+
 namespace adi {
 
 template <typename T> struct Cfg3;
 // waves per workgroup, lines per wave, slots per lane, carry reach (segments), waves per SIMD
-template <> struct Cfg3<float> { static constexpr int NWV = 8, LPW = 2, R = 16, TS = 1, WPE = 4; };
-template <> struct Cfg3<double> { static constexpr int NWV = 4, LPW = 2, R = 16, TS = 2, WPE = 2; };
+// SIN / SOUT: inputs / velocity output staged through LDS in 16-byte chunks
+// along the lines (coalesced), else moved lane-direct (each lane its own
+// segment).
+template <> struct Cfg3<float> {
+    static constexpr int NWV = 8, LPW = 2, R = 16, TS = 1, WPE = 4;
+    static constexpr bool SIN = STAGE_IN_F32, SOUT = STAGE_OUT_F32;
+};
+template <> struct Cfg3<double> {
+    static constexpr int NWV = 4, LPW = 2, R = 16, TS = 2, WPE = 2;
+    static constexpr bool SIN = STAGE_IN_F64, SOUT = STAGE_OUT_F64;
+};
 
 template <typename T> struct K3 {
     static constexpr int NWV = Cfg3<T>::NWV, LPW = Cfg3<T>::LPW, R = Cfg3<T>::R, TS = Cfg3<T>::TS;
+    static constexpr bool SIN = Cfg3<T>::SIN, SOUT = Cfg3<T>::SOUT;
     static constexpr int LPL = 64 / LPW;          // lanes per line
     static constexpr int WS = LPL * R;             // slots per window
     static constexpr int LW = NWV * LPW;           // lines per workgroup
@@ -101,12 +118,6 @@ __device__ __forceinline__ double rlane(double x, int src) {
 constexpr int64_t kBufMax = (int64_t)1 << 31;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ float bload(float, __amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ double bload(double, __amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 __device__ __forceinline__ void bstore(float x, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
@@ -320,65 +331,78 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     L.lwin = w0 == 0;
     L.rwin = w0 + WS >= ns;
     const int s0 = L.s0;
-    const int ln = wave * C::LPW + L.h;          // line of this lane within the workgroup
-    const int q = lg * LW + ln;
-    const bool qok = q < a.nlines;
+    // Line-major rows are indexed r = q + 1 (row 0: a line of zeros), so that
+    // the LW rows of a workgroup map onto LW-aligned runs of the other
+    // direction's slots in the transposed pressure store.
+    const int ln = wave * C::LPW + L.h;          // row of this lane's line within the workgroup
+    const int r = lg * LW + ln, q = r - 1;
+    const bool qok = q >= 0 && q < a.nlines;
 
-    // staging map: thread -> line st_ln, slots st_sl + j SPJ
+    // staging map of the pressure output tile: thread -> row st_ln, slots st_sl + j SPJ
     const int st_ln = tid % LW, st_sl = tid / LW;
-    const int st_q = lg * LW + st_ln;
-    const bool st_qok = st_q < a.nlines;
-    const int st_qc = st_qok ? st_q : a.nlines - 1;
+    const int st_r = lg * LW + st_ln;
+    const bool st_qok = st_r >= 1 && st_r <= a.nlines;
 
-    // ---- loads: every global read issued first, then one LDS round per array ----
-    // Blocks away from the line ends and with a full line group read every
-    // row unconditionally (rows w0 - 1 .. w0 + WS - 1 all exist there).
-    const bool inner = !L.lwin && !L.rwin && (lg + 1) * LW <= a.nlines;
-    auto fetch = [&](const T* base, int64_t ld, bool ptype, T (&v)[EPT]) {
-        if (inner) {
-            const int64_t bytes = (int64_t)(ptype ? uhi : n + 1) * ld * (int64_t)sizeof(T);
-            const int row0 = w0 + st_sl - (ptype ? 1 : 0);
-            if (bytes < kBufMax) {
-                const auto rs = make_rsrc(base, bytes);
-                const int o0 = (row0 * (int)ld + st_q) * (int)sizeof(T), step = SPJ * (int)ld * (int)sizeof(T);
+    // ---- loads: each lane reads its own segment of its line.  Line-major
+    // arrays: element (row r, slot s) at r * ld + s, boundary slots stored
+    // as zeros, rows padded to whole line groups; windows other than the last
+    // start on a multiple of the vector width (the margin H is even). ----
+    constexpr int VEC = 16 / (int)sizeof(T);
+    using VT = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    const bool aligned = (w0 % VEC) == 0;
+    // staged: 16-byte chunks along the LW lines of the workgroup, chunk c of
+    // line l at tile row l; then every lane reads its segment
+    constexpr int CPL = WS / VEC;                 // chunks per line
+    constexpr int CPT = CPL * LW / C::NT;         // chunks per thread
+    static_assert(CPT * C::NT == CPL * LW, "chunking");
+    auto stage_in = [&](const T* base, int64_t ld, VT (&ch)[CPT]) {
 #pragma unroll
-                for (int j = 0; j < EPT; ++j) v[j] = bload(T(), rs, o0 + j * step);
-                return;
-            }
-            const T* p = base + (int64_t)row0 * ld + st_q;
-            const int64_t step = (int64_t)SPJ * ld;
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) v[j] = p[j * step];
-            return;
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int s = w0 + st_sl + j * SPJ;
-            const bool ok = st_qok && (ptype ? (s >= 1 && s <= uhi) : (s <= n));
-            const int row = ok ? (ptype ? s - 1 : s) : 0;
-            const T x = base[(int64_t)row * ld + st_qc];
-            v[j] = ok ? x : T(0);
+        for (int j = 0; j < CPT; ++j) {
+            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
+            ch[j] = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + l) * ld + w0 + sc * VEC);
         }
     };
-    auto spread = [&](const T (&v)[EPT], T (&dst)[R]) {
+    auto stage_spread = [&](const VT (&ch)[CPT], T (&dst)[R]) {
         __syncthreads();   // earlier readers of the tile are done
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) smem[tix<T>(st_ln, st_sl + j * SPJ)] = v[j];
+        for (int j = 0; j < CPT; ++j) {
+            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
+            *reinterpret_cast<VT*>(smem + tix<T>(l, sc * VEC)) = ch[j];
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < R; ++k) dst[k] = smem[tix<T>(ln, L.i * R + k)];
     };
+    auto seg_load = [&](const T* base, int64_t ld, T (&dst)[R]) {
+        const T* p = base + (int64_t)r * ld + s0;
+        if (aligned) {
+#pragma unroll
+            for (int k = 0; k < R; k += VEC) {
+                const VT v = *reinterpret_cast<const VT*>(p + k);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) dst[k + e] = v[e];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) dst[k] = p[k];
+        }
+    };
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
-    {
-        T va[EPT], vb[EPT], vk[EPT], vr[EPT];
-        fetch(a.uin, a.uin_ld, true, va);
-        fetch(a.vin, a.vin_ld, false, vb);
-        if (a.ak) fetch(a.ak, a.ak_ld, true, vk);
-        if (a.ar) fetch(a.ar, a.ar_ld, false, vr);
-        spread(va, A);
-        spread(vb, B);
-        if (a.ak) spread(vk, KK);
-        if (a.ar) spread(vr, RR);
+    if (C::SIN && aligned) {
+        VT ca[CPT], cb[CPT], ck[CPT], cr[CPT];
+        stage_in(a.uin, a.uin_ld, ca);
+        stage_in(a.vin, a.vin_ld, cb);
+        if (a.ak) stage_in(a.ak, a.ak_ld, ck);
+        if (a.ar) stage_in(a.ar, a.ar_ld, cr);
+        stage_spread(ca, A);
+        stage_spread(cb, B);
+        if (a.ak) stage_spread(ck, KK);
+        if (a.ar) stage_spread(cr, RR);
+    } else {
+        seg_load(a.uin, a.uin_ld, A);
+        seg_load(a.vin, a.vin_ld, B);
+        if (a.ak) seg_load(a.ak, a.ak_ld, KK);
+        if (a.ar) seg_load(a.ar, a.ar_ld, RR);
     }
     // scale folded into the material values (compact: 3 alpha / h; mimetic: 9 / (8 h))
     const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
@@ -580,32 +604,46 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         for (int k = 0; k < R; ++k)
             if (q == a.src_q && s0 + k == a.src_s) U[k] += a.aF;
     }
-    __syncthreads();
+    // velocity into the line-major output (central slots only)
+    if (C::SOUT && aligned) {
+        __syncthreads();   // readers of the input tile are done
 #pragma unroll
-    for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = Tt[k];
-    __syncthreads();
-    {
-        const int64_t bytes = (int64_t)(n + 1) * a.vout_ld * (int64_t)sizeof(T);
-        if (bytes < kBufMax) {
-            const auto rs = make_rsrc(a.vout, bytes);
-            const int o0 = ((w0 + st_sl) * (int)a.vout_ld + st_q) * (int)sizeof(T);
-            const int step = SPJ * (int)a.vout_ld * (int)sizeof(T);
+        for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = Tt[k];
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int sl = st_sl + j * SPJ, s = w0 + sl;
-                if (st_qok && s >= c0 && s < c1 && s <= n) bstore(smem[tix<T>(st_ln, sl)], rs, o0 + j * step);
+        for (int j = 0; j < CPT; ++j) {
+            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
+            const int s = w0 + sc * VEC, rr = lg * LW + l;
+            const bool ok = rr >= 1 && rr <= a.nlines;
+            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, sc * VEC));
+            T* p = a.vout + (int64_t)rr * a.vout_ld + s;
+            if (ok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
+                *reinterpret_cast<VT*>(p) = v;
+            } else if (ok) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (s + e >= c0 && s + e < c1 && s + e <= n) p[e] = v[e];
             }
-        } else {
-            T* p = a.vout + (int64_t)(w0 + st_sl) * a.vout_ld + st_q;
-            const int64_t step = (int64_t)SPJ * a.vout_ld;
+        }
+    } else {
+        T* p = a.vout + (int64_t)r * a.vout_ld + s0;
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int sl = st_sl + j * SPJ, s = w0 + sl;
-                if (st_qok && s >= c0 && s < c1 && s <= n) p[j * step] = smem[tix<T>(st_ln, sl)];
+        for (int k = 0; k < R; k += VEC) {
+            const int s = s0 + k;
+            if (aligned && qok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
+                VT v;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = Tt[k + e];
+                *reinterpret_cast<VT*>(p + k) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (qok && s + e >= c0 && s + e < c1 && s + e <= n) p[k + e] = Tt[k + e];
             }
         }
     }
-    __syncthreads();
+    // pressure hand-off for the other direction, transposed through LDS
+    __syncthreads();   // readers of the tile are done
 #pragma unroll
     for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = U[k];
     __syncthreads();
@@ -614,18 +652,20 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         // uout[q * ld + (s - 1)]: TPL consecutive threads along the slots of a line
         constexpr int TPL = C::TPL;
         const int l2 = tid / TPL, t2 = tid % TPL;
-        const int qq = lg * LW + l2;
+        const int qq = lg * LW + l2 - 1;
         const int64_t bytes = (int64_t)a.nlines * a.uout_ld * (int64_t)sizeof(T);
-        if (qq < a.nlines && bytes < kBufMax) {
+        if (qq >= 0 && qq < a.nlines && bytes < kBufMax) {
             const auto rs = make_rsrc(a.uout, bytes);
             int o = (qq * (int)a.uout_ld + lo + t2 - 1) * (int)sizeof(T);
             for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, s - w0)], rs, o);
-        } else if (qq < a.nlines) {
+        } else if (qq >= 0 && qq < a.nlines) {
             T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
             for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, s - w0)];
         }
     } else {
-        T* p = a.uout + (int64_t)(w0 + st_sl - 1) * a.uout_ld + st_q;
+        // uout[(s - 1) * ld + q + 1] (the caller passes the base one element
+        // lower): runs of LW consecutive elements starting at multiples of LW
+        T* p = a.uout + (int64_t)(w0 + st_sl - 1) * a.uout_ld + st_r;
         const int64_t step = (int64_t)SPJ * a.uout_ld;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {

@@ -55,10 +55,22 @@ struct adi_problem {
     size_t ws_bytes = 0;
     bool own_ws = false;
     size_t esz = 4;
-    int64_t ldx = 0, ldy = 0;
-    void *UAT = nullptr, *UC = nullptr, *VT[2] = {nullptr, nullptr}, *WSb[2] = {nullptr, nullptr};
-    void *aK = nullptr, *aKT = nullptr, *aRvT = nullptr, *aRw = nullptr, *coefX = nullptr, *coefY = nullptr;
-    void *UATlo = nullptr, *UClo = nullptr, *VTlo[2] = {nullptr, nullptr}, *WSblo[2] = {nullptr, nullptr};
+    // Device arrays of the passes of one direction (d[0]: along x, lines =
+    // interior rows; d[1]: along y, lines = interior columns).  Line index q,
+    // slot s along the line.  Slot-major (the segment and single-window
+    // kernels): pressure-type element (s - 1) * ld + q, velocity-type s * ld + q.
+    // Line-major (the wave-per-line kernel): element q * ld + s for both, the
+    // boundary slots stored as zeros, rows padded to whole line groups.
+    struct Dir {
+        bool lm = false;
+        int64_t ld = 0;                       // leading dimension (elements)
+        int64_t rows_p = 0, rows_v = 0;       // rows of the pressure- / velocity-type arrays
+        void *P = nullptr;                    // pressure hand-off read by these passes
+        void *V[2] = {nullptr, nullptr};      // velocity along the lines (ping-pong)
+        void *K = nullptr, *R = nullptr;      // a*kappa, a/rho (NULL when constant)
+        void *Plo = nullptr, *Vlo[2] = {nullptr, nullptr};   // compensated low words
+        void *coef = nullptr;                 // single-window compact tables
+    } d[2];
     int vcur = 0, wcur = 0;
     adi::Plan px, py;
 };
