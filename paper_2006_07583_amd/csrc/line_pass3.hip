@@ -71,18 +71,37 @@ template <typename T> struct K3 {
     static constexpr int TP = WS + 4;
     static constexpr int TILE = LW * TP;
     static constexpr int TPL = NT / LW;            // threads per line in the transposed store
-    static constexpr int SPJ = NT / LW;            // slots covered by one staging step
-    static constexpr int EPT = WS / SPJ;           // staging steps per array
 };
 static_assert(K3<float>::WS == LINE_WS && K3<double>::WS == LINE_WS, "window size");
-static_assert(K3<float>::EPT * K3<float>::SPJ == K3<float>::WS, "staging");
-static_assert(K3<double>::EPT * K3<double>::SPJ == K3<double>::WS, "staging");
 
-// element (line, slot) of the LDS tile
+// element (line, position) of the LDS tile
 template <typename T>
-__device__ __forceinline__ int tix(int line, int slot) {
-    return line * K3<T>::TP + slot;
+__device__ __forceinline__ int tix(int line, int pos) {
+    return line * K3<T>::TP + pos;
 }
+
+// Position of a window slot within its tile row.  Lane i's R slots keep their
+// own segment of the row, but the segment's 16-byte chunks are rotated by a
+// lane-dependent amount.  Unrotated, the 128-bit accesses of consecutive lanes
+// to their own segments (64 bytes in FP32, 128 in FP64) would meet in the same
+// LDS banks every second (every) lane; rotated, the lanes of any group of 8
+// (32 banks) or 16 (64 banks) consecutive lanes touch distinct banks, both for
+// their own segments and for consecutive chunks of a row.
+template <typename T> struct TMap {
+    static constexpr int R = K3<T>::R, VEC = 16 / (int)sizeof(T), NC = R / VEC;
+    static constexpr int S = NC == 4 ? 1 : 0, LNC = NC == 4 ? 2 : 3;
+    static_assert(NC == 4 || NC == 8, "segments of 64 or 128 bytes");
+    // chunk c of lane i's segment
+    __device__ static __forceinline__ int chunk(int i, int c) {
+        const int rot = ((i >> S) + (i >> (S + LNC))) & (NC - 1);
+        return i * R + ((c + rot) & (NC - 1)) * VEC;
+    }
+    // window slot sl
+    __device__ static __forceinline__ int slot(int sl) {
+        const int o = sl % R;
+        return chunk(sl / R, o / VEC) + o % VEC;
+    }
+};
 
 // Lane shifts across the whole wave: lane l receives lane l - 1 (shr) or
 // l + 1 (shl); lanes without a source receive 0.
@@ -126,6 +145,24 @@ __device__ __forceinline__ void bstore(double x, __amdgpu_buffer_rsrc_t r, int o
     using v2u = __attribute__((ext_vector_type(2))) unsigned;
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, off, 0, 0);
 }
+// scalar-offset forms: byte offset voff (per lane) + soff (uniform)
+__device__ __forceinline__ void bstore(float x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    using v2u = __attribute__((ext_vector_type(2))) unsigned;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, voff, soff, 0);
+}
+// 16-byte vectors
+using u32x4 = __attribute__((ext_vector_type(4))) unsigned;
+template <typename VT>
+__device__ __forceinline__ VT bload16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <typename VT>
+__device__ __forceinline__ void bstore16(VT v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+}
 
 constexpr double pow_na(int e) {   // (-alpha)^e
     double r = 1.0;
@@ -137,7 +174,15 @@ template <typename T, int METHOD> struct Line3 {
     using C = K3<T>;
     static constexpr int R = C::R, LPL = C::LPL, TS = C::TS;
     int i, h, s0, n;
-    bool first, last, bnd, lwin, rwin;
+    bool first, last, lwin, rwin;
+    // Lanes holding boundary rows.  The first window starts at slot 0 and the
+    // last one ends on the last slot of the line, so those rows sit at fixed
+    // positions: slots 0, 1 at positions 0, 1 of lane 0; slots n, n - 1 at the
+    // end of lane LPL - 1 (positions R - 1, R - 2 in the compact layout, where
+    // the last slot is n; R - 2, R - 3 in the mimetic one, one slot longer).
+    // Any other window reaches a boundary row only with its outermost slot,
+    // H slots from what it writes, like the truncation at its other edges.
+    bool bl, br;
 
     // neighbour values within the line (0 beyond the window)
     __device__ __forceinline__ T prev(T x) const {
@@ -165,23 +210,19 @@ template <typename T, int METHOD> struct Line3 {
             const T fm = k > 0 ? f[k - 1] : fl;
             o[k] = fp - fm;
         }
-        if (bnd) {
-            const T third = T(1.0 / 3.0);
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int s = s0 + k;
-                if (kind == 0) {
-                    if (s == 0 && k + 3 < R)
-                        o[k] = third * (T(-17) * f[k] + T(9) * f[k + 1] + T(9) * f[k + 2] - f[k + 3]);
-                    if (s == n && k >= 3)
-                        o[k] = third * (f[k - 3] - T(9) * f[k - 2] - T(9) * f[k - 1] + T(17) * f[k]);
-                } else {
-                    if (s == 0 || s == n) o[k] = T(0);
-                    if (s == 1 && k >= 1 && k + 2 < R)
-                        o[k] = third * (-f[k - 1] - T(9) * f[k] + T(9) * f[k + 1] + f[k + 2]);
-                    if (s == n - 1 && k >= 2 && k + 1 < R)
-                        o[k] = third * (-f[k - 2] - T(9) * f[k - 1] + T(9) * f[k] + f[k + 1]);
-                }
+        const T third = T(1.0 / 3.0);
+        constexpr int E = R - 1;   // slot n
+        if (kind == 0) {
+            if (bl) o[0] = third * (T(-17) * f[0] + T(9) * f[1] + T(9) * f[2] - f[3]);
+            if (br) o[E] = third * (f[E - 3] - T(9) * f[E - 2] - T(9) * f[E - 1] + T(17) * f[E]);
+        } else {
+            if (bl) {
+                o[0] = T(0);
+                o[1] = third * (-f[0] - T(9) * f[1] + T(9) * f[2] + f[3]);
+            }
+            if (br) {
+                o[E] = T(0);
+                o[E - 1] = third * (-f[E - 3] - T(9) * f[E - 2] + T(9) * f[E - 1] + f[E]);
             }
         }
     }
@@ -309,7 +350,7 @@ template <typename T, int METHOD> struct Line3 {
 template <typename T, int METHOD, int MODE>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
     using C = K3<T>;
-    constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW, SPJ = C::SPJ, EPT = C::EPT;
+    constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW;
     const int lg = tile % a.nlg, g = tile / a.nlg;
     const int n = a.n, ns = a.ns;
     const int uhi = METHOD == LINE_CFD ? n - 1 : n;
@@ -327,9 +368,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     L.s0 = w0 + L.i * R;
     L.first = L.i == 0;
     L.last = L.i == LPL - 1;
-    L.bnd = L.s0 <= 1 || L.s0 + R - 1 >= n - 1;
     L.lwin = w0 == 0;
     L.rwin = w0 + WS >= ns;
+    L.bl = L.lwin && L.first;
+    L.br = L.rwin && L.last;
     const int s0 = L.s0;
     // Line-major rows are indexed r = q + 1 (row 0: a line of zeros), so that
     // the LW rows of a workgroup map onto LW-aligned runs of the other
@@ -337,11 +379,6 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     const int ln = wave * C::LPW + L.h;          // row of this lane's line within the workgroup
     const int r = lg * LW + ln, q = r - 1;
     const bool qok = q >= 0 && q < a.nlines;
-
-    // staging map of the pressure output tile: thread -> row st_ln, slots st_sl + j SPJ
-    const int st_ln = tid % LW, st_sl = tid / LW;
-    const int st_r = lg * LW + st_ln;
-    const bool st_qok = st_r >= 1 && st_r <= a.nlines;
 
     // ---- loads: each lane reads its own segment of its line.  Line-major
     // arrays: element (row r, slot s) at r * ld + s, boundary slots stored
@@ -354,28 +391,67 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     // line l at tile row l; then every lane reads its segment
     constexpr int CPL = WS / VEC;                 // chunks per line
     constexpr int CPT = CPL * LW / C::NT;         // chunks per thread
-    static_assert(CPT * C::NT == CPL * LW, "chunking");
+    constexpr int RPJ = C::NT / CPL;              // lines covered by one staging step
+    static_assert(CPT * C::NT == CPL * LW && RPJ * CPL == C::NT, "chunking");
+    // Thread tid moves chunk tid % CPL of the lines tid / CPL + j RPJ.  The
+    // line-major arrays of this direction span nlg LW rows of ld elements;
+    // when that fits 31 bits they are accessed through buffer descriptors: a
+    // 32-bit lane offset plus a uniform row step.
+    const int64_t lm_rows = (int64_t)a.nlg * LW;
+    const int st_l = tid / CPL, st_c = tid % CPL;
     auto stage_in = [&](const T* base, int64_t ld, VT (&ch)[CPT]) {
+        const int64_t bytes = lm_rows * ld * (int64_t)sizeof(T);
+        if (bytes < kBufMax) {
+            const auto rs = make_rsrc(base, bytes);
+            const int vo = (int)(((int64_t)(lg * LW + st_l) * ld + w0 + st_c * VEC) * (int64_t)sizeof(T));
+            const int so = (int)((int64_t)RPJ * ld * (int64_t)sizeof(T));
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
-            ch[j] = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + l) * ld + w0 + sc * VEC);
+            for (int j = 0; j < CPT; ++j) ch[j] = bload16<VT>(rs, vo, j * so);
+        } else {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j)
+                ch[j] = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + st_l + j * RPJ) * ld + w0 + st_c * VEC);
         }
     };
+    using TM = TMap<T>;
+    constexpr int NC = TM::NC;
     auto stage_spread = [&](const VT (&ch)[CPT], T (&dst)[R]) {
         __syncthreads();   // earlier readers of the tile are done
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
-            *reinterpret_cast<VT*>(smem + tix<T>(l, sc * VEC)) = ch[j];
+            *reinterpret_cast<VT*>(smem + tix<T>(st_l + j * RPJ, TM::chunk(st_c / NC, st_c % NC))) = ch[j];
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < R; ++k) dst[k] = smem[tix<T>(ln, L.i * R + k)];
+        for (int c = 0; c < NC; ++c) {
+            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(ln, TM::chunk(L.i, c)));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) dst[c * VEC + e] = v[e];
+        }
+    };
+    // this lane's segment into its tile row
+    auto seg_to_tile = [&](const T (&src)[R]) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            VT v;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = src[c * VEC + e];
+            *reinterpret_cast<VT*>(smem + tix<T>(ln, TM::chunk(L.i, c))) = v;
+        }
     };
     auto seg_load = [&](const T* base, int64_t ld, T (&dst)[R]) {
         const T* p = base + (int64_t)r * ld + s0;
-        if (aligned) {
+        const int64_t bytes = lm_rows * ld * (int64_t)sizeof(T);
+        if (aligned && bytes < kBufMax) {
+            const auto rs = make_rsrc(base, bytes);
+            const int vo = (int)(((int64_t)r * ld + s0) * (int64_t)sizeof(T));
+#pragma unroll
+            for (int k = 0; k < R; k += VEC) {
+                const VT v = bload16<VT>(rs, vo + k * (int)sizeof(T), 0);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) dst[k + e] = v[e];
+            }
+        } else if (aligned) {
 #pragma unroll
             for (int k = 0; k < R; k += VEC) {
                 const VT v = *reinterpret_cast<const VT*>(p + k);
@@ -406,12 +482,24 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     }
     // scale folded into the material values (compact: 3 alpha / h; mimetic: 9 / (8 h))
     const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
+    // The material arrays hold zeros outside the interior of the lines (slot
+    // 0 and slots past the last unknown, row 0 and the padding rows), so
+    // only the constant values need the masks.
+    if (a.ak) {
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int s = s0 + k;
-        const bool uok = qok && s >= 1 && s <= uhi, vok = qok && s <= n;
-        KK[k] = uok ? sc * (a.ak ? KK[k] : a.ak0) : T(0);
-        RR[k] = vok ? sc * (a.ar ? RR[k] : a.ar0) : T(0);
+        for (int k = 0; k < R; ++k) KK[k] *= sc;
+    } else {
+        const T v = sc * a.ak0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) KK[k] = qok && s0 + k >= 1 && s0 + k <= uhi ? v : T(0);
+    }
+    if (a.ar) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) RR[k] *= sc;
+    } else {
+        const T v = sc * a.ar0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) RR[k] = qok && s0 + k <= n ? v : T(0);
     }
 
     if (METHOD == LINE_CFD) {
@@ -481,7 +569,8 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                           T(8997.0 / 16280.0), T(-2335.0 / 22792.0), T(25.0 / 9768.0)};
         const T g1c[5] = {T(16.0 / 105.0), T(-31.0 / 24.0), T(29.0 / 24.0), T(-3.0 / 40.0),
                           T(1.0 / 168.0)};
-        const bool bnd = L.bnd;
+        const bool bl = L.bl, br = L.br;
+        constexpr int E = R - 2;   // slot n (the mimetic line has one more slot, n + 1)
         // D'(v) on own slots; v given on positions -2..R
         auto applyD = [&](const T (&v)[R], T vm2, T vm1, T vp, T (&o)[R]) {
 #pragma unroll
@@ -491,23 +580,17 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 const T a3 = k + 1 < R ? v[k + 1] : vp;
                 o[k] = md(a2, a1, v[k], a3);
             }
-            if (bnd) {
+            if (bl) {   // slot 1
+                T acc = T(0);
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int s = s0 + k;
-                    if (s == 1 && k >= 1 && k + 4 < R) {
-                        T acc = T(0);
+                for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[c], acc);
+                o[1] = acc * ih8;
+            }
+            if (br) {   // slot n
+                T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[k - 1 + c], acc);
-                        o[k] = acc * ih8;
-                    }
-                    if (s == n && k >= 5) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[k - c], acc);
-                        o[k] = -acc * ih8;
-                    }
-                }
+                for (int c = 0; c < 6; ++c) acc = fma(d0c[c], v[E - c], acc);
+                o[E] = -acc * ih8;
             }
         };
         // G'(u) on own slots, u given on positions -3..R+2
@@ -515,35 +598,23 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             auto U_ = [&](int p) -> T { return p < 0 ? ul[3 + p] : (p < R ? u[p] : ur[p - R]); };
 #pragma unroll
             for (int k = 0; k < R; ++k) o[k] = mg(U_(k - 1), U_(k), U_(k + 1), U_(k + 2));
-            if (bnd) {
+            if (bl) {   // slots 0, 1
+                T acc0 = T(0), acc1 = T(0);
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int s = s0 + k;
-                    if (s == 0 && k + 5 < R) {
-                        T acc = T(0);
+                for (int c = 0; c < 6; ++c) acc0 = fma(g0c[c], u[c], acc0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc = fma(g0c[c], u[k + c], acc);
-                        o[k] = acc * ih8;
-                    }
-                    if (s == 1 && k >= 1 && k + 3 < R) {
-                        T acc = T(0);
+                for (int c = 0; c < 5; ++c) acc1 = fma(g1c[c], u[c], acc1);
+                o[0] = acc0 * ih8;
+                o[1] = acc1 * ih8;
+            }
+            if (br) {   // slots n - 1, n
+                T acc0 = T(0), acc1 = T(0);
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) acc = fma(g1c[c], u[k - 1 + c], acc);
-                        o[k] = acc * ih8;
-                    }
-                    if (s == n - 1 && k >= 2 && k + 2 < R) {
-                        T acc = T(0);
+                for (int c = 0; c < 6; ++c) acc0 = fma(g0c[c], u[E + 1 - c], acc0);
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) acc = fma(g1c[c], u[k + 2 - c], acc);
-                        o[k] = -acc * ih8;
-                    }
-                    if (s == n && k >= 4 && k + 1 < R) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int c = 0; c < 6; ++c) acc = fma(g0c[c], u[k + 1 - c], acc);
-                        o[k] = -acc * ih8;
-                    }
-                }
+                for (int c = 0; c < 5; ++c) acc1 = fma(g1c[c], u[E + 1 - c], acc1);
+                o[E] = -acc0 * ih8;
+                o[E - 1] = -acc1 * ih8;
             }
         };
         auto halo_u = [&](const T (&u)[R], T (&ul)[3], T (&ur)[3]) {
@@ -600,52 +671,84 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 
     // ---- stores through the LDS tile: velocity, then pressure ----
     if (MODE != LINE_FINAL) {
+        const int ks = a.src_s - s0;
+        if (q == a.src_q && ks >= 0 && ks < R) {   // one lane of the grid
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (q == a.src_q && s0 + k == a.src_s) U[k] += a.aF;
+            for (int k = 0; k < R; ++k)
+                if (k == ks) U[k] += a.aF;
+        }
     }
     // velocity into the line-major output (central slots only)
     if (C::SOUT && aligned) {
         __syncthreads();   // readers of the input tile are done
-#pragma unroll
-        for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = Tt[k];
+        seg_to_tile(Tt);
         __syncthreads();
+        // this thread's chunk column: whole, partly or not among the central slots
+        const int s = w0 + st_c * VEC;
+        const bool full = s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n;
+        const bool part = !full && s + VEC > c0 && s < c1;
+        const int64_t bytes = lm_rows * a.vout_ld * (int64_t)sizeof(T);
+        if (bytes < kBufMax) {
+            const auto rs = make_rsrc(a.vout, bytes);
+            const int vo = (int)(((int64_t)(lg * LW + st_l) * a.vout_ld + s) * (int64_t)sizeof(T));
+            const int so = (int)((int64_t)RPJ * a.vout_ld * (int64_t)sizeof(T));
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int c = tid + j * C::NT, l = c / CPL, sc = c % CPL;
-            const int s = w0 + sc * VEC, rr = lg * LW + l;
-            const bool ok = rr >= 1 && rr <= a.nlines;
-            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, sc * VEC));
-            T* p = a.vout + (int64_t)rr * a.vout_ld + s;
-            if (ok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
-                *reinterpret_cast<VT*>(p) = v;
-            } else if (ok) {
+            for (int j = 0; j < CPT; ++j) {
+                const int l = st_l + j * RPJ, rr = lg * LW + l;
+                if (rr < 1 || rr > a.nlines || !(full || part)) continue;
+                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, TM::chunk(st_c / NC, st_c % NC)));
+                if (full) {
+                    bstore16(v, rs, vo, j * so);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (s + e >= c0 && s + e < c1 && s + e <= n) bstore(v[e], rs, vo + e * (int)sizeof(T), j * so);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int l = st_l + j * RPJ, rr = lg * LW + l;
+                if (rr < 1 || rr > a.nlines || !(full || part)) continue;
+                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, TM::chunk(st_c / NC, st_c % NC)));
+                T* p = a.vout + (int64_t)rr * a.vout_ld + s;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     if (s + e >= c0 && s + e < c1 && s + e <= n) p[e] = v[e];
             }
         }
     } else {
-        T* p = a.vout + (int64_t)r * a.vout_ld + s0;
+        const int64_t bytes = lm_rows * a.vout_ld * (int64_t)sizeof(T);
+        if (aligned && bytes < kBufMax) {
+            const auto rs = make_rsrc(a.vout, bytes);
+            const int vo = (int)(((int64_t)r * a.vout_ld + s0) * (int64_t)sizeof(T));
 #pragma unroll
-        for (int k = 0; k < R; k += VEC) {
-            const int s = s0 + k;
-            if (aligned && qok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
-                VT v;
+            for (int k = 0; k < R; k += VEC) {
+                const int s = s0 + k;
+                if (qok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
+                    VT v;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) v[e] = Tt[k + e];
-                *reinterpret_cast<VT*>(p + k) = v;
-            } else {
+                    for (int e = 0; e < VEC; ++e) v[e] = Tt[k + e];
+                    bstore16(v, rs, vo + k * (int)sizeof(T), 0);
+                } else {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e)
-                    if (qok && s + e >= c0 && s + e < c1 && s + e <= n) p[k + e] = Tt[k + e];
+                    for (int e = 0; e < VEC; ++e)
+                        if (qok && s + e >= c0 && s + e < c1 && s + e <= n)
+                            bstore(Tt[k + e], rs, vo + (k + e) * (int)sizeof(T), 0);
+                }
+            }
+        } else {
+            T* p = a.vout + (int64_t)r * a.vout_ld + s0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int s = s0 + k;
+                if (qok && s >= c0 && s < c1 && s <= n) p[k] = Tt[k];
             }
         }
     }
     // pressure hand-off for the other direction, transposed through LDS
     __syncthreads();   // readers of the tile are done
-#pragma unroll
-    for (int k = 0; k < R; ++k) smem[tix<T>(ln, L.i * R + k)] = U[k];
+    seg_to_tile(U);
     __syncthreads();
     const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
     if (a.utrans) {
@@ -657,20 +760,47 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         if (qq >= 0 && qq < a.nlines && bytes < kBufMax) {
             const auto rs = make_rsrc(a.uout, bytes);
             int o = (qq * (int)a.uout_ld + lo + t2 - 1) * (int)sizeof(T);
-            for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, s - w0)], rs, o);
+            for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, TM::slot(s - w0))], rs, o);
         } else if (qq >= 0 && qq < a.nlines) {
             T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
-            for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, s - w0)];
+            for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, TM::slot(s - w0))];
         }
     } else {
         // uout[(s - 1) * ld + q + 1] (the caller passes the base one element
-        // lower): runs of LW consecutive elements starting at multiples of LW
-        T* p = a.uout + (int64_t)(w0 + st_sl - 1) * a.uout_ld + st_r;
-        const int64_t step = (int64_t)SPJ * a.uout_ld;
+        // lower).  Thread -> line pl, chunk columns pc + j PCJ: a chunk's VEC
+        // slots go to VEC rows of the target, the LW lines of the workgroup
+        // forming runs of LW consecutive elements that start on multiples of LW.
+        constexpr int PCJ = C::NT / LW;            // chunk columns per step
+        constexpr int PJ = CPL / PCJ;              // steps
+        static_assert(PJ * PCJ == CPL, "pressure chunking");
+        const int pl = tid % LW, pc = tid / LW;
+        const int rr = lg * LW + pl;               // q + 1
+        if (rr >= 1 && rr <= a.nlines) {
+            // elements the pass writes from uout: up to (uhi - 1) ld + nlines
+            const int64_t lim = ((int64_t)(uhi - 1) * a.uout_ld + a.nlines + 1) * (int64_t)sizeof(T);
+            const bool buf = lim < kBufMax;
+            const auto rs = make_rsrc(a.uout, buf ? lim : 0);
+            const int ldb = buf ? (int)(a.uout_ld * (int64_t)sizeof(T)) : 0;
+            const int rb = rr * (int)sizeof(T);
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int sl = st_sl + j * SPJ, s = w0 + sl;
-            if (st_qok && s >= lo && s <= hi) p[j * step] = smem[tix<T>(st_ln, sl)];
+            for (int j = 0; j < PJ; ++j) {
+                const int sc = pc + j * PCJ, s = w0 + sc * VEC;
+                if (s + VEC - 1 < lo || s > hi) continue;
+                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(pl, TM::chunk(sc / NC, sc % NC)));
+                if (buf && s >= lo && s + VEC - 1 <= hi) {
+                    const int o = (s - 1) * ldb + rb;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) bstore(v[e], rs, o, e * ldb);
+                } else if (buf) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (s + e >= lo && s + e <= hi) bstore(v[e], rs, (s + e - 1) * ldb + rb, 0);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (s + e >= lo && s + e <= hi) a.uout[(int64_t)(s + e - 1) * a.uout_ld + rr] = v[e];
+                }
+            }
         }
     }
 }
