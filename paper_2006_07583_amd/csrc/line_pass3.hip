@@ -810,10 +810,18 @@ __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
 line_pass3_kernel(const LinePassArgs<T> a) {
     __shared__ __align__(16) T smem[K3<T>::TILE];
+    // Each XCD takes a contiguous range of the ordered tiles.  FP32 orders
+    // them line group by line group (all windows of a group in turn), so every
+    // XCD gets an equal share of the last window: that window starts off the
+    // 16-byte grid, moves its data lane by lane and is the slowest, and in
+    // window order it would all land on one XCD.  FP64, whose last window
+    // costs little more than the others, keeps the window order, measured
+    // faster for it.
     const int nb = a.nlg * a.nwin;
     const int per = (nb + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (tile >= nb) return;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= nb) return;
+    const int tile = sizeof(T) == 4 ? (t % a.nwin) * a.nlg + t / a.nwin : t;
     lp3_body<T, METHOD, MODE>(a, tile, smem);
 }
 
