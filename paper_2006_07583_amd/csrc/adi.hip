@@ -76,12 +76,9 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.S = p.ns;
         p.deep = 1;
     } else {
-        // multi-window: the wave-per-line kernel for the compact scheme (its
-        // barrier-free solves pay for the staged loads) and for the mimetic
-        // scheme in FP64; the segment kernel for the mimetic scheme in FP32
-        // (shorter margins, so fewer wasted slots than the wave layout's) and
-        // for the compensated mode
-        p.ver = (dtype == ADI_FP32C || (method == ADI_MFD && dtype == ADI_FP32)) ? 2 : 3;
+        // multi-window: the wave-per-line kernel (barrier-free sweeps); the
+        // segment kernel for the compensated mode, which it alone implements
+        p.ver = dtype == ADI_FP32C ? 2 : 3;
         p.seg = adi::line2_seg(dtype);
         // windows of LINE_WS slots overlapping by 2H; the first and last own
         // LINE_WS - H central slots, the others S = LINE_WS - 2H
@@ -232,7 +229,9 @@ void derive(adi_problem* pb) {
         auto& D = pb->d[d];
         D.lm = pl.ver == 3;
         if (D.lm) {
-            D.ld = pad_to(pl.ns, padm);
+            // rows hold 3 slots past the last one: the wave-per-line kernel reads
+            // whole 16-byte chunks from a window start rounded down to the grid
+            D.ld = pad_to(pl.ns + 3, padm);
             D.rows_p = D.rows_v = pad_to(pl.nlines + 1, adi::line3_lanes(p.dtype));   // row = line + 1
         } else {
             D.ld = pad_to(pl.nlines, padm);

@@ -12,9 +12,14 @@
 //    moves between neighbouring lanes with DPP wave shifts: the sweep loop
 //    has no workgroup barrier and no LDS traffic, and the waves of a
 //    workgroup progress independently.
-//  * Global memory is read and written through an LDS tile per array, so
-//    that every access runs along the lines (the fast index of all the
-//    layouts): LW lines per workgroup, one contiguous run per slot.
+//  * The arrays of a direction are line-major (a line's slots contiguous,
+//    rows padded); every global access moves whole 16-byte chunks along
+//    the lines and passes through an LDS tile of the workgroup's LW lines,
+//    whose per-lane chunks are rotated so that lanes never share a bank.  A
+//    window that does not start on the 16-byte grid (the last one) is read
+//    from the grid slot below it and shifted in LDS.  The pressure handed to
+//    the other direction leaves the tile transposed, LW lines forming one
+//    contiguous run of the other layout.
 //  * Compact scheme: scaled unknowns, zero-carry segment solves, one
 //    carry combination per solve (constants of the interior factors), and a
 //    low-rank correction in the windows holding the first or last slot of
@@ -36,32 +41,19 @@
 #include "line_pass.h"
 #include "pass_common.h"
 
-#ifndef STAGE_IN_F32
-#define STAGE_IN_F32 true
-#define STAGE_OUT_F32 true
-#define STAGE_IN_F64 false
-#define STAGE_OUT_F64 false
-#endif
-
 namespace adi {
 
 template <typename T> struct Cfg3;
 // waves per workgroup, lines per wave, slots per lane, carry reach (segments), waves per SIMD
-// SIN / SOUT: inputs / velocity output staged through LDS in 16-byte chunks
-// along the lines (coalesced), else moved lane-direct (each lane its own
-// segment).
 template <> struct Cfg3<float> {
     static constexpr int NWV = 8, LPW = 2, R = 16, TS = 1, WPE = 4;
-    static constexpr bool SIN = STAGE_IN_F32, SOUT = STAGE_OUT_F32;
 };
 template <> struct Cfg3<double> {
     static constexpr int NWV = 4, LPW = 2, R = 16, TS = 2, WPE = 2;
-    static constexpr bool SIN = STAGE_IN_F64, SOUT = STAGE_OUT_F64;
 };
 
 template <typename T> struct K3 {
     static constexpr int NWV = Cfg3<T>::NWV, LPW = Cfg3<T>::LPW, R = Cfg3<T>::R, TS = Cfg3<T>::TS;
-    static constexpr bool SIN = Cfg3<T>::SIN, SOUT = Cfg3<T>::SOUT;
     static constexpr int LPL = 64 / LPW;          // lanes per line
     static constexpr int WS = LPL * R;             // slots per window
     static constexpr int LW = NWV * LPW;           // lines per workgroup
@@ -380,105 +372,125 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     const int r = lg * LW + ln, q = r - 1;
     const bool qok = q >= 0 && q < a.nlines;
 
-    // ---- loads: each lane reads its own segment of its line.  Line-major
-    // arrays: element (row r, slot s) at r * ld + s, boundary slots stored
-    // as zeros, rows padded to whole line groups; windows other than the last
-    // start on a multiple of the vector width (the margin H is even). ----
+    // ---- loads.  Line-major arrays: element (row r, slot s) at r * ld + s,
+    // boundary slots stored as zeros, rows padded to whole line groups and
+    // to at least 3 slots past the last one.  Staged: the LW lines of the
+    // workgroup are read in 16-byte chunks starting at the slot wa = w0 - sh
+    // on the 16-byte grid (sh = w0 mod VEC; only the last window has sh > 0,
+    // the margin H being even), chunk c of line l into tile row l at position
+    // c VEC (one extra chunk per line when sh > 0); lane i then takes its R
+    // slots from positions sh + i R. ----
     constexpr int VEC = 16 / (int)sizeof(T);
     using VT = T __attribute__((ext_vector_type(16 / sizeof(T))));
-    const bool aligned = (w0 % VEC) == 0;
-    // staged: 16-byte chunks along the LW lines of the workgroup, chunk c of
-    // line l at tile row l; then every lane reads its segment
+    const int sh = w0 % VEC, wa = w0 - sh;
     constexpr int CPL = WS / VEC;                 // chunks per line
     constexpr int CPT = CPL * LW / C::NT;         // chunks per thread
     constexpr int RPJ = C::NT / CPL;              // lines covered by one staging step
     static_assert(CPT * C::NT == CPL * LW && RPJ * CPL == C::NT, "chunking");
-    // Thread tid moves chunk tid % CPL of the lines tid / CPL + j RPJ.  The
-    // line-major arrays of this direction span nlg LW rows of ld elements;
-    // when that fits 31 bits they are accessed through buffer descriptors: a
-    // 32-bit lane offset plus a uniform row step.
+    static_assert(C::TP >= WS + VEC, "tile row holds the extra chunk");
+    // Thread tid moves chunk tid % CPL of the lines tid / CPL + j RPJ, and the
+    // extra chunk (tile position WS) of line tid when sh > 0 and tid < LW.
+    // The line-major arrays of this direction span nlg LW rows of ld
+    // elements; when that fits 31 bits they are accessed through buffer
+    // descriptors: a 32-bit lane offset plus a uniform row step.
     const int64_t lm_rows = (int64_t)a.nlg * LW;
     const int st_l = tid / CPL, st_c = tid % CPL;
-    auto stage_in = [&](const T* base, int64_t ld, VT (&ch)[CPT]) {
+    const bool xtra = sh != 0 && tid < LW;
+    using TM = TMap<T>;
+    constexpr int NC = TM::NC;
+    // tile position of the chunk after this lane's segment
+    const int nxt = L.i + 1 < LPL ? TM::chunk(L.i + 1, 0) : WS;
+    auto stage_in = [&](const T* base, int64_t ld, VT (&ch)[CPT], VT& ce) {
         const int64_t bytes = lm_rows * ld * (int64_t)sizeof(T);
         if (bytes < kBufMax) {
             const auto rs = make_rsrc(base, bytes);
-            const int vo = (int)(((int64_t)(lg * LW + st_l) * ld + w0 + st_c * VEC) * (int64_t)sizeof(T));
+            const int vo = (int)(((int64_t)(lg * LW + st_l) * ld + wa + st_c * VEC) * (int64_t)sizeof(T));
             const int so = (int)((int64_t)RPJ * ld * (int64_t)sizeof(T));
 #pragma unroll
             for (int j = 0; j < CPT; ++j) ch[j] = bload16<VT>(rs, vo, j * so);
+            if (xtra) ce = bload16<VT>(rs, (int)(((int64_t)(lg * LW + tid) * ld + wa + WS) * (int64_t)sizeof(T)), 0);
         } else {
 #pragma unroll
             for (int j = 0; j < CPT; ++j)
-                ch[j] = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + st_l + j * RPJ) * ld + w0 + st_c * VEC);
+                ch[j] = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + st_l + j * RPJ) * ld + wa + st_c * VEC);
+            if (xtra) ce = *reinterpret_cast<const VT*>(base + (int64_t)(lg * LW + tid) * ld + wa + WS);
         }
     };
-    using TM = TMap<T>;
-    constexpr int NC = TM::NC;
-    auto stage_spread = [&](const VT (&ch)[CPT], T (&dst)[R]) {
-        __syncthreads();   // earlier readers of the tile are done
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            *reinterpret_cast<VT*>(smem + tix<T>(st_l + j * RPJ, TM::chunk(st_c / NC, st_c % NC))) = ch[j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(ln, TM::chunk(L.i, c)));
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) dst[c * VEC + e] = v[e];
-        }
-    };
-    // this lane's segment into its tile row
-    auto seg_to_tile = [&](const T (&src)[R]) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            VT v;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = src[c * VEC + e];
-            *reinterpret_cast<VT*>(smem + tix<T>(ln, TM::chunk(L.i, c))) = v;
-        }
-    };
-    auto seg_load = [&](const T* base, int64_t ld, T (&dst)[R]) {
-        const T* p = base + (int64_t)r * ld + s0;
-        const int64_t bytes = lm_rows * ld * (int64_t)sizeof(T);
-        if (aligned && bytes < kBufMax) {
-            const auto rs = make_rsrc(base, bytes);
-            const int vo = (int)(((int64_t)r * ld + s0) * (int64_t)sizeof(T));
-#pragma unroll
-            for (int k = 0; k < R; k += VEC) {
-                const VT v = bload16<VT>(rs, vo + k * (int)sizeof(T), 0);
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) dst[k + e] = v[e];
+    // f(std::integral_constant<int, sh>) for the block's shift
+    auto with_shift = [&](auto&& f) {
+        if constexpr (VEC == 4) {
+            switch (sh) {
+                case 0: f(std::integral_constant<int, 0>{}); break;
+                case 1: f(std::integral_constant<int, 1>{}); break;
+                case 2: f(std::integral_constant<int, 2>{}); break;
+                default: f(std::integral_constant<int, 3>{}); break;
             }
-        } else if (aligned) {
+        } else {
+            if (sh == 0) f(std::integral_constant<int, 0>{});
+            else f(std::integral_constant<int, 1>{});
+        }
+    };
+    // this lane's R slots from its tile row (positions SH + i R ...)
+    auto read_seg = [&](auto shc, T (&dst)[R]) {
+        constexpr int SH = decltype(shc)::value;
+        constexpr int NR = SH ? NC + 1 : NC;
+        T el[NR * VEC];
 #pragma unroll
-            for (int k = 0; k < R; k += VEC) {
-                const VT v = *reinterpret_cast<const VT*>(p + k);
+        for (int c = 0; c < NR; ++c) {
+            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(ln, c < NC ? TM::chunk(L.i, c) : nxt));
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) dst[k + e] = v[e];
+            for (int e = 0; e < VEC; ++e) el[c * VEC + e] = v[e];
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) dst[k] = el[SH + k];
+    };
+    // this lane's R slots into its tile row; with a shift, the first and the
+    // last chunk are shared with the neighbouring lanes and written element-wise
+    auto write_seg = [&](auto shc, const T (&src)[R]) {
+        constexpr int SH = decltype(shc)::value;
+        T* row = smem + tix<T>(ln, 0);
+        if constexpr (SH == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                VT v;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = src[c * VEC + e];
+                *reinterpret_cast<VT*>(row + TM::chunk(L.i, c)) = v;
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < R; ++k) dst[k] = p[k];
+            for (int e = SH; e < VEC; ++e) row[TM::chunk(L.i, 0) + e] = src[e - SH];
+#pragma unroll
+            for (int c = 1; c < NC; ++c) {
+                VT v;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = src[c * VEC + e - SH];
+                *reinterpret_cast<VT*>(row + TM::chunk(L.i, c)) = v;
+            }
+#pragma unroll
+            for (int e = 0; e < SH; ++e) row[nxt + e] = src[R - SH + e];
         }
     };
+    auto stage_spread = [&](const VT (&ch)[CPT], const VT& ce, T (&dst)[R]) {
+        __syncthreads();   // earlier readers of the tile are done
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+            *reinterpret_cast<VT*>(smem + tix<T>(st_l + j * RPJ, TM::chunk(st_c / NC, st_c % NC))) = ch[j];
+        if (xtra) *reinterpret_cast<VT*>(smem + tix<T>(tid, WS)) = ce;
+        __syncthreads();
+        with_shift([&](auto shc) { read_seg(shc, dst); });
+    };
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
-    if (C::SIN && aligned) {
-        VT ca[CPT], cb[CPT], ck[CPT], cr[CPT];
-        stage_in(a.uin, a.uin_ld, ca);
-        stage_in(a.vin, a.vin_ld, cb);
-        if (a.ak) stage_in(a.ak, a.ak_ld, ck);
-        if (a.ar) stage_in(a.ar, a.ar_ld, cr);
-        stage_spread(ca, A);
-        stage_spread(cb, B);
-        if (a.ak) stage_spread(ck, KK);
-        if (a.ar) stage_spread(cr, RR);
-    } else {
-        seg_load(a.uin, a.uin_ld, A);
-        seg_load(a.vin, a.vin_ld, B);
-        if (a.ak) seg_load(a.ak, a.ak_ld, KK);
-        if (a.ar) seg_load(a.ar, a.ar_ld, RR);
+    {
+        VT ca[CPT], cb[CPT], ck[CPT], cr[CPT], ea{}, eb{}, ek{}, er{};
+        stage_in(a.uin, a.uin_ld, ca, ea);
+        stage_in(a.vin, a.vin_ld, cb, eb);
+        if (a.ak) stage_in(a.ak, a.ak_ld, ck, ek);
+        if (a.ar) stage_in(a.ar, a.ar_ld, cr, er);
+        stage_spread(ca, ea, A);
+        stage_spread(cb, eb, B);
+        if (a.ak) stage_spread(ck, ek, KK);
+        if (a.ar) stage_spread(cr, er, RR);
     }
     // scale folded into the material values (compact: 3 alpha / h; mimetic: 9 / (8 h))
     const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
@@ -679,78 +691,42 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         }
     }
     // velocity into the line-major output (central slots only)
-    if (C::SOUT && aligned) {
+    {
         __syncthreads();   // readers of the input tile are done
-        seg_to_tile(Tt);
+        with_shift([&](auto shc) { write_seg(shc, Tt); });
         __syncthreads();
-        // this thread's chunk column: whole, partly or not among the central slots
-        const int s = w0 + st_c * VEC;
-        const bool full = s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n;
-        const bool part = !full && s + VEC > c0 && s < c1;
         const int64_t bytes = lm_rows * a.vout_ld * (int64_t)sizeof(T);
-        if (bytes < kBufMax) {
-            const auto rs = make_rsrc(a.vout, bytes);
-            const int vo = (int)(((int64_t)(lg * LW + st_l) * a.vout_ld + s) * (int64_t)sizeof(T));
-            const int so = (int)((int64_t)RPJ * a.vout_ld * (int64_t)sizeof(T));
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int l = st_l + j * RPJ, rr = lg * LW + l;
-                if (rr < 1 || rr > a.nlines || !(full || part)) continue;
-                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, TM::chunk(st_c / NC, st_c % NC)));
-                if (full) {
-                    bstore16(v, rs, vo, j * so);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        if (s + e >= c0 && s + e < c1 && s + e <= n) bstore(v[e], rs, vo + e * (int)sizeof(T), j * so);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int l = st_l + j * RPJ, rr = lg * LW + l;
-                if (rr < 1 || rr > a.nlines || !(full || part)) continue;
-                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, TM::chunk(st_c / NC, st_c % NC)));
-                T* p = a.vout + (int64_t)rr * a.vout_ld + s;
+        const bool buf = bytes < kBufMax;
+        const auto rs = make_rsrc(a.vout, buf ? bytes : 0);
+        // chunk at tile position pos (slots s .. s + VEC - 1) of tile row l
+        auto put = [&](int l, int pos, int s) {
+            const int rr = lg * LW + l;
+            if (rr < 1 || rr > a.nlines || s + VEC <= c0 || s >= c1) return;
+            const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(l, pos));
+            const int64_t off = (int64_t)rr * a.vout_ld + s;
+            if (s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
+                if (buf) bstore16(v, rs, (int)(off * (int64_t)sizeof(T)), 0);
+                else *reinterpret_cast<VT*>(a.vout + off) = v;
+            } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    if (s + e >= c0 && s + e < c1 && s + e <= n) p[e] = v[e];
+                    if (s + e >= c0 && s + e < c1 && s + e <= n) {
+                        if (buf) bstore(v[e], rs, (int)((off + e) * (int64_t)sizeof(T)));
+                        else a.vout[off + e] = v[e];
+                    }
             }
-        }
-    } else {
-        const int64_t bytes = lm_rows * a.vout_ld * (int64_t)sizeof(T);
-        if (aligned && bytes < kBufMax) {
-            const auto rs = make_rsrc(a.vout, bytes);
-            const int vo = (int)(((int64_t)r * a.vout_ld + s0) * (int64_t)sizeof(T));
+        };
 #pragma unroll
-            for (int k = 0; k < R; k += VEC) {
-                const int s = s0 + k;
-                if (qok && s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
-                    VT v;
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) v[e] = Tt[k + e];
-                    bstore16(v, rs, vo + k * (int)sizeof(T), 0);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        if (qok && s + e >= c0 && s + e < c1 && s + e <= n)
-                            bstore(Tt[k + e], rs, vo + (k + e) * (int)sizeof(T), 0);
-                }
-            }
-        } else {
-            T* p = a.vout + (int64_t)r * a.vout_ld + s0;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int s = s0 + k;
-                if (qok && s >= c0 && s < c1 && s <= n) p[k] = Tt[k];
-            }
-        }
+        for (int j = 0; j < CPT; ++j) put(st_l + j * RPJ, TM::chunk(st_c / NC, st_c % NC), wa + st_c * VEC);
+        if (xtra) put(tid, WS, wa + WS);
     }
     // pressure hand-off for the other direction, transposed through LDS
     __syncthreads();   // readers of the tile are done
-    seg_to_tile(U);
+    with_shift([&](auto shc) { write_seg(shc, U); });
     __syncthreads();
     const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
+    // tile position of window position p (slot wa + p)
+    auto tpos = [&](int p) { return p < WS ? TM::slot(p) : p; };
     if (a.utrans) {
         // uout[q * ld + (s - 1)]: TPL consecutive threads along the slots of a line
         constexpr int TPL = C::TPL;
@@ -760,10 +736,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         if (qq >= 0 && qq < a.nlines && bytes < kBufMax) {
             const auto rs = make_rsrc(a.uout, bytes);
             int o = (qq * (int)a.uout_ld + lo + t2 - 1) * (int)sizeof(T);
-            for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, TM::slot(s - w0))], rs, o);
+            for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, tpos(s - wa))], rs, o);
         } else if (qq >= 0 && qq < a.nlines) {
             T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
-            for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, TM::slot(s - w0))];
+            for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, tpos(s - wa))];
         }
     } else {
         // uout[(s - 1) * ld + q + 1] (the caller passes the base one element
@@ -782,11 +758,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             const auto rs = make_rsrc(a.uout, buf ? lim : 0);
             const int ldb = buf ? (int)(a.uout_ld * (int64_t)sizeof(T)) : 0;
             const int rb = rr * (int)sizeof(T);
-#pragma unroll
-            for (int j = 0; j < PJ; ++j) {
-                const int sc = pc + j * PCJ, s = w0 + sc * VEC;
-                if (s + VEC - 1 < lo || s > hi) continue;
-                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(pl, TM::chunk(sc / NC, sc % NC)));
+            // chunk at tile position pos of row pl: slots s .. s + VEC - 1
+            auto put = [&](int pos, int s) {
+                if (s + VEC - 1 < lo || s > hi) return;
+                const VT v = *reinterpret_cast<const VT*>(smem + tix<T>(pl, pos));
                 if (buf && s >= lo && s + VEC - 1 <= hi) {
                     const int o = (s - 1) * ldb + rb;
 #pragma unroll
@@ -800,28 +775,33 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                     for (int e = 0; e < VEC; ++e)
                         if (s + e >= lo && s + e <= hi) a.uout[(int64_t)(s + e - 1) * a.uout_ld + rr] = v[e];
                 }
+            };
+#pragma unroll
+            for (int j = 0; j < PJ; ++j) {
+                const int sc = pc + j * PCJ;
+                put(TM::chunk(sc / NC, sc % NC), wa + sc * VEC);
             }
+            if (sh != 0 && pc == 0) put(WS, wa + WS);
         }
     }
 }
+
+template <typename T, int METHOD>
+constexpr bool kGroupOrder = METHOD == LINE_CFD || sizeof(T) == 4;
 
 template <typename T, int METHOD, int MODE>
 __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
 line_pass3_kernel(const LinePassArgs<T> a) {
     __shared__ __align__(16) T smem[K3<T>::TILE];
-    // Each XCD takes a contiguous range of the ordered tiles.  FP32 orders
-    // them line group by line group (all windows of a group in turn), so every
-    // XCD gets an equal share of the last window: that window starts off the
-    // 16-byte grid, moves its data lane by lane and is the slowest, and in
-    // window order it would all land on one XCD.  FP64, whose last window
-    // costs little more than the others, keeps the window order, measured
-    // faster for it.
+    // Each XCD takes a contiguous range of the ordered tiles: line group by
+    // line group (all windows of a group in turn) or window by window,
+    // whichever measured faster for the variant.
     const int nb = a.nlg * a.nwin;
     const int per = (nb + 7) / 8;
     const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (t >= nb) return;
-    const int tile = sizeof(T) == 4 ? (t % a.nwin) * a.nlg + t / a.nwin : t;
+    const int tile = kGroupOrder<T, METHOD> ? (t % a.nwin) * a.nlg + t / a.nwin : t;
     lp3_body<T, METHOD, MODE>(a, tile, smem);
 }
 
