@@ -358,8 +358,7 @@ def main():
                      "frac": rd["gbs"] / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if (dom == adi.CFD and head == adi.FP32 and n == 4096) else None,
                      "traffic_unit": "bytes per launch (counters)", "alg_bytes": rd["alg_bytes_pass"],
-                     "kernel": (f"{'line_pass3_kernel' if dom == 0 else 'line_pass2_kernel'}<"
-                                f"{'float' if head == adi.FP32 else 'double'}, {dom}, SWEEP> "
+                     "kernel": (f"line_pass3_kernel<{'float' if head == adi.FP32 else 'double'}, {dom}, SWEEP> "
                                 f"({'compact' if dom == 0 else 'mimetic'} line pass)")},
         "variants": variants,
     }
