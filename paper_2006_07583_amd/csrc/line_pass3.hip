@@ -45,8 +45,11 @@ namespace adi {
 
 template <typename T> struct Cfg3;
 // waves per workgroup, lines per wave, slots per lane, carry reach (segments), waves per SIMD
+// (FP32: four workgroups of 4 waves per CU at 116 registers overlap the
+// staging rounds of one with the sweeps of the others better than two of 8
+// waves; the transposed pressure runs are then 8 lines, 32 bytes, long.)
 template <> struct Cfg3<float> {
-    static constexpr int NWV = 8, LPW = 2, R = 16, TS = 1, WPE = 4;
+    static constexpr int NWV = 4, LPW = 2, R = 16, TS = 1, WPE = 4;
 };
 template <> struct Cfg3<double> {
     static constexpr int NWV = 4, LPW = 2, R = 16, TS = 2, WPE = 2;
