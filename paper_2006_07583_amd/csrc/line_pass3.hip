@@ -99,9 +99,9 @@ template <typename T> struct TMap {
 };
 
 // Lane shifts across the whole wave: lane l receives lane l - 1 (shr) or
-// l + 1 (shl); lanes without a source receive 0.
-__device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false); }
+// l + 1 (shl); lanes without a source receive 0 (bound control).
+__device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float wshr(float x) { return __int_as_float(dpp_shr1(__float_as_int(x))); }
 __device__ __forceinline__ float wshl(float x) { return __int_as_float(dpp_shl1(__float_as_int(x))); }
 __device__ __forceinline__ double wshr(double x) {
@@ -205,6 +205,7 @@ template <typename T, int METHOD> struct Line3 {
             const T fm = k > 0 ? f[k - 1] : fl;
             o[k] = fp - fm;
         }
+        if (!(lwin || rwin)) return;   // uniform: only the end windows hold boundary rows
         const T third = T(1.0 / 3.0);
         constexpr int E = R - 1;   // slot n
         if (kind == 0) {
@@ -235,6 +236,9 @@ template <typename T, int METHOD> struct Line3 {
         constexpr Resp<R> rs{};
         const T G = T(rs.G);
         const T rawf = o[0], rawl = o[R - 1];
+        // The shifted values below are used as they come off the lane shift
+        // (at a line's first / last lane they belong to the other line of the
+        // wave); the line-edge masks are applied once, to the results.
         const T y1 = prev(yend);
         T Y = y1, Ym = T(0);
         if (TS > 1) {
@@ -242,17 +246,18 @@ template <typename T, int METHOD> struct Line3 {
             Y = fma(G, Ym, Y);
         }
         const T Yv = fma(G, Y, yend);            // forward carry into the next lane
-        const T nf = next(rawf);
+        const T nf = wshl(rawf);
         T X = last ? T(0) : fma(T(rs.a[0]), Yv, nf);
         if (TS > 1) {
-            const T Yv2 = fma(G, Yv, next(yend));
-            const T nf2 = next(nf);
+            const T Yv2 = fma(G, Yv, wshl(yend));
+            const T nf2 = wshl(nf);
             X = i < LPL - 2 ? fma(T(rs.b[0]), fma(T(rs.a[0]), Yv2, nf2), X) : X;
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) o[k] = fma(T(rs.a[k]), Y, fma(T(rs.b[k]), X, o[k]));
-        const T pl = prev(rawl);
-        xl = first ? T(0) : fma(T(rs.b[R - 1]), o[0], fma(T(rs.a[R - 1]), Ym, pl));
+        const T pl = wshr(rawl);
+        const T xl0 = TS > 1 ? fma(T(rs.a[R - 1]), Ym, pl) : pl;
+        xl = first ? T(0) : fma(T(rs.b[R - 1]), o[0], xl0);
         xr = X;
         if (lwin || rwin) correct(kind, o, xl, xr);
     }
@@ -595,6 +600,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 const T a3 = k + 1 < R ? v[k + 1] : vp;
                 o[k] = md(a2, a1, v[k], a3);
             }
+            if (!(L.lwin || L.rwin)) return;   // uniform: only the end windows hold boundary rows
             if (bl) {   // slot 1
                 T acc = T(0);
 #pragma unroll
@@ -613,6 +619,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             auto U_ = [&](int p) -> T { return p < 0 ? ul[3 + p] : (p < R ? u[p] : ur[p - R]); };
 #pragma unroll
             for (int k = 0; k < R; ++k) o[k] = mg(U_(k - 1), U_(k), U_(k + 1), U_(k + 2));
+            if (!(L.lwin || L.rwin)) return;   // uniform: only the end windows hold boundary rows
             if (bl) {   // slots 0, 1
                 T acc0 = T(0), acc1 = T(0);
 #pragma unroll

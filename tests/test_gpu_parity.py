@@ -195,6 +195,21 @@ _EDGES = {adi.CFD: [127, 128, 255, 256, 511, 512], adi.MFD: [126, 127, 254, 255,
 
 
 @pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("shift", range(4))
+@pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
+def test_last_window_off_grid(method, shift, dtype):
+    """Lines just over one window: the last window starts `shift` slots past
+    a multiple of 4 (its chunks are read from the grid slot below and shifted),
+    for every shift, both layouts' roles and both methods."""
+    ns0 = 512 + 4 + shift                      # line slots: n + 1 (CFD), n + 2 (MFD)
+    n = ns0 - (1 if method == adi.CFD else 2)
+    tol = TOL64 if dtype == adi.FP64 else TOL32
+    for nx, ny in ((n, 12), (12, n)):
+        errs = compare(method, dtype, nx, ny, seed=90 + shift, nsteps=3, cfl=0.6)
+        assert max(errs) <= tol, (nx, ny, errs)
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
 @pytest.mark.parametrize("k", range(6))
 @pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
 def test_window_shape_boundaries(method, k, dtype):
