@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # size); valid while the sources that define that kernel are unchanged.
 COUNTERS = os.path.join(HERE, "profiles", "line_pass3_cfd_fp32_4096_counters.txt")
 KERNEL_FILES = ["line_pass3.hip", "line_consts.h", "pass_common.h", "line_pass.h", "line_pass.hip", "adi.hip",
-                "problem.h"]
+                "problem.h", "tile_map.h"]
 
 
 def counter_traffic():

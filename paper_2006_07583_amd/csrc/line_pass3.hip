@@ -40,6 +40,7 @@
 #include "line_consts.h"
 #include "line_pass.h"
 #include "pass_common.h"
+#include "tile_map.h"
 
 namespace adi {
 
@@ -75,28 +76,8 @@ __device__ __forceinline__ int tix(int line, int pos) {
     return line * K3<T>::TP + pos;
 }
 
-// Position of a window slot within its tile row.  Lane i's R slots keep their
-// own segment of the row, but the segment's 16-byte chunks are rotated by a
-// lane-dependent amount.  Unrotated, the 128-bit accesses of consecutive lanes
-// to their own segments (64 bytes in FP32, 128 in FP64) would meet in the same
-// LDS banks every second (every) lane; rotated, the lanes of any group of 8
-// (32 banks) or 16 (64 banks) consecutive lanes touch distinct banks, both for
-// their own segments and for consecutive chunks of a row.
-template <typename T> struct TMap {
-    static constexpr int R = K3<T>::R, VEC = 16 / (int)sizeof(T), NC = R / VEC;
-    static constexpr int S = NC == 4 ? 1 : 0, LNC = NC == 4 ? 2 : 3;
-    static_assert(NC == 4 || NC == 8, "segments of 64 or 128 bytes");
-    // chunk c of lane i's segment
-    __device__ static __forceinline__ int chunk(int i, int c) {
-        const int rot = ((i >> S) + (i >> (S + LNC))) & (NC - 1);
-        return i * R + ((c + rot) & (NC - 1)) * VEC;
-    }
-    // window slot sl
-    __device__ static __forceinline__ int slot(int sl) {
-        const int o = sl % R;
-        return chunk(sl / R, o / VEC) + o % VEC;
-    }
-};
+// Tile-row positions of the window slots (chunks rotated per lane, tile_map.h).
+template <typename T> using TMap = TileMap<K3<T>::R, (int)sizeof(T)>;
 
 // Lane shifts across the whole wave: lane l receives lane l - 1 (shr) or
 // l + 1 (shl); lanes without a source receive 0 (bound control).
