@@ -68,6 +68,9 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_run.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_run_eps.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+        lib.oracle_run_eps.restype = ctypes.c_int
         lib.oracle_source.argtypes = [ctypes.POINTER(_Params), ctypes.c_double]
         lib.oracle_source.restype = ctypes.c_double
         for name in ("oracle_cfd_d", "oracle_cfd_dbar", "oracle_mfd_g", "oracle_mfd_d"):
@@ -144,6 +147,30 @@ def run(method, U, V, W, *, h, dt, nsteps, sweeps=6, K=None, Rv=None, Rw=None,
     if rc != 0:
         raise ValueError("oracle_run rejected its arguments")
     return U, V, W
+
+
+def run_eps(method, U, V, W, *, h, dt, nsteps, eps, min_sweeps=2, sweeps=16, K=None, Rv=None,
+            Rw=None, order=0, src=None, t0=0.0, kappa0=1.0, rinv0=1.0, threads=0):
+    """As :func:`run`, with the tolerance test of Algorithms 3 and 4 instead
+    of a fixed sweep count (``sweeps`` is then the cap).  Returns
+    (U, V, W, used) with ``used[2 m + s]`` the sweeps of stage s of step m."""
+    ny = U.shape[0] - (1 if method == CFD else 2)
+    nx = U.shape[1] - (1 if method == CFD else 2)
+    sh = shapes(method, nx, ny)
+    U = _f64(U, sh["U"], "U").copy()
+    V = _f64(V, sh["V"], "V").copy()
+    W = _f64(W, sh["W"], "W").copy()
+    K = None if K is None else _f64(K, sh["K"], "K")
+    Rv = None if Rv is None else _f64(Rv, sh["Rv"], "Rv")
+    Rw = None if Rw is None else _f64(Rw, sh["Rw"], "Rw")
+    p = make_params(method, nx, ny, h, dt, sweeps, order, src, t0, kappa0, rinv0, threads)
+    used = np.zeros(2 * int(nsteps), dtype=np.int32)
+    rc = _load().oracle_run_eps(ctypes.byref(p), _ptr(U), _ptr(V), _ptr(W), _ptr(K), _ptr(Rv), _ptr(Rw),
+                                int(nsteps), float(eps), int(min_sweeps),
+                                used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc != 0:
+        raise ValueError("oracle_run_eps rejected its arguments")
+    return U, V, W, used
 
 
 def source_value(src, h, t):

@@ -48,7 +48,14 @@
  *   - W* and V^{m+1} apply G to the full pressure line (boundary values
  *     included);
  *   - the second-stage iteration starts from W* (the algorithm text), not W^m;
- *   - exactly `sweeps` fixed-point sweeps per stage (no tolerance test).
+ *   - exactly `sweeps` fixed-point sweeps per stage (oracle_run), or the
+ *     tolerance test of Algorithms 3 and 4 (oracle_run_eps): after sweep k,
+ *     k >= min_sweeps, the change of the whole stage
+ *       ||Ubar_k - Ubar_{k-1}||_F + ||vel_k - vel_{k-1}||_F
+ *     is compared with eps; the first count that passes is rounded up to an
+ *     even count (odd counts amplify the unconverged modes) and `sweeps` is
+ *     the cap.  The first test comes after the second sweep at the earliest,
+ *     as the paper's GPU codes also run a minimum number of sweeps first.
  *
  * Built with -O2 -ffp-contract=off and no fast-math so every operation is
  * rounded as written.
@@ -316,7 +323,10 @@ typedef struct {
  * and explicit direction e = 1-d, forcing value F at the source point.
  * Stage (d = x) is eq. ecua2:PR solved through eqs. ecua1:ADI / adiSolve;
  * stage (d = y) is eq. ecua3:PR solved through eq. adiSolve2. */
-static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads) {
+static void implicit_eps(problem* pb, int d, int sweeps, int nthreads, double eps, int min_sweeps, int32_t* used);
+
+static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads, double eps, int min_sweeps,
+                  int32_t* used) {
     const int e = 1 - d;
     const int method = pb->method;
     const double a = pb->a;
@@ -364,6 +374,12 @@ static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads) {
         free(ubuf); free(vbuf); free(tmp);
     }
 
+    if (eps > 0.0) {
+        implicit_eps(pb, d, sweeps, nthreads, eps, min_sweeps, used);
+        return;
+    }
+    if (used) *used = sweeps;
+
     /* ---- implicit part along direction d: fixed-point sweeps per line ---- */
 #pragma omp parallel num_threads(nthreads)
     {
@@ -403,6 +419,78 @@ static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads) {
 #undef RU_AT
 }
 
+/* Implicit part along direction d with the tolerance test (Algorithms 3
+ * and 4): every line advances one sweep at a time, and after each sweep the
+ * Frobenius norms of the changes of the whole stage are summed and tested. */
+static void implicit_eps(problem* pb, int d, int sweeps, int nthreads, double eps, int min_sweeps, int32_t* used) {
+    const int e = 1 - d;
+    const int method = pb->method;
+    const double a = pb->a;
+    const int nd = d == 0 ? pb->nx : pb->ny;
+    const line_ops* od = d == 0 ? &pb->ox : &pb->oy;
+    field* vel_d = d == 0 ? &pb->V : &pb->W;
+    const field* R_d = d == 0 ? &pb->Rv : &pb->Rw;
+    const int ne = e == 0 ? pb->nx : pb->ny;
+    const int niu_d = n_uint(method, nd), niu_e = n_uint(method, ne);
+    const int nfu_d = n_ufull(method, nd);
+    const int ni_x = n_uint(method, pb->nx);
+    const double* RU = pb->RU;
+    /* state of every line: interior pressure iterate, velocity iterate, and
+     * the velocity the stage started from */
+    double* Ub = calloc((size_t)niu_e * (size_t)niu_d, sizeof(double));
+    double* Vk = malloc(sizeof(double) * (size_t)niu_e * (size_t)(nd + 1));
+    double* V0 = malloc(sizeof(double) * (size_t)niu_e * (size_t)(nd + 1));
+    for (int l = 1; l <= niu_e; ++l) {
+        gather(vel_d, d, l, 0, nd + 1, V0 + (size_t)(l - 1) * (nd + 1));
+        gather(vel_d, d, l, 0, nd + 1, Vk + (size_t)(l - 1) * (nd + 1));
+    }
+    int k = 0, last = sweeps;
+    while (k < last) {
+        double su = 0.0, sv = 0.0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : su, sv)
+        {
+            double* ubuf = malloc(sizeof(double) * (size_t)(nfu_d + 2));
+            double* tmp = malloc(sizeof(double) * (size_t)(nd + 2));
+#pragma omp for schedule(static)
+            for (int l = 1; l <= niu_e; ++l) {
+                double* ub = Ub + (size_t)(l - 1) * niu_d;
+                double* vk = Vk + (size_t)(l - 1) * (nd + 1);
+                const double* v0 = V0 + (size_t)(l - 1) * (nd + 1);
+                /* Ubar_k = R_U - a K .* Dbar_d(vel_{k-1}) */
+                deriv_D(od, vk, tmp);
+                gather(&pb->U, d, l, 0, nfu_d, ubuf);   /* boundary values */
+                for (int q = 1; q <= niu_d; ++q) {
+                    int j = d == 0 ? l : q, i = d == 0 ? q : l;
+                    double kap = mat(&pb->K, d, l, q, pb->kappa0);
+                    double un = RU[(size_t)(j - 1) * ni_x + (i - 1)] - a * kap * tmp[q - 1];
+                    su += (un - ub[q - 1]) * (un - ub[q - 1]);
+                    ub[q - 1] = un;
+                    ubuf[q] = un;
+                }
+                /* vel_k = vel_d - a R_d .* G_d(U_k) */
+                deriv_G(od, ubuf, tmp);
+                for (int q = 0; q <= nd; ++q) {
+                    double r = mat(R_d, d, l, q, pb->rinv0);
+                    double vn = v0[q] - a * r * tmp[q];
+                    sv += (vn - vk[q]) * (vn - vk[q]);
+                    vk[q] = vn;
+                }
+            }
+            free(ubuf); free(tmp);
+        }
+        ++k;
+        /* the change of the first sweep has no earlier iterate of Ubar */
+        if (last == sweeps && k >= min_sweeps && k >= 2 && sqrt(su) + sqrt(sv) <= eps)
+            last = k + (k & 1);   /* round up to even */
+    }
+    for (int l = 1; l <= niu_e; ++l) {
+        scatter(&pb->U, d, l, 1, niu_d, Ub + (size_t)(l - 1) * niu_d);
+        scatter(vel_d, d, l, 0, nd + 1, Vk + (size_t)(l - 1) * (nd + 1));
+    }
+    if (used) *used = last;
+    free(Ub); free(Vk); free(V0);
+}
+
 static int check_params(const oracle_params* p) {
     if (!p) return -1;
     if (p->method != ORC_CFD && p->method != ORC_MFD) return -1;
@@ -413,10 +501,9 @@ static int check_params(const oracle_params* p) {
     return 0;
 }
 
-/* Advance (U, V, W) by nsteps Peaceman-Rachford steps in place.
- * Step m runs from t0 + m dt to t0 + (m+1) dt.  Returns 0 or -1. */
-int oracle_run(const oracle_params* p, double* U, double* V, double* W,
-               const double* K, const double* Rv, const double* Rw, int64_t nsteps) {
+static int run_impl(const oracle_params* p, double* U, double* V, double* W, const double* K,
+                    const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
+                    int32_t* used) {
     if (check_params(p) || !U || !V || !W || nsteps < 0) return -1;
     problem pb;
     memset(&pb, 0, sizeof(pb));
@@ -451,18 +538,38 @@ int oracle_run(const oracle_params* p, double* U, double* V, double* W,
         double tm = p->t0 + (double)s * p->dt, tm1 = p->t0 + (double)(s + 1) * p->dt;
         double Fm = has_src ? ricker(tm, p->src_f0, p->src_t0, p->src_amp) / h2 : 0.0;
         double Fm1 = has_src ? ricker(tm1, p->src_f0, p->src_t0, p->src_amp) / h2 : 0.0;
+        int32_t* u0 = used ? used + 2 * s : NULL;
+        int32_t* u1 = used ? used + 2 * s + 1 : NULL;
         if (p->order == 0) {
-            stage(&pb, 0, Fm, p->sweeps, nthreads);
-            stage(&pb, 1, Fm1, p->sweeps, nthreads);
+            stage(&pb, 0, Fm, p->sweeps, nthreads, eps, min_sweeps, u0);
+            stage(&pb, 1, Fm1, p->sweeps, nthreads, eps, min_sweeps, u1);
         } else {
-            stage(&pb, 1, Fm, p->sweeps, nthreads);
-            stage(&pb, 0, Fm1, p->sweeps, nthreads);
+            stage(&pb, 1, Fm, p->sweeps, nthreads, eps, min_sweeps, u0);
+            stage(&pb, 0, Fm1, p->sweeps, nthreads, eps, min_sweeps, u1);
         }
     }
     free(pb.RU);
     line_ops_free(&pb.ox);
     line_ops_free(&pb.oy);
     return 0;
+}
+
+/* Advance (U, V, W) by nsteps Peaceman-Rachford steps in place, exactly
+ * `sweeps` sweeps per stage.  Step m runs from t0 + m dt to t0 + (m+1) dt.
+ * Returns 0 or -1. */
+int oracle_run(const oracle_params* p, double* U, double* V, double* W,
+               const double* K, const double* Rv, const double* Rw, int64_t nsteps) {
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL);
+}
+
+/* As oracle_run, with the tolerance test: eps > 0, min_sweeps even in
+ * [2, sweeps].  used (NULL or 2 nsteps entries) receives the sweep count of
+ * each stage in order. */
+int oracle_run_eps(const oracle_params* p, double* U, double* V, double* W, const double* K,
+                   const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
+                   int32_t* used) {
+    if (!(eps > 0.0) || min_sweeps < 2 || (min_sweeps & 1) || !p || min_sweeps > p->sweeps) return -1;
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used);
 }
 
 /* Ricker source value F(t) = s(t) / h^2 as the oracle applies it. */

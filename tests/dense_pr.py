@@ -80,3 +80,47 @@ class DenseProblem:
             Uk = C - a * (self.DUy @ Wk)
             Wk = Ws - a * (self.DWy @ Uk)
         return np.concatenate([Uk, Vn, Wk])
+
+    def step_eps(self, z, Fm, Fm1, eps, min_sweeps, cap):
+        """Both stages with the tolerance test of Algorithms 3 and 4: after
+        sweep k >= max(2, min_sweeps), stop once ||U_k - U_{k-1}|| +
+        ||vel_k - vel_{k-1}|| <= eps (Frobenius norms over the stage), the
+        count rounded up to even, at most `cap`.  Returns (z, [k1, k2])."""
+        a = self.a
+
+        def sweeps(Arhs, vel0, DU, DV):
+            Vk = vel0.copy()
+            Uk = np.zeros(self.nu)
+            k, last = 0, cap
+            while k < last:
+                Un = Arhs - a * (DU @ Vk)
+                Vn = vel0 - a * (DV @ Un)
+                d = np.linalg.norm(Un - Uk) + np.linalg.norm(Vn - Vk)
+                Uk, Vk, k = Un, Vn, k + 1
+                if last == cap and k >= max(2, min_sweeps) and d <= eps:
+                    last = k + (k & 1)
+            return Uk, Vk, last
+
+        U, V, W = (x.ravel() for x in self.unpack(z))
+        A = U - a * (self.DUy @ W) + a * Fm.ravel()
+        Ws = W - a * (self.DWy @ U)
+        Us, Vs, k1 = sweeps(A, V, self.DUx, self.DVx)
+        C = Us - a * (self.DUx @ Vs) + a * Fm1.ravel()
+        Vn = Vs - a * (self.DVx @ Us)
+        Uk, Wk, k2 = sweeps(C, Ws, self.DUy, self.DWy)
+        return np.concatenate([Uk, Vn, Wk]), [k1, k2]
+
+    def stage1_changes(self, z, Fm, n):
+        """||U_k - U_{k-1}|| + ||V_k - V_{k-1}|| of the first stage for
+        k = 1..n (U_0 = 0)."""
+        a = self.a
+        U, V, W = (x.ravel() for x in self.unpack(z))
+        A = U - a * (self.DUy @ W) + a * Fm.ravel()
+        Vk, Uk, out = V.copy(), np.zeros(self.nu), []
+        for _ in range(n):
+            Un = A - a * (self.DUx @ Vk)
+            Vn = V - a * (self.DVx @ Un)
+            out.append(np.linalg.norm(Un - Uk) + np.linalg.norm(Vn - Vk))
+            Uk, Vk = Un, Vn
+        return out
+

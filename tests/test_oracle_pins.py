@@ -429,3 +429,59 @@ def test_ricker_source_closed_form():
     vals = np.array([O.source_value(src, h, t) for t in ts])
     assert abs(np.trapezoid(vals, ts)) < 1e-9
     assert np.abs(vals - vals[::-1]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- tolerance test (stop rule)
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_eps_mode_matches_dense_stop_rule(method):
+    """The tolerance test of Algorithms 3 and 4 (whole-stage Frobenius norms,
+    tested from min_sweeps on, count rounded up to even) against the same
+    rule run on the dense matrix form: same sweep counts, same fields."""
+    nx, ny = 11, 9
+    h, f, med, src = _tiny_case(method, nx, ny, 5)
+    dt = 0.8 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    dp = _dense_for(method, nx, ny, h, dt / 2, med["K"], med["Rv"], med["Rw"])
+    z = dp.pack(f["U"][1:-1, 1:-1], f["V"][1:-1, :], f["W"][:, 1:-1])
+    F = [np.zeros((dp.niy, dp.nix)) for _ in range(3)]
+    for m in range(3):
+        F[m][src["j"] - 1, src["i"] - 1] = O.source_value(src, h, m * dt)
+    # a tolerance between the 5th and 6th changes of the first stage
+    d = dp.stage1_changes(z, F[0], 8)
+    assert all(d[k + 1] < d[k] for k in range(1, 7)), d
+    eps = math.sqrt(d[4] * d[5])
+    zz, used_ref = z, []
+    for m in range(2):
+        zz, u = dp.step_eps(zz, F[m], F[m + 1], eps, 2, 16)
+        used_ref += u
+    assert used_ref[0] == 6
+    U, V, W, used = O.run_eps(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=2, eps=eps,
+                              min_sweeps=2, sweeps=16, K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    assert list(used) == used_ref
+    Ue, Ve, We = dp.unpack(zz)
+    for got, ref in ((U[1:-1, 1:-1], Ue), (V[1:-1, :], Ve), (W[:, 1:-1], We)):
+        assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_eps_mode_limits(method):
+    """A tolerance every change passes stops each stage at min_sweeps; one no
+    change passes runs the cap: both equal the fixed-count runs bit for bit.
+    Counts are even and grow as the tolerance shrinks."""
+    nx, ny = 12, 10
+    h, f, med, src = _tiny_case(method, nx, ny, 8)
+    dt = 0.7 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    kw = dict(h=h, dt=dt, nsteps=3, K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    for eps, k in ((1e30, 4), (1e-300, 10)):
+        a = O.run_eps(method, f["U"], f["V"], f["W"], eps=eps, min_sweeps=4, sweeps=10, **kw)
+        b = O.run(method, f["U"], f["V"], f["W"], sweeps=k, **kw)
+        assert list(a[3]) == [k] * 6
+        for x, y in zip(a[:3], b):
+            assert np.array_equal(x, y)
+    prev = None
+    for eps in (1e-2, 1e-5, 1e-8, 1e-11):
+        used = O.run_eps(method, f["U"], f["V"], f["W"], eps=eps, min_sweeps=2, sweeps=16, **kw)[3]
+        assert all(u % 2 == 0 and 2 <= u <= 16 for u in used)
+        if prev is not None:
+            assert all(u >= p for u, p in zip(used, prev))
+        prev = used
