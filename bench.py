@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--dtypes", default="fp32,fp64")
     ap.add_argument("--cpu-baseline-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tolerance-steps", type=int, default=40,
+                    help="steps of the tolerance-tested leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the batched 256-problem workload (0 = skip it)")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -83,7 +85,7 @@ def alg_bytes_per_pass(method, n, elem, k_varies, r_varies):
     return elem * (2 * nu + 2 * nv + (nu if k_varies else 0) + (nv if r_varies else 0))
 
 
-def gpu_case(method, dtype, n, steps, warmup, sweeps):
+def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
     import torch
     from paper_2006_07583_amd import adi, inputs
     pr = inputs.seismic_problem(method, n, seed=0)
@@ -94,6 +96,8 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps):
     p = adi.make_params(method, dtype, n, n, pr["h"], pr["dt"], pr["cmax"], sweeps=sweeps, src=pr["src"])
     stream = torch.cuda.current_stream()
     pb = adi.Problem(p, stream).bind(U, V, W, K)
+    if tol is not None:                      # (eps, min_sweeps): tolerance-tested stages
+        pb.set_tolerance(*tol)
     pb.run(warmup)
     pb.sync()
 
@@ -114,8 +118,25 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps):
     # transposes and explicit pass; every step is two line passes
     per_pass = (t_ev - t_half) / (2.0 * (steps - half)) if steps > half else t_ev / (2.0 * steps)
     finite = bool(torch.isfinite(U).all().item())
+    stats = pb.sweep_stats() if tol is not None else (0, 0)
     pb.close()
-    return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite}
+    return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite,
+            "sweeps_per_pass": stats[1] / stats[0] if stats[0] else float(sweeps)}
+
+
+def tolerance_case(n, steps):
+    """Cost of the tolerance-tested stages on the compact FP32 pass at n^2:
+    min_sweeps 6 and cap 8 against the fixed 6-sweep pass, with every stage
+    passing the test at 6 sweeps (the attempt with 8 sweeps exits at once) and
+    with none passing (6 sweeps, then the pass recomputed with 8)."""
+    from paper_2006_07583_amd import adi
+    fixed = gpu_case(adi.CFD, adi.FP32, n, steps, 2, 6)
+    out = {"workload": f"compact FP32 {n}x{n}, min_sweeps 6, cap 8", "fixed6_pass_us": fixed["per_pass"] * 1e6}
+    for name, eps in (("pass_at_6", 1e30), ("none_pass", 1e-30)):
+        r = gpu_case(adi.CFD, adi.FP32, n, steps, 2, 8, tol=(eps, 6))
+        out[name] = {"pass_us": r["per_pass"] * 1e6, "sweeps_per_pass": r["sweeps_per_pass"],
+                     "vs_fixed6": r["per_pass"] / fixed["per_pass"], "finite": r["finite"]}
+    return out
 
 
 def batch_case(steps, count):
@@ -362,6 +383,13 @@ def main():
                                 f"({'compact' if dom == 0 else 'mimetic'} line pass)")},
         "variants": variants,
     }
+    if args.tolerance_steps > 0:
+        tc = tolerance_case(n, args.tolerance_steps)
+        print(f"# tolerance-tested compact FP32: fixed 6 sweeps {tc['fixed6_pass_us']:.1f} us/pass; "
+              f"stopping at 6 {tc['pass_at_6']['pass_us']:.1f} us ({tc['pass_at_6']['vs_fixed6']:.2f}x); "
+              f"6 then 8 {tc['none_pass']['pass_us']:.1f} us ({tc['none_pass']['vs_fixed6']:.2f}x)",
+              file=sys.stderr, flush=True)
+        out["tolerance"] = tc
     if args.batch_steps > 0:
         bc = batch_case(args.batch_steps, args.batch_count)
         print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "

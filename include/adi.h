@@ -140,6 +140,33 @@ int adi_sync(adi_problem* pb);
 int adi_get_step(const adi_problem* pb, int64_t* m);
 int adi_set_step(adi_problem* pb, int64_t m);
 
+/* Tolerance-tested stages: the stopping rule of the ADI iterations in
+ * Algorithms 3 and 4 (Appendix C) instead of a fixed sweep count.  After
+ * sweep k of a stage, k >= min_sweeps, the Frobenius norms of the changes of
+ * the whole stage, ||Ubar_k - Ubar_{k-1}|| + ||vel_k - vel_{k-1}||, are summed
+ * and compared with eps; the first count that passes is rounded up to an
+ * even count (odd counts amplify the unconverged modes), and params.sweeps
+ * is the cap.  Like the paper's GPU codes (Section 3), the test starts after
+ * a minimum number of sweeps; unlike them, the decision never leaves the
+ * device: each pass is queued as attempts with min_sweeps, min_sweeps + 2,
+ * .. sweeps sweeps, each recomputing the pass from its unchanged inputs and
+ * running only while the earlier ones have not converged.
+ *   eps         > 0 switches the test on, 0 restores the fixed count.
+ *   min_sweeps  even, in [2, params.sweeps].
+ * Applies to FP32 and FP64 problems whose lines are longer than 512 slots in
+ * both directions (nx, ny >= 512 for CFD, >= 511 for MFD), run with adi_run /
+ * adi_step; such a problem cannot join a batch.  Clears the counters of
+ * adi_sweep_stats.  Allocates 32 bytes of device memory per workgroup of
+ * the wave-per-line kernel (about 150 KiB at 4096^2) the first time.
+ * Errors: ADI_EINVAL for a NULL problem, eps < 0 or not finite, min_sweeps
+ * out of range, or a problem outside the scope above. */
+int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps);
+
+/* Tolerance-tested passes run and the sweeps they used since the last
+ * adi_set_tolerance (both 0 if it was never called).  Waits for the
+ * problem's queued work. */
+int adi_sweep_stats(adi_problem* pb, int64_t* passes, int64_t* sweeps);
+
 /* Free the problem and any workspace the library allocated. */
 int adi_destroy(adi_problem* pb);
 

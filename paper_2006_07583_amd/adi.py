@@ -20,7 +20,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync",
-           "adi_get_step", "adi_set_step", "adi_destroy",
+           "adi_get_step", "adi_set_step", "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
            "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait",
@@ -91,6 +91,8 @@ def lib():
         L.adi_sync.argtypes = [vp]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
         L.adi_set_step.argtypes = [vp, i64]
+        L.adi_set_tolerance.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+        L.adi_sweep_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.adi_destroy.argtypes = [vp]
         L.adi_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_int, ctypes.POINTER(vp)]
         L.adi_batch_run.argtypes = [vp, i64]
@@ -191,6 +193,18 @@ class Problem:
     @step_index.setter
     def step_index(self, m: int):
         _check(lib().adi_set_step(self._h, int(m)))
+
+    def set_tolerance(self, eps: float, min_sweeps: int = 2) -> "Problem":
+        """Tolerance-tested stages (adi_set_tolerance); eps = 0 restores the
+        fixed sweep count."""
+        _check(lib().adi_set_tolerance(self._h, float(eps), int(min_sweeps)))
+        return self
+
+    def sweep_stats(self):
+        """(passes, sweeps) of the tolerance-tested passes since set_tolerance."""
+        p, s = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().adi_sweep_stats(self._h, ctypes.byref(p), ctypes.byref(s)))
+        return p.value, s.value
 
     def close(self):
         if self._h:

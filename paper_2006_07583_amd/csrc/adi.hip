@@ -504,6 +504,49 @@ template hipError_t launch_pass<double>(const PassDesc<double>&, hipStream_t);
 
 namespace {
 
+// Device state of the tolerance-tested stages: the per-workgroup change
+// partials of one attempt (4 x the largest tile count of the two
+// directions), the attempt flags, and the counters of passes decided and
+// sweeps used.
+constexpr int kMaxAttempts = 8;   // (16 - 2) / 2 + 1: sweeps <= 16, min_sweeps >= 2
+struct EpsLayout {
+    double* part;
+    int* go;
+    long long* stats;
+};
+size_t eps_tiles(const adi_problem* pb) {
+    return (size_t)std::max(pb->px.nlg * pb->px.nwin, pb->py.nlg * pb->py.nwin);
+}
+size_t eps_bytes(const adi_problem* pb) { return 4 * eps_tiles(pb) * sizeof(double) + 64 + 2 * sizeof(long long); }
+EpsLayout eps_layout(const adi_problem* pb) {
+    char* b = (char*)pb->eps_buf;
+    const size_t po = 4 * eps_tiles(pb) * sizeof(double);
+    return {(double*)b, (int*)(b + po), (long long*)(b + po + 64)};
+}
+static_assert((kMaxAttempts + 1) * sizeof(int) <= 64, "flags");
+
+// One tolerance-tested pass (Algorithms 3 and 4): attempts with K = kmin,
+// kmin + 2, .. sweeps sweeps, each recomputing the pass from its unchanged
+// inputs and running only while the earlier ones have not converged; the
+// decisions stay on the device.
+template <typename T>
+hipError_t launch_tested(adi_problem* pb, adi::PassDesc<T> d) {
+    const int kmin = pb->eps_kmin, kmax = pb->p.sweeps;
+    const int J = (kmax - kmin) / 2 + 1;
+    const EpsLayout L = eps_layout(pb);
+    const int nb = d.a.nlg * d.a.nwin;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < J && e == hipSuccess; ++j) {
+        const int K = kmin + 2 * j;
+        d.a.sweeps = K;
+        d.a.eps_part = L.part;
+        d.a.eps_go = L.go + j;
+        e = adi::launch_pass<T>(d, pb->st);
+        if (e == hipSuccess) e = adi::launch_eps_check(L.part, nb, L.go, j, J, pb->eps, K, kmin, kmax, L.stats, pb->st);
+    }
+    return e;
+}
+
 template <typename T>
 int run_impl(adi_problem* pb, int64_t nsteps) {
     int rc = adi::run_begin<T>(pb, pb->st);
@@ -511,7 +554,10 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
     for (int64_t s = 0; s < nsteps; ++s)
         for (int half = 0; half < 2; ++half) {
             const auto d = adi::run_pass<T>(pb, s, half, nsteps, nullptr);
-            HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
+            if (pb->eps > 0.0)
+                HIP_TRY(launch_tested<T>(pb, d), half == 0 ? "first line pass" : "second line pass");
+            else
+                HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
         }
     return adi::run_end<T>(pb, pb->st, nsteps);
 }
@@ -719,12 +765,59 @@ int adi_set_step(adi_problem* pb, int64_t m) {
     return ADI_OK;
 }
 
+int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ADI_EINVAL, "eps must be finite and >= 0");
+    if (eps == 0.0) {
+        pb->eps = 0.0;
+        pb->eps_kmin = 0;
+        return ADI_OK;
+    }
+    if (min_sweeps < 2 || (min_sweeps & 1) || min_sweeps > pb->p.sweeps)
+        return fail(ADI_EINVAL, "min_sweeps must be even and in [2, sweeps] (got %d, sweeps %d)", min_sweeps,
+                    pb->p.sweeps);
+    if (pb->p.dtype == ADI_FP32C) return fail(ADI_EINVAL, "tolerance-tested stages: FP32 or FP64 only");
+    if (pb->px.ver != 3 || pb->py.ver != 3)
+        return fail(ADI_EINVAL,
+                    "tolerance-tested stages need lines longer than %d slots in both directions "
+                    "(nx, ny >= %d for CFD, >= %d for MFD)",
+                    adi::LINE_WS, adi::LINE_WS, adi::LINE_WS - 1);
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    if (!pb->eps_buf) HIP_TRY(hipMalloc(&pb->eps_buf, eps_bytes(pb)), "tolerance state");
+    // flags: attempt 0 of the next pass runs; counters cleared
+    const EpsLayout L = eps_layout(pb);
+    int go[kMaxAttempts + 1] = {1};
+    const long long zero[2] = {0, 0};
+    HIP_TRY(hipMemcpy(L.go, go, sizeof(go), hipMemcpyHostToDevice), "tolerance flags");
+    HIP_TRY(hipMemcpy(L.stats, zero, sizeof(zero), hipMemcpyHostToDevice), "tolerance counters");
+    pb->eps = eps;
+    pb->eps_kmin = min_sweeps;
+    return ADI_OK;
+}
+
+int adi_sweep_stats(adi_problem* pb, int64_t* passes, int64_t* sweeps) {
+    g_err.clear();
+    if (!pb || !passes || !sweeps) return fail(ADI_EINVAL, "NULL argument");
+    *passes = *sweeps = 0;
+    if (!pb->eps_buf) return ADI_OK;
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    long long st[2];
+    HIP_TRY(hipMemcpy(st, eps_layout(pb).stats, sizeof(st), hipMemcpyDeviceToHost), "tolerance counters");
+    *passes = st[0];
+    *sweeps = st[1];
+    return ADI_OK;
+}
+
 int adi_destroy(adi_problem* pb) {
     if (!pb) return ADI_OK;
-    if (pb->own_ws && pb->ws) {
+    if ((pb->own_ws && pb->ws) || pb->eps_buf) {
         (void)hipSetDevice(pb->dev);
         (void)hipStreamSynchronize(pb->st);
-        (void)hipFree(pb->ws);
+        if (pb->own_ws && pb->ws) (void)hipFree(pb->ws);
+        if (pb->eps_buf) (void)hipFree(pb->eps_buf);
     }
     delete pb;
     return ADI_OK;

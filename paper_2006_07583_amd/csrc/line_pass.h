@@ -37,6 +37,13 @@ struct LinePassArgs {
     const T* uin_lo; const T* vin_lo; T* vout_lo; T* uout_lo;
     // grouped launches: when set, aF = aFtab[tick] (tick read from device memory)
     const T* aFtab;
+    // tolerance-tested stages (wave-per-line kernel, single launches): when
+    // eps_part is set the launch runs only if *eps_go != 0, and workgroup
+    // `tile` stores the squared Frobenius norms of the changes of the last two
+    // sweeps, {|u_{K-1} - u_{K-2}|^2, |v_{K-1} - v_{K-2}|^2, |u_K - u_{K-1}|^2,
+    // |v_K - v_{K-1}|^2}, over the slots it writes at eps_part[q nlg nwin + tile]
+    double* eps_part;
+    const int* eps_go;
 };
 
 // A grouped launch: the passes items[0..nitems) (any problems, any
@@ -85,5 +92,14 @@ hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hip
 template <typename T>
 hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st);
 int line3_lanes(int dtype);
+
+// Tolerance-tested stages (LinePassArgs::eps_part): a pass is `attempts`
+// launches, attempt j with K = kmin + 2 j sweeps running while go[j] != 0
+// (go[0] = 1 at the start of every pass).  After attempt j, eps_check reduces
+// the nb per-workgroup partials, sets go[j + 1], and when the attempt decides
+// the stage adds one pass and K sweeps to stats[0], stats[1]; the check of
+// the last attempt also resets the flags for the next pass.
+hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int attempts, double eps, int K,
+                            int kmin, int kmax, long long* stats, hipStream_t st);
 
 }  // namespace adi

@@ -328,8 +328,12 @@ template <typename T, int METHOD> struct Line3 {
 
 // One workgroup's share of a pass: LW lines (line group tile % nlg) over
 // window tile / nlg.
-template <typename T, int METHOD, int MODE>
+// EPS: the tolerance-tested form (LinePassArgs::eps_part).  It keeps the
+// previous iterates by solving into a spare array, and stores the squared
+// changes of the last two sweeps over the slots the window writes.
+template <typename T, int METHOD, int MODE, bool EPS = false>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
+    if (EPS && *a.eps_go == 0) return;   // uniform: an earlier attempt converged
     using C = K3<T>;
     constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW;
     const int lg = tile % a.nlg, g = tile / a.nlg;
@@ -503,6 +507,25 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         for (int k = 0; k < R; ++k) RR[k] = qok && s0 + k <= n ? v : T(0);
     }
 
+    // Tolerance test: squared changes of the last two sweeps over the slots
+    // this window writes (pressure: interior slots; velocity: slots 0..n).
+    // (accumulated in the kernel's precision per lane, reduced in FP64)
+    T ev[4] = {T(0), T(0), T(0), T(0)};
+    int umask = 0, vmask = 0;
+    if constexpr (EPS) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int s = s0 + k;
+            const bool own = qok && s >= c0 && s < c1;
+            if (own && s >= 1 && s <= uhi) umask |= 1 << k;
+            if (own && s <= n) vmask |= 1 << k;
+        }
+    }
+    auto chg = [](T x, T y, int on) {
+        const T d = on ? x - y : T(0);
+        return d * d;
+    };
+
     if (METHOD == LINE_CFD) {
         // neighbours' edge values of the inputs
         T Al = L.prev(A[R - 1]), Ar = L.next(A[0]);
@@ -528,24 +551,66 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
             T Ul = fma(-Kl, xl, Al), Ur = fma(-Kr, xr, Ar);
             T Tl, Tr;
-            for (int it = 1; it < a.sweeps; ++it) {
+            if constexpr (EPS) {
+                T X[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) Tt[k] = B[k];                     // v_0
+                // one sweep (v_it, then u_{it+1}); tv: sum the change of v,
+                // q >= 0: sum the change of u into ev[q] (constants at each call)
+                auto sweep = [&](bool tv, int q) {
+                    L.rhs(0, U, Ul, Ur, X);
+                    L.solve(0, X, xl, xr);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T vn = fma(-RR[k], X[k], B[k]);
+                        if (tv) ev[1] += chg(vn, Tt[k], (vmask >> k) & 1);
+                        Tt[k] = vn;
+                    }
+                    Tl = fma(-Rl, xl, Bl);
+                    Tr = fma(-Rr, xr, Br);
+                    L.rhs(1, Tt, Tl, Tr, X);
+                    L.solve(1, X, xl, xr);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T un = fma(-KK[k], X[k], A[k]);
+                        if (q >= 0) ev[q] += chg(un, U[k], (umask >> k) & 1);
+                        U[k] = un;
+                    }
+                    Ul = fma(-Kl, xl, Al);
+                    Ur = fma(-Kr, xr, Ar);
+                };
+                // sweeps it = 1 .. K - 1: untracked, then u_{K-1}, then v_{K-1} and u_K
+                for (int it = 1; it < a.sweeps - 2; ++it) sweep(false, -1);
+                if (a.sweeps >= 3) sweep(false, 0);
+                sweep(true, 2);
+                L.rhs(0, U, Ul, Ur, X);
+                L.solve(0, X, xl, xr);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {                                  // v_K
+                    const T vn = fma(-RR[k], X[k], B[k]);
+                    ev[3] += chg(vn, Tt[k], (vmask >> k) & 1);
+                    Tt[k] = vn;
+                }
+            } else {
+                for (int it = 1; it < a.sweeps; ++it) {
+                    L.rhs(0, U, Ul, Ur, Tt);
+                    L.solve(0, Tt, xl, xr);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
+                    Tl = fma(-Rl, xl, Bl);
+                    Tr = fma(-Rr, xr, Br);
+                    L.rhs(1, Tt, Tl, Tr, U);
+                    L.solve(1, U, xl, xr);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                    Ul = fma(-Kl, xl, Al);
+                    Ur = fma(-Kr, xr, Ar);
+                }
                 L.rhs(0, U, Ul, Ur, Tt);
                 L.solve(0, Tt, xl, xr);
 #pragma unroll
-                for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
-                Tl = fma(-Rl, xl, Bl);
-                Tr = fma(-Rr, xr, Br);
-                L.rhs(1, Tt, Tl, Tr, U);
-                L.solve(1, U, xl, xr);
-#pragma unroll
-                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
-                Ul = fma(-Kl, xl, Al);
-                Ur = fma(-Kr, xr, Ar);
+                for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // v_K
             }
-            L.rhs(0, U, Ul, Ur, Tt);
-            L.solve(0, Tt, xl, xr);
-#pragma unroll
-            for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);       // v_K
             if (MODE == LINE_SWEEP) {
                 Tl = fma(-Rl, xl, Bl);
                 Tr = fma(-Rr, xr, Br);
@@ -653,13 +718,44 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             applyD(B, Bm2, Bm1, Bp, U);
 #pragma unroll
             for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
-            for (int it = 1; it < a.sweeps; ++it) {
-                velocity(U, Tt, Tm2, Tm1, Tp);
-                applyD(Tt, Tm2, Tm1, Tp, U);
+            if constexpr (EPS) {
+                T X[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                for (int k = 0; k < R; ++k) Tt[k] = B[k];                     // v_0
+                // one sweep (v_it, then u_{it+1}); tracking as in the compact form
+                auto sweep = [&](bool tv, int q) {
+                    velocity(U, X, Tm2, Tm1, Tp);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        if (tv) ev[1] += chg(X[k], Tt[k], (vmask >> k) & 1);
+                        Tt[k] = X[k];
+                    }
+                    applyD(Tt, Tm2, Tm1, Tp, X);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T un = fma(-KK[k], X[k], A[k]);
+                        if (q >= 0) ev[q] += chg(un, U[k], (umask >> k) & 1);
+                        U[k] = un;
+                    }
+                };
+                for (int it = 1; it < a.sweeps - 2; ++it) sweep(false, -1);
+                if (a.sweeps >= 3) sweep(false, 0);
+                sweep(true, 2);
+                velocity(U, X, Tm2, Tm1, Tp);                                 // v_K
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    ev[3] += chg(X[k], Tt[k], (vmask >> k) & 1);
+                    Tt[k] = X[k];
+                }
+            } else {
+                for (int it = 1; it < a.sweeps; ++it) {
+                    velocity(U, Tt, Tm2, Tm1, Tp);
+                    applyD(Tt, Tm2, Tm1, Tp, U);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                }
+                velocity(U, Tt, Tm2, Tm1, Tp);                               // v_K
             }
-            velocity(U, Tt, Tm2, Tm1, Tp);                                   // v_K
             if (MODE == LINE_SWEEP) {
                 applyD(Tt, Tm2, Tm1, Tp, A);
 #pragma unroll
@@ -669,6 +765,24 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                     U[k] = fma(-KK[k], A[k], U[k]);
                 }
             }
+        }
+    }
+
+    if constexpr (EPS) {
+        // wave sums, then the workgroup's, stored as this tile's partials
+        __shared__ double wsum[C::NWV][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double v = (double)ev[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) wsum[wave][q] = v;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            for (int w = 0; w < C::NWV; ++w) v += wsum[w][tid];
+            a.eps_part[(int64_t)tid * a.nlg * a.nwin + tile] = v;
         }
     }
 
@@ -780,9 +894,15 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 template <typename T, int METHOD>
 constexpr bool kGroupOrder = METHOD == LINE_CFD || sizeof(T) == 4;
 
-template <typename T, int METHOD, int MODE>
+// The tolerance-tested form holds a spare array and the change sums: it
+// runs at a lower occupancy (2 waves per SIMD in FP32, 1 in FP64) rather
+// than spill.
+template <typename T, bool EPS>
+constexpr int kWpe = EPS ? (sizeof(T) == 4 ? 2 : 1) : Cfg3<T>::WPE;
+
+template <typename T, int METHOD, int MODE, bool EPS = false>
 __global__ void __launch_bounds__(K3<T>::NT)
-__attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
+__attribute__((amdgpu_waves_per_eu(kWpe<T, EPS>, kWpe<T, EPS>)))
 line_pass3_kernel(const LinePassArgs<T> a) {
     __shared__ __align__(16) T smem[K3<T>::TILE];
     // Each XCD takes a contiguous range of the ordered tiles: line group by
@@ -793,7 +913,7 @@ line_pass3_kernel(const LinePassArgs<T> a) {
     const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (t >= nb) return;
     const int tile = kGroupOrder<T, METHOD> ? (t % a.nwin) * a.nlg + t / a.nwin : t;
-    lp3_body<T, METHOD, MODE>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, EPS>(a, tile, smem);
 }
 
 template <typename T, int METHOD, int MODE>
@@ -814,9 +934,13 @@ hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method,
     const int nb = a ? a->nlg * a->nwin : ga->total;
     if (nb <= 0) return hipSuccess;
     dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
+    const bool eps = a && a->eps_part;
+    if (eps && mode == LINE_EXPLICIT) return hipErrorInvalidValue;
 #define LP3_CASE(M, MD)                                                                                  \
     if (method == M && mode == MD) {                                                                     \
-        if (a)                                                                                           \
+        if (eps)                                                                                         \
+            hipLaunchKernelGGL((line_pass3_kernel<T, M, MD, MD != LINE_EXPLICIT>), grid, block, 0, st, *a); \
+        else if (a)                                                                                      \
             hipLaunchKernelGGL((line_pass3_kernel<T, M, MD>), grid, block, 0, st, *a);                  \
         else                                                                                             \
             hipLaunchKernelGGL((line_pass3_group_kernel<T, M, MD>), grid, block, 0, st, *ga);           \
@@ -843,6 +967,56 @@ hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipS
 }
 
 int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW; }
+
+// ---- tolerance-tested stages: control kernels ----
+
+// after attempt j with K sweeps: the stage has converged if the change of
+// sweep K - 1 (tested only from kmin on) or of sweep K is at most eps; the
+// next attempt (K + 2 sweeps) runs only if this one ran and did not converge
+// and K < kmax.  A deciding attempt adds one pass and its K sweeps to stats.
+// The last attempt's check re-arms the flags for the next pass.
+__global__ void __launch_bounds__(256)
+eps_check_kernel(const double* part, int nb, int* go, int j, int attempts, double eps, int K, int kmin, int kmax,
+                 long long* stats) {
+    __shared__ double red[4][256];
+    const int t = threadIdx.x;
+    const bool ran = go[j] != 0;   // uniform
+    if (ran) {
+        for (int q = 0; q < 4; ++q) {
+            double v = 0.0;
+            for (int i = t; i < nb; i += 256) v += part[(int64_t)q * nb + i];
+            red[q][t] = v;
+        }
+        for (int w = 128; w > 0; w >>= 1) {
+            __syncthreads();
+            if (t < w)
+                for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + w];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    bool next = false;
+    if (ran) {
+        const bool t1 = K - 1 >= kmin && sqrt(red[0][0]) + sqrt(red[1][0]) <= eps;
+        const bool t2 = sqrt(red[2][0]) + sqrt(red[3][0]) <= eps;
+        const bool stop = t1 || t2 || K >= kmax;
+        next = !stop;
+        if (stop) {
+            stats[0] += 1;
+            stats[1] += K;
+        }
+    }
+    go[j + 1] = next ? 1 : 0;
+    if (j == attempts - 1)
+        for (int i = 0; i <= attempts; ++i) go[i] = i == 0 ? 1 : 0;
+}
+
+hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int attempts, double eps, int K,
+                            int kmin, int kmax, long long* stats, hipStream_t st) {
+    hipLaunchKernelGGL(eps_check_kernel, dim3(1), dim3(256), 0, st, part, nb, go, j, attempts, eps, K, kmin, kmax,
+                       stats);
+    return hipGetLastError();
+}
 
 template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t);

@@ -73,6 +73,12 @@ struct adi_problem {
     } d[2];
     int vcur = 0, wcur = 0;
     adi::Plan px, py;
+    // tolerance-tested stages (adi_set_tolerance): eps > 0 switches them on;
+    // eps_buf holds the per-attempt change sums, the attempt flags and the
+    // pass / sweep counters (layout in adi.hip, eps_layout)
+    double eps = 0.0;
+    int eps_kmin = 0;
+    void* eps_buf = nullptr;
 };
 
 namespace adi {

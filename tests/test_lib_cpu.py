@@ -92,6 +92,9 @@ def test_null_arguments():
     assert L.adi_bind(None, None, None, None, None, None, None, None, None, 0) == -1
     assert L.adi_destroy(None) == 0
     assert L.adi_status_string(-5) == b"ADI_ENOTREADY"
+    assert L.adi_set_tolerance(None, 1e-6, 2) == -1
+    n = ctypes.c_int64()
+    assert L.adi_sweep_stats(None, ctypes.byref(n), ctypes.byref(n)) == -1
 
 
 def test_batch_create_validates_arguments_on_the_host():
