@@ -71,6 +71,8 @@ def _load():
         lib.oracle_run_eps.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
         lib.oracle_run_eps.restype = ctypes.c_int
+        lib.oracle_run_direct.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64]
+        lib.oracle_run_direct.restype = ctypes.c_int
         lib.oracle_source.argtypes = [ctypes.POINTER(_Params), ctypes.c_double]
         lib.oracle_source.restype = ctypes.c_double
         for name in ("oracle_cfd_d", "oracle_cfd_dbar", "oracle_mfd_g", "oracle_mfd_d"):
@@ -171,6 +173,28 @@ def run_eps(method, U, V, W, *, h, dt, nsteps, eps, min_sweeps=2, sweeps=16, K=N
     if rc != 0:
         raise ValueError("oracle_run_eps rejected its arguments")
     return U, V, W, used
+
+
+def run_direct(method, U, V, W, *, h, dt, nsteps, K=None, Rv=None, Rw=None, order=0, src=None,
+               t0=0.0, kappa0=1.0, rinv0=1.0, threads=0):
+    """As :func:`run` with every stage's line systems solved exactly by
+    dense Gaussian elimination with partial pivoting (the limit of infinitely
+    many sweeps).  Cost grows as the cube of the line length: small grids."""
+    ny = U.shape[0] - (1 if method == CFD else 2)
+    nx = U.shape[1] - (1 if method == CFD else 2)
+    sh = shapes(method, nx, ny)
+    U = _f64(U, sh["U"], "U").copy()
+    V = _f64(V, sh["V"], "V").copy()
+    W = _f64(W, sh["W"], "W").copy()
+    K = None if K is None else _f64(K, sh["K"], "K")
+    Rv = None if Rv is None else _f64(Rv, sh["Rv"], "Rv")
+    Rw = None if Rw is None else _f64(Rw, sh["Rw"], "Rw")
+    p = make_params(method, nx, ny, h, dt, 0, order, src, t0, kappa0, rinv0, threads)
+    rc = _load().oracle_run_direct(ctypes.byref(p), _ptr(U), _ptr(V), _ptr(W),
+                                   _ptr(K), _ptr(Rv), _ptr(Rw), int(nsteps))
+    if rc != 0:
+        raise ValueError("oracle_run_direct rejected its arguments")
+    return U, V, W
 
 
 def source_value(src, h, t):

@@ -55,7 +55,11 @@
  *     is compared with eps; the first count that passes is rounded up to an
  *     even count (odd counts amplify the unconverged modes) and `sweeps` is
  *     the cap.  The first test comes after the second sweep at the earliest,
- *     as the paper's GPU codes also run a minimum number of sweeps first.
+ *     as the paper's GPU codes also run a minimum number of sweeps first;
+ *   - direct mode (oracle_run_direct): each stage's line systems solved
+ *     exactly, the limit of infinitely many sweeps, which is the
+ *     Peaceman-Rachford step itself (eqs. ecua2:PR, ecua3:PR2) with no
+ *     fixed-point error and no step-size limit from the iteration.
  *
  * Built with -O2 -ffp-contract=off and no fast-math so every operation is
  * rounded as written.
@@ -324,6 +328,7 @@ typedef struct {
  * Stage (d = x) is eq. ecua2:PR solved through eqs. ecua1:ADI / adiSolve;
  * stage (d = y) is eq. ecua3:PR solved through eq. adiSolve2. */
 static void implicit_eps(problem* pb, int d, int sweeps, int nthreads, double eps, int min_sweeps, int32_t* used);
+static void implicit_direct(problem* pb, int d, int nthreads);
 
 static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads, double eps, int min_sweeps,
                   int32_t* used) {
@@ -374,6 +379,11 @@ static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads, dou
         free(ubuf); free(vbuf); free(tmp);
     }
 
+    if (sweeps == 0) {
+        implicit_direct(pb, d, nthreads);
+        if (used) *used = 0;
+        return;
+    }
     if (eps > 0.0) {
         implicit_eps(pb, d, sweeps, nthreads, eps, min_sweeps, used);
         return;
@@ -491,11 +501,122 @@ static void implicit_eps(problem* pb, int d, int sweeps, int nthreads, double ep
     free(Ub); free(Vk); free(V0);
 }
 
+/* Solve the dense m x m system M x = b in place by Gaussian elimination
+ * with partial pivoting (row interchanges); M is row-major and destroyed,
+ * b becomes x.  Returns -1 for an exactly singular matrix. */
+static int dense_solve(int m, double* M, double* b) {
+    for (int k = 0; k < m; ++k) {
+        int p = k;
+        for (int i = k + 1; i < m; ++i)
+            if (fabs(M[(size_t)i * m + k]) > fabs(M[(size_t)p * m + k])) p = i;
+        if (M[(size_t)p * m + k] == 0.0) return -1;
+        if (p != k) {
+            for (int j = 0; j < m; ++j) {
+                double t = M[(size_t)k * m + j];
+                M[(size_t)k * m + j] = M[(size_t)p * m + j];
+                M[(size_t)p * m + j] = t;
+            }
+            double t = b[k]; b[k] = b[p]; b[p] = t;
+        }
+        for (int i = k + 1; i < m; ++i) {
+            double l = M[(size_t)i * m + k] / M[(size_t)k * m + k];
+            if (l == 0.0) continue;
+            for (int j = k; j < m; ++j) M[(size_t)i * m + j] -= l * M[(size_t)k * m + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < m; ++j) s -= M[(size_t)i * m + j] * b[j];
+        b[i] = s / M[(size_t)i * m + i];
+    }
+    return 0;
+}
+
+/* Implicit part along direction d solved exactly (the limit of infinitely
+ * many sweeps).  For each line the stage equations
+ *     Ubar + a K .* Dbar_d(vel)                 = R_U
+ *     vel  + a R_d .* G_d([U_bnd, Ubar, U_bnd]) = vel_d
+ * are one linear system in the unknowns [Ubar (interior points), vel (all
+ * nodes)].  Its matrix is assembled from the columns of Dbar_d and G_d,
+ * obtained by applying the line derivatives to unit vectors, and the system
+ * is solved by Gaussian elimination with partial pivoting.  The Dirichlet
+ * values U_bnd move to the right-hand side. */
+static void implicit_direct(problem* pb, int d, int nthreads) {
+    const int e = 1 - d;
+    const int method = pb->method;
+    const double a = pb->a;
+    const int nd = d == 0 ? pb->nx : pb->ny;
+    const int ne = e == 0 ? pb->nx : pb->ny;
+    const line_ops* od = d == 0 ? &pb->ox : &pb->oy;
+    field* vel_d = d == 0 ? &pb->V : &pb->W;
+    const field* R_d = d == 0 ? &pb->Rv : &pb->Rw;
+    const int niu = n_uint(method, nd), niu_e = n_uint(method, ne);
+    const int nfu = n_ufull(method, nd), nv = nd + 1;
+    const int m = niu + nv;
+    const int ni_x = n_uint(method, pb->nx);
+    /* the line derivatives as dense matrices: Dm (niu x nv), Gm (nv x nfu) */
+    double* Dm = calloc((size_t)niu * nv, sizeof(double));
+    double* Gm = calloc((size_t)nv * nfu, sizeof(double));
+    {
+        double* unit = calloc((size_t)(nfu + nv), sizeof(double));
+        double* col = calloc((size_t)(nfu + nv), sizeof(double));
+        for (int c = 0; c < nv; ++c) {
+            memset(unit, 0, sizeof(double) * (size_t)(nfu + nv));
+            unit[c] = 1.0;
+            deriv_D(od, unit, col);
+            for (int r = 0; r < niu; ++r) Dm[(size_t)r * nv + c] = col[r];
+        }
+        for (int c = 0; c < nfu; ++c) {
+            memset(unit, 0, sizeof(double) * (size_t)(nfu + nv));
+            unit[c] = 1.0;
+            deriv_G(od, unit, col);
+            for (int r = 0; r < nv; ++r) Gm[(size_t)r * nfu + c] = col[r];
+        }
+        free(unit); free(col);
+    }
+#pragma omp parallel num_threads(nthreads)
+    {
+        double* M = malloc(sizeof(double) * (size_t)m * m);
+        double* b = malloc(sizeof(double) * (size_t)m);
+        double* ubuf = malloc(sizeof(double) * (size_t)nfu);
+#pragma omp for schedule(dynamic)
+        for (int l = 1; l <= niu_e; ++l) {
+            memset(M, 0, sizeof(double) * (size_t)m * m);
+            gather(&pb->U, d, l, 0, nfu, ubuf);
+            /* pressure rows: Ubar_q + a K_q sum_c Dm[q][c] vel_c = R_U */
+            for (int q = 0; q < niu; ++q) {
+                int k = q + 1;
+                int j = d == 0 ? l : k, i = d == 0 ? k : l;
+                double kap = mat(&pb->K, d, l, k, pb->kappa0);
+                M[(size_t)q * m + q] = 1.0;
+                for (int c = 0; c < nv; ++c) M[(size_t)q * m + niu + c] = a * kap * Dm[(size_t)q * nv + c];
+                b[q] = pb->RU[(size_t)(j - 1) * ni_x + (i - 1)];
+            }
+            /* velocity rows: vel_f + a R_f sum_q G[f][q+1] Ubar_q
+             *                = vel_d_f - a R_f (G[f][0] U_0 + G[f][nfu-1] U_last) */
+            for (int f = 0; f < nv; ++f) {
+                double r = mat(R_d, d, l, f, pb->rinv0);
+                size_t row = (size_t)(niu + f) * m;
+                M[row + niu + f] = 1.0;
+                for (int q = 0; q < niu; ++q) M[row + q] = a * r * Gm[(size_t)f * nfu + q + 1];
+                double gb = Gm[(size_t)f * nfu] * ubuf[0] + Gm[(size_t)f * nfu + nfu - 1] * ubuf[nfu - 1];
+                b[niu + f] = *at(vel_d, d, l, f) - a * r * gb;
+            }
+            dense_solve(m, M, b);
+            scatter(&pb->U, d, l, 1, niu, b);
+            scatter(vel_d, d, l, 0, nv, b + niu);
+        }
+        free(M); free(b); free(ubuf);
+    }
+    free(Dm); free(Gm);
+}
+
 static int check_params(const oracle_params* p) {
     if (!p) return -1;
     if (p->method != ORC_CFD && p->method != ORC_MFD) return -1;
     if (p->nx < 8 || p->ny < 8) return -1;
-    if (p->sweeps < 1) return -1;
+    if (p->sweeps < 0) return -1;   /* 0: direct (exact) line solves */
     if (!(p->h > 0.0) || !(p->dt > 0.0)) return -1;
     if (p->order != 0 && p->order != 1) return -1;
     return 0;
@@ -559,6 +680,7 @@ static int run_impl(const oracle_params* p, double* U, double* V, double* W, con
  * Returns 0 or -1. */
 int oracle_run(const oracle_params* p, double* U, double* V, double* W,
                const double* K, const double* Rv, const double* Rw, int64_t nsteps) {
+    if (!p || p->sweeps < 1) return -1;
     return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL);
 }
 
@@ -570,6 +692,16 @@ int oracle_run_eps(const oracle_params* p, double* U, double* V, double* W, cons
                    int32_t* used) {
     if (!(eps > 0.0) || min_sweeps < 2 || (min_sweeps & 1) || !p || min_sweeps > p->sweeps) return -1;
     return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used);
+}
+
+/* As oracle_run with every stage's line systems solved exactly (the limit
+ * of infinitely many sweeps); p->sweeps is ignored. */
+int oracle_run_direct(const oracle_params* p, double* U, double* V, double* W, const double* K,
+                      const double* Rv, const double* Rw, int64_t nsteps) {
+    if (!p) return -1;
+    oracle_params q = *p;
+    q.sweeps = 0;
+    return run_impl(&q, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL);
 }
 
 /* Ricker source value F(t) = s(t) / h^2 as the oracle applies it. */

@@ -485,3 +485,64 @@ def test_eps_mode_limits(method):
         if prev is not None:
             assert all(u >= p for u, p in zip(used, prev))
         prev = used
+
+
+# ---------------------------------------------------------------- direct (exact) line solves
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (9, 12), (12, 10)])
+def test_direct_matches_dense_exact_step(method, nx, ny):
+    """Per-line exact solves equal the exactly solved stages of eqs.
+    ecua2:PR / ecua3:PR2 assembled over the whole grid, at cfl 2.5, where
+    the fixed-point sweeps diverge."""
+    h, f, med, src = _tiny_case(method, nx, ny, 7 + nx)
+    dt = 2.5 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    t0 = 0.05
+    U, V, W = O.run_direct(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=1,
+                           K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src, t0=t0)
+    dp = _dense_for(method, nx, ny, h, dt / 2, med["K"], med["Rv"], med["Rw"])
+    Fm = np.zeros((dp.niy, dp.nix)); Fm1 = np.zeros_like(Fm)
+    Fm[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, t0)
+    Fm1[src["j"] - 1, src["i"] - 1] = O.source_value(src, h, t0 + dt)
+    z = dp.pack(f["U"][1:-1, 1:-1], f["V"][1:-1, :], f["W"][:, 1:-1])
+    Ue, Ve, We = dp.unpack(dp.step_exact(z, Fm, Fm1))
+    for got, ref in ((U[1:-1, 1:-1], Ue), (V[1:-1, :], Ve), (W[:, 1:-1], We)):
+        assert np.abs(got - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1.0)
+    assert np.array_equal(U[0], f["U"][0]) and np.array_equal(U[:, -1], f["U"][:, -1])
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_direct_is_limit_of_sweeps_with_dirichlet_data(method):
+    """With non-zero boundary pressure values (which the dense form above
+    does not carry) the exact solves equal 60 sweeps at cfl 0.4, where the
+    sweeps contract by at most 0.24 each, over two steps."""
+    nx, ny = 13, 11
+    h, f, med, src = _tiny_case(method, nx, ny, 21)
+    rng = np.random.default_rng(5)
+    U0 = f["U"].copy()
+    for sl in (np.s_[0, :], np.s_[-1, :], np.s_[:, 0], np.s_[:, -1]):
+        U0[sl] = rng.standard_normal(U0[sl].shape)
+    dt = 0.4 * h / math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    kw = dict(h=h, dt=dt, nsteps=2, K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src)
+    a = O.run_direct(method, U0, f["V"], f["W"], **kw)
+    b = O.run(method, U0, f["V"], f["W"], sweeps=60, **kw)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("method,mode,tol", [(O.MFD, (2, 3), 1e-5), (O.CFD, (1, 1), 2e-7)])
+@pytest.mark.parametrize("cfl", [2.0, 4.0])
+def test_direct_beyond_fixed_point_limit_matches_closed_form(method, mode, tol, cfl):
+    """At cfl 2 and 4, beyond the divergence limit of the sweeps, the exact
+    solves follow the closed-form Peaceman-Rachford solution of the standing
+    mode to within the spatial error, while 6 sweeps blow up."""
+    N = 64
+    h = 1.0 / N
+    f = inputs.standing_mode(method, N, N, h, *mode)
+    dt = cfl * h
+    nsteps = int(round(0.5 / dt))
+    U, _, _ = O.run_direct(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps)
+    g = pr_mode_factor(mode[0] * math.pi, mode[1] * math.pi, dt / 2, nsteps)
+    assert np.abs(U - g * f["U"]).max() < tol
+    Us, _, _ = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, sweeps=6)
+    assert not np.abs(Us - g * f["U"]).max() < 1.0
