@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/adi.h"
+#include "direct_core.h"
 #include "line_pass.h"
 #include "problem.h"
 
@@ -156,6 +157,7 @@ namespace {
 // Workspace regions of one direction: P, V0, V1, K, R, Plo, V0lo, V1lo, coef.
 struct Layout {
     size_t off[2][9];
+    size_t fs_off;   // factor store of the direct solves (shared by both directions)
     size_t total;
 };
 
@@ -177,8 +179,39 @@ Layout layout(const adi_problem& pb) {
             cur += (sizes[i] * pb.esz + 255) / 256 * 256;
         }
     }
+    L.fs_off = cur;
+    if (p.sweeps == 0) {
+        const int nv = adi::direct_values_per_row(p.method == ADI_MFD ? adi::LINE_MFD : adi::LINE_CFD);
+        size_t fs = 0;
+        for (const Plan* pl : {&pb.px, &pb.py})
+            fs = std::max(fs, (size_t)pl->dnlp * pl->dnwin * pl->drows * nv * pb.esz);
+        cur += (fs + 255) / 256 * 256;
+    }
     L.total = cur;
     return L;
+}
+
+// Window margin of the direct solves (slots): the decay of the line
+// inverse at the largest (a c / h)^2, to 1e-17 (FP64) or 1e-9 (FP32) of its
+// peak.
+int direct_margin_of(const adi_params& p) {
+    const double ac = 0.5 * p.dt * p.c_max / p.h;
+    const int m = p.method == ADI_MFD ? adi::direct::MFD : adi::direct::CFD;
+    return adi::direct::direct_margin(m, ac * ac, p.dtype == ADI_FP64 ? 1e-17 : 1e-9);
+}
+
+// Windows of the direct solves along one direction: enough windows for
+// about 2^17 threads, each keeping at least twice its margin.
+void direct_plan(Plan& pl, const adi_params& p) {
+    const int m = p.method == ADI_MFD ? adi::direct::MFD : adi::direct::CFD;
+    const int ns = pl.n - adi::direct::direct_smin(m) + 1;
+    pl.dH = direct_margin_of(p);
+    pl.dnlp = (pl.nlines + 63) / 64 * 64;
+    const int want = std::max(1, (1 << 17) / pl.dnlp);
+    int S = std::max({2 * pl.dH, 16, (ns + want - 1) / want});
+    pl.dS = std::min(S, ns);
+    pl.dnwin = adi::direct::direct_nwin(m, pl.n, pl.dS);
+    pl.drows = adi::direct::direct_rows(m, pl.n, pl.dS, pl.dH);
 }
 
 int validate(const adi_params* p) {
@@ -192,8 +225,10 @@ int validate(const adi_params* p) {
         return fail(ADI_EINVAL, "order must be 0 (x-implicit stage first) or 1 (y-implicit first)");
     if (p->nx < 8 || p->ny < 8) return fail(ADI_EINVAL, "nx, ny must be >= 8 (got %d, %d)", p->nx, p->ny);
     if (p->nx > (1 << 20) || p->ny > (1 << 20)) return fail(ADI_EINVAL, "grid too large");
-    if (p->sweeps < 2 || p->sweeps > 16 || (p->sweeps & 1))
-        return fail(ADI_EINVAL, "sweeps must be even and in [2, 16] (got %d)", p->sweeps);
+    if (p->sweeps != 0 && (p->sweeps < 2 || p->sweeps > 16 || (p->sweeps & 1)))
+        return fail(ADI_EINVAL, "sweeps must be 0 (direct solves) or even and in [2, 16] (got %d)", p->sweeps);
+    if (p->sweeps == 0 && p->dtype == ADI_FP32C)
+        return fail(ADI_EINVAL, "direct solves (sweeps 0) run in FP32 or FP64, not the compensated mode");
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(ADI_EINVAL, "h must be positive");
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(ADI_EINVAL, "dt must be positive");
     if (!(p->c_max > 0.0) || !std::isfinite(p->c_max)) return fail(ADI_EINVAL, "c_max must be positive");
@@ -201,8 +236,10 @@ int validate(const adi_params* p) {
     if (!(p->kappa0 > 0.0) || !(p->rinv0 > 0.0)) return fail(ADI_EINVAL, "kappa0, rinv0 must be positive");
     const double cfl = p->dt * p->c_max / p->h;
     const double lim = p->method == ADI_CFD ? 1.15 : 0.81;
-    if (!(cfl < lim))
+    if (p->sweeps != 0 && !(cfl < lim))
         return fail(ADI_EINVAL, "cfl %.4f at or above the fixed-point limit %.2f of this method", cfl, lim);
+    if (p->sweeps == 0 && direct_margin_of(*p) < 0)
+        return fail(ADI_EINVAL, "cfl %.4f too large for the windows of the direct solves", cfl);
     const int nix = p->method == ADI_CFD ? p->nx - 1 : p->nx;
     const int niy = p->method == ADI_CFD ? p->ny - 1 : p->ny;
     const bool has_src = p->src_i >= 0 || p->src_j >= 0;
@@ -224,6 +261,10 @@ void derive(adi_problem* pb) {
     const int64_t padm = 256 / (int64_t)pb->esz;   // 256-byte rows
     pb->px = make_plan(p.method, p.dtype, p.nx, pb->niy, p.sweeps);
     pb->py = make_plan(p.method, p.dtype, p.ny, pb->nix, p.sweeps);
+    if (p.sweeps == 0) {
+        direct_plan(pb->px, p);
+        direct_plan(pb->py, p);
+    }
     for (int d = 0; d < 2; ++d) {
         const Plan& pl = d == 0 ? pb->px : pb->py;
         auto& D = pb->d[d];
@@ -364,6 +405,7 @@ adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, co
         a.aFtab = mode == adi::LINE_SWEEP ? aFtab : nullptr;
     }
     d.ver = pl.ver;
+    d.dir = dir;
     d.cfg = pl.ver == 1 ? pl.cfg : 0;
     d.method = p.method;
     d.mode = mode;
@@ -547,6 +589,58 @@ hipError_t launch_tested(adi_problem* pb, adi::PassDesc<T> d) {
     return e;
 }
 
+// A line pass of the direct solves (sweeps 0): the same hand-off buffers as
+// the sweep pass it replaces, read through (line, slot) strides.  Along a
+// line-major direction element (q, s) is at (q + 1) ld + s; along a
+// slot-major one pressure-type arrays hold (s - 1) ld + q and velocity-type
+// arrays s ld + q; the pressure output is written transposed (utrans 1:
+// q ld + s - 1) or slot-major ((s - 1) ld + q).
+template <typename T>
+hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
+    const auto& a = d.a;
+    const Plan& pl = d.dir == 0 ? pb->px : pb->py;
+    const bool lm = pb->d[d.dir].lm;
+    adi::DirectArgs<T> g{};
+    auto pres_in = [&](const T* base, int64_t ld, const T*& o, int64_t& l, int64_t& s) {
+        if (!base) { o = nullptr; l = s = 0; return; }
+        if (lm) { o = base + ld; l = ld; s = 1; }
+        else { o = base - ld; l = 1; s = ld; }
+    };
+    auto vel_at = [&](const T* base, int64_t ld, const T*& o, int64_t& l, int64_t& s) {
+        if (!base) { o = nullptr; l = s = 0; return; }
+        if (lm) { o = base + ld; l = ld; s = 1; }
+        else { o = base; l = 1; s = ld; }
+    };
+    pres_in(a.uin, a.uin_ld, g.a, g.a_l, g.a_s);
+    pres_in(a.ak, a.ak_ld, g.k, g.k_l, g.k_s);
+    vel_at(a.vin, a.vin_ld, g.b, g.b_l, g.b_s);
+    vel_at(a.ar, a.ar_ld, g.r, g.r_l, g.r_s);
+    const T* vo;
+    vel_at(a.vout, a.vout_ld, vo, g.v_l, g.v_s);
+    g.v = const_cast<T*>(vo);
+    // the wave-per-line pass addresses a line-major pressure target one
+    // element lower; undo that shift
+    T* uo = a.uout + (pl.ver == 3 && a.utrans == 0 ? 1 : 0);
+    if (a.utrans) { g.u = uo - 1; g.u_l = a.uout_ld; g.u_s = 1; }
+    else { g.u = uo - a.uout_ld; g.u_l = 1; g.u_s = a.uout_ld; }
+    g.fs = (T*)pb->dfs;
+    g.k0 = a.ak0;
+    g.r0 = a.ar0;
+    g.inv_h = a.inv_h;
+    g.aF = a.aF;
+    g.nlines = a.nlines;
+    g.nlp = pl.dnlp;
+    g.n = a.n;
+    g.S = pl.dS;
+    g.H = pl.dH;
+    g.nwin = pl.dnwin;
+    g.mode = d.mode == adi::LINE_FINAL ? 1 : 0;
+    g.src_q = d.mode == adi::LINE_FINAL ? -1 : a.src_q;
+    g.src_s = a.src_s;
+    g.nthr = (int64_t)pl.dnlp * pl.dnwin;
+    return adi::launch_direct<T>(g, d.method, pb->st);
+}
+
 template <typename T>
 int run_impl(adi_problem* pb, int64_t nsteps) {
     int rc = adi::run_begin<T>(pb, pb->st);
@@ -554,7 +648,9 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
     for (int64_t s = 0; s < nsteps; ++s)
         for (int half = 0; half < 2; ++half) {
             const auto d = adi::run_pass<T>(pb, s, half, nsteps, nullptr);
-            if (pb->eps > 0.0)
+            if (pb->p.sweeps == 0)
+                HIP_TRY(launch_direct_pass<T>(pb, d), half == 0 ? "first direct pass" : "second direct pass");
+            else if (pb->eps > 0.0)
                 HIP_TRY(launch_tested<T>(pb, d), half == 0 ? "first line pass" : "second line pass");
             else
                 HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
@@ -719,6 +815,7 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         D.Vlo[0] = comp ? w + L.off[d][6] : nullptr;
         D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
         D.coef = w + L.off[d][8];
+        pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
     }
     pb->U = U; pb->V = V; pb->W = W;
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];
@@ -774,6 +871,7 @@ int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
         pb->eps_kmin = 0;
         return ADI_OK;
     }
+    if (pb->p.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) take no tolerance");
     if (min_sweeps < 2 || (min_sweeps & 1) || min_sweeps > pb->p.sweeps)
         return fail(ADI_EINVAL, "min_sweeps must be even and in [2, sweeps] (got %d, sweeps %d)", min_sweeps,
                     pb->p.sweeps);

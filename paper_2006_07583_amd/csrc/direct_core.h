@@ -1,0 +1,398 @@
+// Exact line solves of one Peaceman-Rachford stage over a window of a line
+// (the limit of infinitely many fixed-point sweeps).  Host- and
+// device-callable: the GPU kernel runs it per (line, window) thread; the host
+// runs it on a constant-coefficient line to size the window margins.
+//
+// Along a line with n cells, slot s holds the pressure value of index s and
+// the velocity value of node s.  With ak = a kappa, ar = a / rho and the
+// stage right-hand sides A (pressure, interior slots) and B (velocity, all
+// nodes), a stage solves, per line,
+//     Ubar + ak .* Dbar(vel) = A,      vel + ar .* G([0, Ubar, 0]) = B
+// (Section 2.1, eqs. ecua2:PR / ecua3:PR2 with homogeneous Dirichlet
+// pressure).  Both methods are rewritten as banded systems:
+//   MFD (Appendix B): eliminating vel gives
+//       (I - ak .* D4 (ar .* G4)) Ubar = A - ak .* D4 B,
+//     one unknown per cell 1..n, bandwidths (6, 6) at the closure rows and
+//     (3, 3) inside;
+//   CFD (Appendix A): with z = Pbar^-1 Qbar vel and y = P^-1 Q U the pair
+//       Pbar z + Qbar (ar .* y) = Qbar B,   P y + Q (ak .* z) = Q A
+//     is banded; unknowns z_s, y_s interleaved per slot (z_0 = z_n = 0 as
+//     trivial rows), bandwidths (7, 5).  Then Ubar = A - ak z, vel = B - ar y.
+// A window solves the rows of its slot range [w0, w1] with the unknowns
+// outside it dropped, by LU without pivoting in the Doolittle row order, and
+// keeps only the slots at least H from a cut.  The inverse of these banded
+// matrices decays geometrically away from the diagonal, so a margin H sized
+// from that decay makes the kept values those of the whole-line solve to
+// rounding.
+#pragma once
+#include <stdint.h>
+#include <algorithm>
+#include <cmath>
+#include <vector>
+#ifndef DIRECT_HD
+#include <hip/hip_runtime.h>
+#define DIRECT_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>   // host-only build of this header (a host check)
+#endif
+
+namespace adi {
+namespace direct {
+#ifdef DIRECT_HOST_ONLY
+using std::fma;
+#endif
+
+enum { MFD = 1, CFD = 0 };
+enum { OUT_NEXT = 0, OUT_STAGE = 1 };   // fused next explicit part / the stage result
+
+// Appendix B closure rows (first rows; the last rows are their centro-skew
+// images) and the interior stencil, without the 1/h factor.
+constexpr double D0[6] = {-4751.0 / 5192.0, 909.0 / 1298.0, 6091.0 / 15576.0,
+                          -1165.0 / 5192.0, 129.0 / 2596.0, -25.0 / 15576.0};
+constexpr double G0[6] = {-47888.0 / 14245.0, 1790.0 / 407.0, -14545.0 / 9768.0,
+                          8997.0 / 16280.0, -2335.0 / 22792.0, 25.0 / 9768.0};
+constexpr double G1[5] = {16.0 / 105.0, -31.0 / 24.0, 29.0 / 24.0, -3.0 / 40.0, 1.0 / 168.0};
+constexpr double ST[4] = {1.0 / 24.0, -9.0 / 8.0, 9.0 / 8.0, -1.0 / 24.0};
+
+template <int METHOD> struct Band;
+template <> struct Band<MFD> { static constexpr int ML = 6, MU = 6, RPS = 1; };
+template <> struct Band<CFD> { static constexpr int ML = 7, MU = 5, RPS = 2; };
+
+// D4 entry (cell c = 1..n, face f = 0..n), without 1/h.
+DIRECT_HD double dco(int n, int c, int f) {
+    if (c == 1) return (f >= 0 && f <= 5) ? D0[f] : 0.0;
+    if (c == n) { const int k = n - f; return (k >= 0 && k <= 5) ? -D0[k] : 0.0; }
+    const int k = f - (c - 2);
+    return (k >= 0 && k <= 3) ? ST[k] : 0.0;
+}
+// G4 entry (face f = 0..n, cell / boundary index c = 0..n+1), without 1/h.
+DIRECT_HD double gco(int n, int f, int c) {
+    if (f == 0) return (c >= 0 && c <= 5) ? G0[c] : 0.0;
+    if (f == 1) return (c >= 0 && c <= 4) ? G1[c] : 0.0;
+    if (f == n) { const int k = n + 1 - c; return (k >= 0 && k <= 5) ? -G0[k] : 0.0; }
+    if (f == n - 1) { const int k = n + 1 - c; return (k >= 0 && k <= 4) ? -G1[k] : 0.0; }
+    const int k = c - (f - 1);
+    return (k >= 0 && k <= 3) ? ST[k] : 0.0;
+}
+
+// Window bounds in slots: output slots [o0, o1], solved slots [w0, w1].
+struct Win {
+    int o0, o1, w0, w1;
+};
+DIRECT_HD Win window(int smin, int smax, int S, int H, int w) {
+    Win r;
+    r.o0 = smin + w * S;
+    r.o1 = r.o0 + S - 1 < smax ? r.o0 + S - 1 : smax;
+    r.w0 = r.o0 - H > smin ? r.o0 - H : smin;
+    r.w1 = r.o1 + H < smax ? r.o1 + H : smax;
+    return r;
+}
+// First unknown row whose factor the back substitution reads: the MFD
+// velocity of face f is formed at the step of its lowest cell, at most 4
+// below the face (the last closure row).
+DIRECT_HD int first_kept_row(int method, const Win& w) {
+    if (method == CFD) return 2 * w.o0;
+    return w.o0 - 4 > w.w0 ? w.o0 - 4 : w.w0;
+}
+
+// IO: A(s), B(s), K(s) (= ak), R(s) (= ar) reads; putU(s, x), putV(s, x)
+// writes; st(i, k) / ld(i, k) the factor store of kept row i.
+// Row i of the window system: e[k] is the entry in column i - ML + k.
+template <typename T, class IO>
+DIRECT_HD void row_mfd(const IO& io, int n, T inv_h, int c, T* e, T& rhs) {
+    constexpr int ML = Band<MFD>::ML, NB = Band<MFD>::ML + Band<MFD>::MU + 1;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) e[k] = T(0);
+    const T akc = io.K(c);
+    T dB = T(0);
+    if (c >= 4 && c <= n - 3) {
+        // interior: faces c-2..c+1, each coupling cells f-1..f+2
+#pragma unroll
+        for (int fo = -2; fo <= 1; ++fo) {
+            const int f = c + fo;
+            const T bf = io.B(f), rf = io.R(f);
+            const T d = T(ST[fo + 2]);
+            dB = fma(d, bf, dB);
+            const T dr = d * rf;
+#pragma unroll
+            for (int go = -1; go <= 2; ++go) e[ML + fo + go] = fma(dr, T(ST[go + 1]), e[ML + fo + go]);
+        }
+    } else {
+        // closure rows: faces c-5..c+4 cover every D4 row, cells f-4..f+5
+        // every G4 row
+#pragma unroll
+        for (int fo = -5; fo <= 4; ++fo) {
+            const int f = c + fo;
+            if (f < 0 || f > n) continue;
+            const T d = T(dco(n, c, f));
+            if (d == T(0)) continue;
+            const T bf = io.B(f), rf = io.R(f);
+            dB = fma(d, bf, dB);
+            const T dr = d * rf;
+#pragma unroll
+            for (int go = -4; go <= 5; ++go) {
+                const int cc = f + go;
+                if (fo + go < -ML || fo + go > NB - 1 - ML) continue;
+                if (cc < 1 || cc > n) continue;
+                e[ML + fo + go] = fma(dr, T(gco(n, f, cc)), e[ML + fo + go]);
+            }
+        }
+    }
+    const T s = -akc * inv_h * inv_h;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) e[k] *= s;
+    e[ML] += T(1);
+    rhs = io.A(c) - akc * inv_h * dB;
+}
+
+// CFD rows: i = 2 s is the z row of slot s, i = 2 s + 1 the y row.
+template <typename T, class IO>
+DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
+    constexpr int ML = Band<CFD>::ML, NB = Band<CFD>::ML + Band<CFD>::MU + 1;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) e[k] = T(0);
+    const int s = i >> 1;
+    rhs = T(0);
+    if ((i & 1) == 0) {
+        // z row: Pbar z + Qbar (ar y) = Qbar B on interior nodes; z_0 = z_n = 0
+        if (s == 0 || s == n) { e[ML] = T(1); return; }
+        // offsets: z_{s+k} at 2k, y_{s+k} at 2k + 1
+        if (s == 1) {
+            e[ML] = T(6); e[ML + 2] = T(6);
+        } else if (s == n - 1) {
+            e[ML - 2] = T(6); e[ML] = T(6);
+        } else {
+            e[ML - 2] = T(1); e[ML] = T(4); e[ML + 2] = T(1);
+        }
+        if (s == 1 || s == n - 1) {
+            const int j0 = s == 1 ? 0 : n - 3;
+            const T q[4] = {T(-1), T(-9), T(9), T(1)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int j = j0 + k;
+                const T qh = q[k] * inv_h;
+                rhs = fma(qh, io.B(j), rhs);
+                e[ML + 2 * (j - s) + 1] = qh * io.R(j);
+            }
+        } else {
+            const T qh = T(3) * inv_h;
+            rhs = qh * (io.B(s + 1) - io.B(s - 1));
+            e[ML - 1] = -qh * io.R(s - 1);
+            e[ML + 3] = qh * io.R(s + 1);
+        }
+        return;
+    }
+    // y row: P y + Q (ak z) = Q A, z and A on interior nodes only;
+    // offsets: y_{s+k} at 2k, z_{s+k} at 2k - 1
+    if (s == 0) {
+        e[ML] = T(6); e[ML + 2] = T(18);
+    } else if (s == n) {
+        e[ML - 2] = T(18); e[ML] = T(6);
+    } else {
+        e[ML - 2] = T(1); e[ML] = T(4); e[ML + 2] = T(1);
+    }
+    if (s == 0 || s == n) {
+        const T q0[4] = {T(-17), T(9), T(9), T(-1)};
+        const T qn[4] = {T(1), T(-9), T(-9), T(17)};
+        const int j0 = s == 0 ? 0 : n - 3;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = j0 + k;
+            if (j < 1 || j > n - 1) continue;
+            const T qh = (s == 0 ? q0[k] : qn[k]) * inv_h;
+            rhs = fma(qh, io.A(j), rhs);
+            e[ML + 2 * (j - s) - 1] = qh * io.K(j);
+        }
+    } else {
+        const T qh = T(3) * inv_h;
+        if (s + 1 <= n - 1) {
+            rhs = fma(qh, io.A(s + 1), rhs);
+            e[ML + 1] = qh * io.K(s + 1);
+        }
+        if (s - 1 >= 1) {
+            rhs = fma(-qh, io.A(s - 1), rhs);
+            e[ML - 3] = -qh * io.K(s - 1);
+        }
+    }
+}
+
+// MFD velocity of face f from the cells held in x[0..MU] (x[t] = cell c + t).
+template <typename T>
+DIRECT_HD T g_of(int n, int f, int c, const T* x) {
+    T g = T(0);
+#pragma unroll
+    for (int t = 0; t <= Band<MFD>::MU; ++t) {
+        const int cc = c + t;
+        if (cc >= 1 && cc <= n) g = fma(T(gco(n, f, cc)), x[t], g);
+    }
+    return g;
+}
+
+// Solve window w of one line and write its output slots.  mode OUT_NEXT
+// writes 2 Ubar - A (+ aF at the source slot src_s when src_s > 0) and
+// 2 vel - B, the explicit part of the next stage along the same lines;
+// OUT_STAGE writes Ubar and vel.
+template <typename T, int METHOD, class IO>
+DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, int mode, int src_s, T aF) {
+    constexpr int ML = Band<METHOD>::ML, MU = Band<METHOD>::MU, NB = ML + MU + 1;
+    const int smin = METHOD == MFD ? 1 : 0;
+    const Win W = window(smin, n, S, H, w);
+    const int r0 = METHOD == MFD ? W.w0 : 2 * W.w0;
+    const int r1 = METHOD == MFD ? W.w1 : 2 * W.w1 + 1;
+    const int rb = first_kept_row(METHOD, W);
+
+    // forward: Doolittle rows with the last ML normalised U rows in registers
+    T ur[ML][MU], yr[ML];
+#pragma unroll
+    for (int j = 0; j < ML; ++j) {
+        yr[j] = T(0);
+#pragma unroll
+        for (int t = 0; t < MU; ++t) ur[j][t] = T(0);
+    }
+    for (int i = r0; i <= r1; ++i) {
+        T e[NB], r;
+        if (METHOD == MFD) row_mfd<T>(io, n, inv_h, i, e, r);
+        else row_cfd<T>(io, n, inv_h, i, e, r);
+        // unknowns outside the window are dropped
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int col = i - ML + k;
+            if (col < r0 || col > r1) e[k] = T(0);
+        }
+        // eliminate with rows i-ML .. i-1 (ur[0] is row i-ML)
+#pragma unroll
+        for (int c = 0; c < ML; ++c) {
+            const T f = e[c];
+#pragma unroll
+            for (int t = 1; t <= MU; ++t)
+                if (c + t < NB) e[c + t] = fma(-f, ur[c][t - 1], e[c + t]);
+            r = fma(-f, yr[c], r);
+        }
+        const T inv = T(1) / e[ML];
+#pragma unroll
+        for (int j = 0; j < ML - 1; ++j) {
+            yr[j] = yr[j + 1];
+#pragma unroll
+            for (int t = 0; t < MU; ++t) ur[j][t] = ur[j + 1][t];
+        }
+        yr[ML - 1] = r * inv;
+#pragma unroll
+        for (int t = 0; t < MU; ++t) ur[ML - 1][t] = e[ML + 1 + t] * inv;
+        if (i >= rb) {
+            io.st(i - rb, 0, yr[ML - 1]);
+#pragma unroll
+            for (int t = 0; t < MU; ++t) io.st(i - rb, t + 1, ur[ML - 1][t]);
+        }
+    }
+
+    // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}; x[0] = x_i, x[t] = x_{i+t}
+    T x[MU + 1];
+#pragma unroll
+    for (int t = 0; t <= MU; ++t) x[t] = T(0);
+    for (int i = r1; i >= rb; --i) {
+        T v = io.ld(i - rb, 0);
+#pragma unroll
+        for (int t = MU; t >= 1; --t) x[t] = x[t - 1];
+#pragma unroll
+        for (int t = 1; t <= MU; ++t) v = fma(-io.ld(i - rb, t), x[t], v);
+        x[0] = v;
+        if (METHOD == MFD) {
+            const int c = i;
+            if (c >= W.o0 && c <= W.o1) {
+                const T A = io.A(c);
+                T u = mode == OUT_NEXT ? fma(T(2), v, -A) : v;
+                if (mode == OUT_NEXT && c == src_s) u += aF;
+                io.putU(c, u);
+            }
+            // faces whose lowest cell is c
+            const int fo0 = w == 0 ? 0 : W.o0;
+            auto face = [&](int f) {
+                if (f < fo0 || f > W.o1) return;
+                const T g = g_of<T>(n, f, c, x) * inv_h;
+                const T B = io.B(f), rr = io.R(f);
+                io.putV(f, mode == OUT_NEXT ? fma(T(-2) * rr, g, B) : fma(-rr, g, B));
+            };
+            if (c == 1) { face(0); face(1); }
+            if (c + 1 <= n - 2) face(c + 1);
+            if (c == n - 3) face(n - 1);
+            if (c == n - 4) face(n);
+        } else {
+            const int s = i >> 1;
+            if (s >= W.o0 && s <= W.o1) {
+                if (i & 1) {
+                    const T B = io.B(s), rr = io.R(s);
+                    io.putV(s, mode == OUT_NEXT ? fma(T(-2) * rr, v, B) : fma(-rr, v, B));
+                } else if (s >= 1 && s <= n - 1) {
+                    const T A = io.A(s), kk = io.K(s);
+                    T u = mode == OUT_NEXT ? fma(T(-2) * kk, v, A) : fma(-kk, v, A);
+                    if (mode == OUT_NEXT && s == src_s) u += aF;
+                    io.putU(s, u);
+                }
+            }
+        }
+    }
+}
+
+// Slots and kept unknown rows of the windows of a line.
+DIRECT_HD int direct_smin(int method) { return method == MFD ? 1 : 0; }
+inline int direct_nwin(int method, int n, int S) {
+    const int ns = n - direct_smin(method) + 1;
+    return (ns + S - 1) / S;
+}
+// Largest number of kept rows over the windows (factor store per thread).
+inline int direct_rows(int method, int n, int S, int H) {
+    int best = 0;
+    const int nw = direct_nwin(method, n, S), smin = direct_smin(method);
+    for (int w = 0; w < nw; ++w) {
+        const Win W = window(smin, n, S, H, w);
+        const int r1 = method == MFD ? W.w1 : 2 * W.w1 + 1;
+        const int rows = r1 - first_kept_row(method, W) + 1;
+        if (rows > best) best = rows;
+    }
+    return best;
+}
+
+// A line held in host arrays (slots 0..n+1), for the margin computation
+// and host checks.
+template <typename T>
+struct HostLine {
+    const T *a, *b, *k, *r;
+    T *u, *v, *fs;
+    int nrow;   // kept rows per window (factor store stride)
+    T A(int s) const { return a[s]; }
+    T B(int s) const { return b[s]; }
+    T K(int s) const { return k[s]; }
+    T R(int s) const { return r[s]; }
+    void putU(int s, T x) const { u[s] = x; }
+    void putV(int s, T x) const { v[s] = x; }
+    void st(int i, int kk, T x) const { fs[(size_t)i * 8 + kk] = x; }
+    T ld(int i, int kk) const { return fs[(size_t)i * 8 + kk]; }
+};
+
+// Margin of the windows, in slots: the distance from a unit impulse in the
+// pressure right-hand side beyond which the whole-line stage solution of a
+// constant-coefficient line with (a kappa)(a / rho) / h^2 = c2 stays below
+// tol of its peak, plus the reach of the operators.  -1 if the solution has
+// not fallen that far within 4096 slots.
+inline int direct_margin(int method, double c2, double tol) {
+    const double ak = std::sqrt(c2);
+    for (int L = 128; L <= 4096; L *= 2) {
+        const int n = 2 * L;
+        std::vector<double> A(n + 2, 0.0), B(n + 2, 0.0), K(n + 2, ak), R(n + 2, ak), U(n + 2, 0.0),
+            V(n + 2, 0.0), F((size_t)2 * (n + 2) * 8, 0.0);
+        A[L] = 1.0;
+        HostLine<double> io{A.data(), B.data(), K.data(), R.data(), U.data(), V.data(), F.data(), 0};
+        if (method == MFD) solve_window<double, MFD>(io, n, n, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        else solve_window<double, CFD>(io, n, n + 1, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        double peak = 0.0;
+        for (int s = 0; s <= n; ++s) peak = std::fmax(peak, std::fmax(std::fabs(U[s]), std::fabs(V[s])));
+        int far = -1;
+        for (int s = 0; s <= n; ++s)
+            if (std::fmax(std::fabs(U[s]), std::fabs(V[s])) >= tol * peak) far = std::max(far, std::abs(s - L));
+        if (far < L - 16) return far + 6;
+    }
+    return -1;
+}
+
+}  // namespace direct
+}  // namespace adi

@@ -16,6 +16,9 @@ struct Plan {
                    // compensated mode) or 3 (line_pass3.hip)
     int cfg = 0;   // tile shape of the single-window kernel
     int seg = 0;   // slots per lane segment of the multi-window kernel
+    // direct (exact) line solves: output slots per window, margin, windows,
+    // kept rows per window, lines padded to a multiple of 64
+    int dS = 0, dH = 0, dnwin = 0, drows = 0, dnlp = 0;
 };
 
 // One pass, ready to launch.
@@ -24,6 +27,7 @@ struct PassDesc {
     LinePassArgs<T> a;
     int ver, cfg, method, mode;
     bool comp;
+    int dir;
     int tiles() const { return a.nlg * a.nwin; }
     // kernel variant: passes with equal keys can share a grouped launch
     int key() const { return ((ver * 4 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0); }
@@ -79,6 +83,8 @@ struct adi_problem {
     double eps = 0.0;
     int eps_kmin = 0;
     void* eps_buf = nullptr;
+    // factor store of the direct solves (sweeps 0), part of the workspace
+    void* dfs = nullptr;
 };
 
 namespace adi {

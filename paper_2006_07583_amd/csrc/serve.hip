@@ -501,6 +501,7 @@ int adi_submit(adi_server* S, const adi_request* rq, uint64_t* ticket) {
     if (rq->struct_size != sizeof(adi_request)) return fail(ADI_EINVAL, "bad adi_request struct_size");
     if (!rq->U || !rq->V || !rq->W) return fail(ADI_EINVAL, "U, V and W are required");
     if (rq->nsteps < 1) return fail(ADI_EINVAL, "nsteps must be >= 1");
+    if (rq->params.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) are not served");
     size_t ws = 0;
     int rc = adi_workspace_size(&rq->params, rq->K != nullptr, rq->Rv != nullptr, rq->Rw != nullptr, &ws);
     if (rc != ADI_OK) return rc;

@@ -54,7 +54,9 @@ def test_workspace_size_grows_with_materials():
 
 @pytest.mark.parametrize("mutate,expect", [
     (lambda p: setattr(p, "sweeps", 7), "even"),
-    (lambda p: setattr(p, "sweeps", 0), "even"),
+    (lambda p: setattr(p, "sweeps", -2), "even"),
+    (lambda p: (setattr(p, "sweeps", 0), setattr(p, "dtype", adi.FP32C)), "compensated"),
+    (lambda p: (setattr(p, "sweeps", 0), setattr(p, "dt", 400.0 / 64)), "too large"),
     (lambda p: setattr(p, "nx", 7), ">= 8"),
     (lambda p: setattr(p, "dt", 1.2 / 64), "cfl"),
     (lambda p: setattr(p, "method", 5), "method"),
@@ -136,3 +138,20 @@ def test_server_validates_arguments_on_the_host():
     assert L.adi_poll(None, 1, ctypes.byref(st)) == -1
     assert L.adi_wait(None, 1) == -1
     assert L.adi_server_destroy(None) == 0
+
+
+def test_direct_solves_accept_large_steps_and_size_their_store():
+    """sweeps 0 (direct solves) lifts the divergence limit of the sweeps and
+    adds the factor store to the workspace, larger for larger steps."""
+    n = 1024
+    p = good(n=n)
+    p.dt = 1.2 / n
+    assert _ws(p)[0] == -1
+    p.sweeps = 0
+    rc, small = _ws(p)
+    assert rc == 0
+    p.dt = 4.0 / n
+    rc, big = _ws(p)
+    assert rc == 0 and big > small
+    p.sweeps, p.dt = 6, 0.5 / n
+    assert _ws(p)[1] < small
