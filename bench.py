@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tolerance-steps", type=int, default=40,
                     help="steps of the tolerance-tested leg (0 = skip)")
+    ap.add_argument("--direct-steps", type=int, default=10,
+                    help="steps of the direct-solve leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the batched 256-problem workload (0 = skip it)")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -136,6 +138,22 @@ def tolerance_case(n, steps):
         r = gpu_case(adi.CFD, adi.FP32, n, steps, 2, 8, tol=(eps, 6))
         out[name] = {"pass_us": r["per_pass"] * 1e6, "sweeps_per_pass": r["sweeps_per_pass"],
                      "vs_fixed6": r["per_pass"] / fixed["per_pass"], "finite": r["finite"]}
+    return out
+
+
+def direct_case(n, steps):
+    """Direct (exact) line solves (sweeps 0, windowed banded LU per line) on
+    the layered seismic workload at n^2 and CFL 0.8, every method and
+    precision, beside the 6-sweep pass; the rate counts the same algorithmic
+    bytes as the sweep pass."""
+    from paper_2006_07583_amd import adi
+    out = {"workload": f"layered seismic {n}x{n}, cfl 0.8, direct line solves"}
+    for method, mname in ((adi.CFD, "cfd"), (adi.MFD, "mfd")):
+        for dtype, dname, elem in ((adi.FP32, "fp32", 4), (adi.FP64, "fp64", 8)):
+            r = gpu_case(method, dtype, n, steps, 2, 0)
+            alg = alg_bytes_per_pass(method, n, elem, True, False)
+            out[f"{mname}_{dname}"] = {"pass_us": r["per_pass"] * 1e6, "pt_steps_s": n * n / (2 * r["per_pass"]),
+                                       "alg_GBs": alg / r["per_pass"] / 1e9, "finite": r["finite"]}
     return out
 
 
@@ -390,6 +408,12 @@ def main():
               f"6 then 8 {tc['none_pass']['pass_us']:.1f} us ({tc['none_pass']['vs_fixed6']:.2f}x)",
               file=sys.stderr, flush=True)
         out["tolerance"] = tc
+    if args.direct_steps > 0:
+        dc = direct_case(n, args.direct_steps)
+        print("# direct line solves: " + ", ".join(
+            f"{k} {v['pass_us']:.0f} us/pass ({v['alg_GBs']:.0f} GB/s alg)" for k, v in dc.items() if k != "workload"),
+              file=sys.stderr, flush=True)
+        out["direct"] = dc
     if args.batch_steps > 0:
         bc = batch_case(args.batch_steps, args.batch_count)
         print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "
