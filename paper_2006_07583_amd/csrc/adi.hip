@@ -78,8 +78,10 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
         p.deep = 1;
     } else {
         // multi-window: the wave-per-line kernel (barrier-free sweeps); the
-        // segment kernel for the compensated mode, which it alone implements
-        p.ver = dtype == ADI_FP32C ? 2 : 3;
+        // segment kernel for the compensated mode, which it alone implements,
+        // and for the direct solves, whose thread-per-line passes read the
+        // slot-major layout it keeps (64 lines at one slot are contiguous)
+        p.ver = (dtype == ADI_FP32C || sweeps == 0) ? 2 : 3;
         p.seg = adi::line2_seg(dtype);
         // windows of LINE_WS slots overlapping by 2H; the first and last own
         // LINE_WS - H central slots, the others S = LINE_WS - 2H
@@ -158,6 +160,7 @@ namespace {
 struct Layout {
     size_t off[2][9];
     size_t fs_off;   // factor store of the direct solves (shared by both directions)
+    size_t dc_off;   // their constant materials
     size_t total;
 };
 
@@ -187,6 +190,8 @@ Layout layout(const adi_problem& pb) {
             fs = std::max(fs, (size_t)pl->dnlp * pl->dnwin * pl->drows * nv * pb.esz);
         cur += (fs + 255) / 256 * 256;
     }
+    L.dc_off = cur;
+    if (p.sweeps == 0) cur += 256;
     L.total = cur;
     return L;
 }
@@ -201,17 +206,19 @@ int direct_margin_of(const adi_params& p) {
 }
 
 // Windows of the direct solves along one direction: enough windows for
-// about 2^17 threads, each keeping at least twice its margin.
+// about 2^19 threads (8 waves per SIMD of the interior-band kernel), each
+// keeping at least twice its margin.
 void direct_plan(Plan& pl, const adi_params& p) {
     const int m = p.method == ADI_MFD ? adi::direct::MFD : adi::direct::CFD;
     const int ns = pl.n - adi::direct::direct_smin(m) + 1;
     pl.dH = direct_margin_of(p);
     pl.dnlp = (pl.nlines + 63) / 64 * 64;
-    const int want = std::max(1, (1 << 17) / pl.dnlp);
+    const int want = std::max(1, (1 << 19) / pl.dnlp);
     int S = std::max({2 * pl.dH, 16, (ns + want - 1) / want});
     pl.dS = std::min(S, ns);
     pl.dnwin = adi::direct::direct_nwin(m, pl.n, pl.dS);
     pl.drows = adi::direct::direct_rows(m, pl.n, pl.dS, pl.dH);
+    adi::direct::narrow_range(m, pl.n, pl.dS, pl.dH, pl.dwa, pl.dwb);
 }
 
 int validate(const adi_params* p) {
@@ -615,6 +622,9 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     pres_in(a.ak, a.ak_ld, g.k, g.k_l, g.k_s);
     vel_at(a.vin, a.vin_ld, g.b, g.b_l, g.b_s);
     vel_at(a.ar, a.ar_ld, g.r, g.r_l, g.r_s);
+    // constant materials: the two values bind_materials stored, strides 0
+    if (!g.k) g.k = (const T*)pb->dconst;
+    if (!g.r) g.r = (const T*)pb->dconst + 1;
     const T* vo;
     vel_at(a.vout, a.vout_ld, vo, g.v_l, g.v_s);
     g.v = const_cast<T*>(vo);
@@ -624,8 +634,6 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     if (a.utrans) { g.u = uo - 1; g.u_l = a.uout_ld; g.u_s = 1; }
     else { g.u = uo - a.uout_ld; g.u_l = 1; g.u_s = a.uout_ld; }
     g.fs = (T*)pb->dfs;
-    g.k0 = a.ak0;
-    g.r0 = a.ar0;
     g.inv_h = a.inv_h;
     g.aF = a.aF;
     g.nlines = a.nlines;
@@ -634,11 +642,23 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     g.S = pl.dS;
     g.H = pl.dH;
     g.nwin = pl.dnwin;
+    g.drows = pl.drows;
     g.mode = d.mode == adi::LINE_FINAL ? 1 : 0;
     g.src_q = d.mode == adi::LINE_FINAL ? -1 : a.src_q;
     g.src_s = a.src_s;
-    g.nthr = (int64_t)pl.dnlp * pl.dnwin;
-    return adi::launch_direct<T>(g, d.method, pb->st);
+    // windows before dwa and after dwb reach the closure rows
+    auto go = [&](int wbase, int wcount, bool wide) {
+        if (wcount <= 0) return hipSuccess;
+        g.wbase = wbase;
+        g.wcount = wcount;
+        g.nthr = (int64_t)pl.dnlp * wcount;
+        return adi::launch_direct<T>(g, d.method, wide, pb->st);
+    };
+    if (pl.dwa > pl.dwb) return go(0, pl.dnwin, true);
+    hipError_t e = go(0, pl.dwa, true);
+    if (e == hipSuccess) e = go(pl.dwa, pl.dwb - pl.dwa + 1, false);
+    if (e == hipSuccess) e = go(pl.dwb + 1, pl.dnwin - pl.dwb - 1, true);
+    return e;
 }
 
 template <typename T>
@@ -666,6 +686,9 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
     // the workspace starts zeroed: line-major arrays keep zeros on the
     // boundary slots and on the padding lines
     HIP_TRY(hipMemsetAsync(pb->ws, 0, pb->ws_bytes, st), "workspace clear");
+    const T dconst[2] = {(T)(pb->a * p.kappa0), (T)(pb->a * p.rinv0)};
+    if (pb->dconst)
+        HIP_TRY(hipMemcpyAsync(pb->dconst, dconst, sizeof(dconst), hipMemcpyHostToDevice, st), "constant materials");
     for (int d = 0; d < 2; ++d) {
         if (K) HIP_TRY(pres_to_dir<T>(pb, d, (T*)pb->d[d].K, K, ldK, a, st), "a kappa");
         const T* R = d == 0 ? Rv : Rw;
@@ -816,6 +839,7 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
         D.coef = w + L.off[d][8];
         pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
+        pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
     }
     pb->U = U; pb->V = V; pb->W = W;
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];

@@ -54,9 +54,14 @@ constexpr double G0[6] = {-47888.0 / 14245.0, 1790.0 / 407.0, -14545.0 / 9768.0,
 constexpr double G1[5] = {16.0 / 105.0, -31.0 / 24.0, 29.0 / 24.0, -3.0 / 40.0, 1.0 / 168.0};
 constexpr double ST[4] = {1.0 / 24.0, -9.0 / 8.0, 9.0 / 8.0, -1.0 / 24.0};
 
+// Bandwidths of the window systems: with the closure rows of the line ends
+// (WIDE) and of interior rows only, (3, 3) for both methods.
 template <int METHOD> struct Band;
 template <> struct Band<MFD> { static constexpr int ML = 6, MU = 6, RPS = 1; };
 template <> struct Band<CFD> { static constexpr int ML = 7, MU = 5, RPS = 2; };
+template <int METHOD, bool WIDE> struct BandOf {
+    static constexpr int ML = WIDE ? Band<METHOD>::ML : 3, MU = WIDE ? Band<METHOD>::MU : 3;
+};
 
 // D4 entry (cell c = 1..n, face f = 0..n), without 1/h.
 DIRECT_HD double dco(int n, int c, int f) {
@@ -98,14 +103,13 @@ DIRECT_HD int first_kept_row(int method, const Win& w) {
 // IO: A(s), B(s), K(s) (= ak), R(s) (= ar) reads; putU(s, x), putV(s, x)
 // writes; st(i, k) / ld(i, k) the factor store of kept row i.
 // Row i of the window system: e[k] is the entry in column i - ML + k.
-template <typename T, class IO>
+template <typename T, int ML, int NB, bool WIDE, class IO>
 DIRECT_HD void row_mfd(const IO& io, int n, T inv_h, int c, T* e, T& rhs) {
-    constexpr int ML = Band<MFD>::ML, NB = Band<MFD>::ML + Band<MFD>::MU + 1;
 #pragma unroll
     for (int k = 0; k < NB; ++k) e[k] = T(0);
     const T akc = io.K(c);
     T dB = T(0);
-    if (c >= 4 && c <= n - 3) {
+    if (!WIDE || (c >= 4 && c <= n - 3)) {
         // interior: faces c-2..c+1, each coupling cells f-1..f+2
 #pragma unroll
         for (int fo = -2; fo <= 1; ++fo) {
@@ -117,7 +121,7 @@ DIRECT_HD void row_mfd(const IO& io, int n, T inv_h, int c, T* e, T& rhs) {
 #pragma unroll
             for (int go = -1; go <= 2; ++go) e[ML + fo + go] = fma(dr, T(ST[go + 1]), e[ML + fo + go]);
         }
-    } else {
+    } else if constexpr (WIDE) {
         // closure rows: faces c-5..c+4 cover every D4 row, cells f-4..f+5
         // every G4 row
 #pragma unroll
@@ -146,13 +150,27 @@ DIRECT_HD void row_mfd(const IO& io, int n, T inv_h, int c, T* e, T& rhs) {
 }
 
 // CFD rows: i = 2 s is the z row of slot s, i = 2 s + 1 the y row.
-template <typename T, class IO>
+template <typename T, int ML, int NB, bool WIDE, class IO>
 DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
-    constexpr int ML = Band<CFD>::ML, NB = Band<CFD>::ML + Band<CFD>::MU + 1;
 #pragma unroll
     for (int k = 0; k < NB; ++k) e[k] = T(0);
     const int s = i >> 1;
     rhs = T(0);
+    if constexpr (!WIDE) {
+        // interior slots 2..n-2 only: offsets within (3, 3)
+        const T qh = T(3) * inv_h;
+        e[ML - 2] = T(1); e[ML] = T(4); e[ML + 2] = T(1);
+        if ((i & 1) == 0) {
+            rhs = qh * (io.B(s + 1) - io.B(s - 1));
+            e[ML - 1] = -qh * io.R(s - 1);
+            e[ML + 3] = qh * io.R(s + 1);
+        } else {
+            rhs = qh * (io.A(s + 1) - io.A(s - 1));
+            e[ML + 1] = qh * io.K(s + 1);
+            e[ML - 3] = -qh * io.K(s - 1);
+        }
+        return;
+    }
     if ((i & 1) == 0) {
         // z row: Pbar z + Qbar (ar y) = Qbar B on interior nodes; z_0 = z_n = 0
         if (s == 0 || s == n) { e[ML] = T(1); return; }
@@ -216,25 +234,32 @@ DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
     }
 }
 
-// MFD velocity of face f from the cells held in x[0..MU] (x[t] = cell c + t).
-template <typename T>
-DIRECT_HD T g_of(int n, int f, int c, const T* x) {
+// MFD: write the velocity of face f (owned faces fo0..fo1), whose G4 row
+// reaches cells c..c+MU held in x.
+template <typename T, int MU, class IO>
+DIRECT_HD void put_face(const IO& io, int n, int f, int c, int fo0, int fo1, const T (&x)[MU + 1], T inv_h,
+                        int mode) {
+    if (f < fo0 || f > fo1) return;
     T g = T(0);
 #pragma unroll
-    for (int t = 0; t <= Band<MFD>::MU; ++t) {
+    for (int t = 0; t <= MU; ++t) {
         const int cc = c + t;
         if (cc >= 1 && cc <= n) g = fma(T(gco(n, f, cc)), x[t], g);
     }
-    return g;
+    g *= inv_h;
+    const T B = io.B(f), rr = io.R(f);
+    io.putV(f, mode == OUT_NEXT ? fma(T(-2) * rr, g, B) : fma(-rr, g, B));
 }
 
 // Solve window w of one line and write its output slots.  mode OUT_NEXT
 // writes 2 Ubar - A (+ aF at the source slot src_s when src_s > 0) and
 // 2 vel - B, the explicit part of the next stage along the same lines;
 // OUT_STAGE writes Ubar and vel.
-template <typename T, int METHOD, class IO>
+// WIDE = false is for windows whose rows are all interior rows (see
+// narrow_range).
+template <typename T, int METHOD, bool WIDE, class IO>
 DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, int mode, int src_s, T aF) {
-    constexpr int ML = Band<METHOD>::ML, MU = Band<METHOD>::MU, NB = ML + MU + 1;
+    constexpr int ML = BandOf<METHOD, WIDE>::ML, MU = BandOf<METHOD, WIDE>::MU, NB = ML + MU + 1;
     const int smin = METHOD == MFD ? 1 : 0;
     const Win W = window(smin, n, S, H, w);
     const int r0 = METHOD == MFD ? W.w0 : 2 * W.w0;
@@ -251,8 +276,8 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, i
     }
     for (int i = r0; i <= r1; ++i) {
         T e[NB], r;
-        if (METHOD == MFD) row_mfd<T>(io, n, inv_h, i, e, r);
-        else row_cfd<T>(io, n, inv_h, i, e, r);
+        if constexpr (METHOD == MFD) row_mfd<T, ML, NB, WIDE>(io, n, inv_h, i, e, r);
+        else row_cfd<T, ML, NB, WIDE>(io, n, inv_h, i, e, r);
         // unknowns outside the window are dropped
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -296,7 +321,7 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, i
 #pragma unroll
         for (int t = 1; t <= MU; ++t) v = fma(-io.ld(i - rb, t), x[t], v);
         x[0] = v;
-        if (METHOD == MFD) {
+        if constexpr (METHOD == MFD) {
             const int c = i;
             if (c >= W.o0 && c <= W.o1) {
                 const T A = io.A(c);
@@ -306,16 +331,17 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, i
             }
             // faces whose lowest cell is c
             const int fo0 = w == 0 ? 0 : W.o0;
-            auto face = [&](int f) {
-                if (f < fo0 || f > W.o1) return;
-                const T g = g_of<T>(n, f, c, x) * inv_h;
-                const T B = io.B(f), rr = io.R(f);
-                io.putV(f, mode == OUT_NEXT ? fma(T(-2) * rr, g, B) : fma(-rr, g, B));
-            };
-            if (c == 1) { face(0); face(1); }
-            if (c + 1 <= n - 2) face(c + 1);
-            if (c == n - 3) face(n - 1);
-            if (c == n - 4) face(n);
+            if constexpr (WIDE) {
+                if (c == 1) {
+                    put_face<T, MU>(io, n, 0, c, fo0, W.o1, x, inv_h, mode);
+                    put_face<T, MU>(io, n, 1, c, fo0, W.o1, x, inv_h, mode);
+                }
+                if (c + 1 <= n - 2) put_face<T, MU>(io, n, c + 1, c, fo0, W.o1, x, inv_h, mode);
+                if (c == n - 3) put_face<T, MU>(io, n, n - 1, c, fo0, W.o1, x, inv_h, mode);
+                if (c == n - 4) put_face<T, MU>(io, n, n, c, fo0, W.o1, x, inv_h, mode);
+            } else {
+                put_face<T, MU>(io, n, c + 1, c, fo0, W.o1, x, inv_h, mode);
+            }
         } else {
             const int s = i >> 1;
             if (s >= W.o0 && s <= W.o1) {
@@ -352,6 +378,23 @@ inline int direct_rows(int method, int n, int S, int H) {
     return best;
 }
 
+// Windows wa..wb hold interior rows only (MFD cells 4..n-3, CFD slots
+// 2..n-2) and are solved with the (3, 3) band; wa > wb when there are none.
+// The window starts and ends grow with w, so the set is contiguous.
+inline void narrow_range(int method, int n, int S, int H, int& wa, int& wb) {
+    const int nw = direct_nwin(method, n, S), smin = direct_smin(method);
+    const int lo = method == MFD ? 4 : 2, hi = method == MFD ? n - 3 : n - 2;
+    wa = nw;
+    wb = -1;
+    for (int w = 0; w < nw; ++w) {
+        const Win W = window(smin, n, S, H, w);
+        if (W.w0 >= lo && W.w1 <= hi) {
+            if (wa > w) wa = w;
+            wb = w;
+        }
+    }
+}
+
 // A line held in host arrays (slots 0..n+1), for the margin computation
 // and host checks.
 template <typename T>
@@ -382,8 +425,8 @@ inline int direct_margin(int method, double c2, double tol) {
             V(n + 2, 0.0), F((size_t)2 * (n + 2) * 8, 0.0);
         A[L] = 1.0;
         HostLine<double> io{A.data(), B.data(), K.data(), R.data(), U.data(), V.data(), F.data(), 0};
-        if (method == MFD) solve_window<double, MFD>(io, n, n, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
-        else solve_window<double, CFD>(io, n, n + 1, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        if (method == MFD) solve_window<double, MFD, true>(io, n, n, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        else solve_window<double, CFD, true>(io, n, n + 1, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
         double peak = 0.0;
         for (int s = 0; s <= n; ++s) peak = std::fmax(peak, std::fmax(std::fabs(U[s]), std::fabs(V[s])));
         int far = -1;

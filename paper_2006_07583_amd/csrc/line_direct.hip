@@ -1,8 +1,8 @@
 // Direct (exact) line passes: each thread solves one window of one line with
 // the banded LU of direct_core.h.  A wave holds 64 consecutive lines of the
 // same window, so every branch on the slot index is uniform across the wave;
-// the factor store is laid out [kept row][value][thread] so that each of its
-// accesses is one contiguous 64-lane segment.
+// the factor store is laid out [wave][kept row][value][lane]: each access is
+// one contiguous 64-lane segment and a wave's rows follow each other.
 #include "direct_core.h"
 #include "line_pass.h"
 
@@ -10,51 +10,60 @@ namespace adi {
 
 namespace {
 
-template <typename T, int METHOD>
+template <typename T, int NV>   // NV: values per kept row
 struct DevLine {
-    static constexpr int NV = direct::Band<METHOD>::MU + 1;   // values per kept row
-    const DirectArgs<T>* p;
+    DirectArgs<T> a;   // a copy: its fields stay in scalar registers
     int64_t q;
     int64_t tid;
     bool live;
-    DIRECT_HD T A(int s) const { return p->a[q * p->a_l + s * p->a_s]; }
-    DIRECT_HD T B(int s) const { return p->b[q * p->b_l + s * p->b_s]; }
-    DIRECT_HD T K(int s) const { return p->k ? p->k[q * p->k_l + s * p->k_s] : p->k0; }
-    DIRECT_HD T R(int s) const { return p->r ? p->r[q * p->r_l + s * p->r_s] : p->r0; }
+    DIRECT_HD T A(int s) const { return a.a[q * a.a_l + s * a.a_s]; }
+    DIRECT_HD T B(int s) const { return a.b[q * a.b_l + s * a.b_s]; }
+    DIRECT_HD T K(int s) const { return a.k[q * a.k_l + s * a.k_s]; }
+    DIRECT_HD T R(int s) const { return a.r[q * a.r_l + s * a.r_s]; }
     DIRECT_HD void putU(int s, T x) const {
-        if (live) p->u[q * p->u_l + s * p->u_s] = x;
+        if (live) a.u[q * a.u_l + s * a.u_s] = x;
     }
     DIRECT_HD void putV(int s, T x) const {
-        if (live) p->v[q * p->v_l + s * p->v_s] = x;
+        if (live) a.v[q * a.v_l + s * a.v_s] = x;
     }
-    DIRECT_HD void st(int i, int k, T x) const { p->fs[((int64_t)i * NV + k) * p->nthr + tid] = x; }
-    DIRECT_HD T ld(int i, int k) const { return p->fs[((int64_t)i * NV + k) * p->nthr + tid]; }
+    DIRECT_HD int64_t fi(int i, int k) const {
+        return (((tid >> 6) * a.drows + i) * NV + k) * 64 + (tid & 63);
+    }
+    DIRECT_HD void st(int i, int k, T x) const { a.fs[fi(i, k)] = x; }
+    DIRECT_HD T ld(int i, int k) const { return a.fs[fi(i, k)]; }
 };
 
-template <typename T, int METHOD>
+template <typename T, int METHOD, bool WIDE>
 __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
     const int64_t tid = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (tid >= p.nthr) return;
-    const int q = (int)(tid % p.nlp), w = (int)(tid / p.nlp);
+    const int q = (int)(tid % p.nlp), w = p.wbase + (int)(tid / p.nlp);
     const bool live = q < p.nlines;
-    const DevLine<T, METHOD> io{&p, live ? q : 0, tid, live};
+    const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live};
     const int src = (live && q == p.src_q) ? p.src_s : -1;
-    direct::solve_window<T, METHOD>(io, p.n, p.S, p.H, w, p.inv_h, p.mode, src, p.aF);
+    direct::solve_window<T, METHOD, WIDE>(io, p.n, p.S, p.H, w, p.inv_h, p.mode, src, p.aF);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_direct(const DirectArgs<T>& p, int method, hipStream_t st) {
-    if (p.nthr <= 0 || p.nthr % 64 || p.nlp % 64 || (int64_t)p.nlp * p.nwin != p.nthr) return hipErrorInvalidValue;
+hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st) {
+    if (p.wcount <= 0 || p.wbase < 0 || p.wbase + p.wcount > p.nwin || p.nlp % 64 ||
+        (int64_t)p.nlp * p.wcount != p.nthr)
+        return hipErrorInvalidValue;
     const dim3 grid((unsigned)(p.nthr / 64)), block(64);
-    if (method == LINE_MFD) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD>), grid, block, 0, st, p);
+    if (method == LINE_MFD) {
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, false>), grid, block, 0, st, p);
+    } else {
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, false>), grid, block, 0, st, p);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_direct<float>(const DirectArgs<float>&, int, hipStream_t);
-template hipError_t launch_direct<double>(const DirectArgs<double>&, int, hipStream_t);
+template hipError_t launch_direct<float>(const DirectArgs<float>&, int, bool, hipStream_t);
+template hipError_t launch_direct<double>(const DirectArgs<double>&, int, bool, hipStream_t);
 
 int direct_values_per_row(int method) {
     return method == LINE_MFD ? direct::Band<direct::MFD>::MU + 1 : direct::Band<direct::CFD>::MU + 1;

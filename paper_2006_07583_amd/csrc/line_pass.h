@@ -103,28 +103,32 @@ hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int atte
                             int kmin, int kmax, long long* stats, hipStream_t st);
 
 // Direct (exact) line pass (line_direct.hip): thread t solves window
-// t / nlp of line t % nlp (lines padded to nlp, a multiple of 64).  Element
+// wbase + t / nlp of line t % nlp (lines padded to nlp, a multiple of 64).  Element
 // (line q, slot s) of each array sits at base[q * x_l + s * x_s]; A and K are
 // pressure-type (slots 1..n-1 for CFD, 1..n for MFD), B, R, V velocity-type
 // (slots 0..n).  mode 0 writes 2 Ubar - A (+ aF at (src_q, src_s)) and
-// 2 vel - B, mode 1 Ubar and vel.  fs holds nthr * rows * values-per-row
+// 2 vel - B, mode 1 Ubar and vel.  fs holds nthr * drows * values-per-row
 // elements.
 template <typename T>
 struct DirectArgs {
     const T* a; int64_t a_l, a_s;
     const T* b; int64_t b_l, b_s;
-    const T* k; int64_t k_l, k_s;   // a kappa, NULL -> k0
-    const T* r; int64_t r_l, r_s;   // a / rho, NULL -> r0
+    const T* k; int64_t k_l, k_s;   // a kappa (a constant: one element, strides 0)
+    const T* r; int64_t r_l, r_s;   // a / rho (likewise)
     T* u; int64_t u_l, u_s;
     T* v; int64_t v_l, v_s;
     T* fs;
-    T k0, r0, inv_h, aF;
+    T inv_h, aF;
     int nlines, nlp, n, S, H, nwin, mode;
     int src_q, src_s;
-    int64_t nthr;
+    int wbase, wcount;   // this launch solves windows wbase .. wbase + wcount - 1
+    int drows;           // kept rows per thread in fs (the largest over the windows)
+    int64_t nthr;        // nlp * wcount
 };
+// wide: the closure rows of the line ends are in reach (windows 0 and past
+// narrow_last); otherwise the interior (3, 3) band
 template <typename T>
-hipError_t launch_direct(const DirectArgs<T>& p, int method, hipStream_t st);
+hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st);
 int direct_values_per_row(int method);
 
 }  // namespace adi

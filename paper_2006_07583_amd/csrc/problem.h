@@ -18,7 +18,8 @@ struct Plan {
     int seg = 0;   // slots per lane segment of the multi-window kernel
     // direct (exact) line solves: output slots per window, margin, windows,
     // kept rows per window, lines padded to a multiple of 64
-    int dS = 0, dH = 0, dnwin = 0, drows = 0, dnlp = 0;
+    // interior-band windows dwa..dwb
+    int dS = 0, dH = 0, dnwin = 0, drows = 0, dnlp = 0, dwa = 0, dwb = -1;
 };
 
 // One pass, ready to launch.
@@ -83,8 +84,11 @@ struct adi_problem {
     double eps = 0.0;
     int eps_kmin = 0;
     void* eps_buf = nullptr;
-    // factor store of the direct solves (sweeps 0), part of the workspace
+    // factor store of the direct solves (sweeps 0) and the constant
+    // materials {a kappa0, a rinv0} they read when K or R is absent, both
+    // part of the workspace
     void* dfs = nullptr;
+    void* dconst = nullptr;
 };
 
 namespace adi {

@@ -31,11 +31,21 @@ int main(int argc, char** argv) {
     const int rows = direct_rows(method, n, S, H);
     std::vector<double> fs((size_t)rows * 8, 0.0);
     HostLine<double> io{a.data(), b.data(), k.data(), r.data(), u.data(), v.data(), fs.data(), rows};
+    // the library's dispatch: windows 1..narrow_last with the interior band
     const int nw = direct_nwin(method, n, S);
+    int wa, wb;
+    narrow_range(method, n, S, H, wa, wb);
     for (int w = 0; w < nw; ++w) {
-        if (method == MFD) solve_window<double, MFD>(io, n, S, H, w, inv_h, mode, src_s, aF);
-        else solve_window<double, CFD>(io, n, S, H, w, inv_h, mode, src_s, aF);
+        const bool narrow = w >= wa && w <= wb;
+        if (method == MFD) {
+            if (narrow) solve_window<double, MFD, false>(io, n, S, H, w, inv_h, mode, src_s, aF);
+            else solve_window<double, MFD, true>(io, n, S, H, w, inv_h, mode, src_s, aF);
+        } else {
+            if (narrow) solve_window<double, CFD, false>(io, n, S, H, w, inv_h, mode, src_s, aF);
+            else solve_window<double, CFD, true>(io, n, S, H, w, inv_h, mode, src_s, aF);
+        }
     }
+    std::fprintf(stderr, "windows %d, interior-band windows %d\n", nw, wb >= wa ? wb - wa + 1 : 0);
     for (auto* arr : {&u, &v}) {
         for (double x : *arr) std::printf("%.17g ", x);
         std::printf("\n");

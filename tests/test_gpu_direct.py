@@ -56,10 +56,10 @@ def test_direct_y_implicit_first(method):
     assert max(errs) <= TOL64, errs
 
 
-# lines longer than 512 slots are held line-major by the library: 530 x 64
-# mixes a line-major x direction with a slot-major y direction
+# lines longer than 512 slots take the multi-window explicit pass: 530 x 64
+# mixes it (x) with the single-window one (y)
 @pytest.mark.parametrize("method,nx,ny", [(adi.CFD, 530, 64), (adi.MFD, 530, 520)])
-def test_direct_line_major_layouts(method, nx, ny):
+def test_direct_long_lines(method, nx, ny):
     log(f"direct layouts method={method} {nx}x{ny}")
     errs = _compare(method, adi.FP64, _case(method, nx, ny, 13, 0.8), 1)
     assert max(errs) <= TOL64, errs
