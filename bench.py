@@ -28,27 +28,31 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(HERE, "profiles", "line_pass3_cfd_fp32_4096_counters.txt")
 KERNEL_FILES = ["line_pass3.hip", "line_consts.h", "pass_common.h", "line_pass.h", "line_pass.hip", "adi.hip",
                 "problem.h", "tile_map.h"]
+DIRECT_COUNTERS = os.path.join(HERE, "profiles", "line_direct_mfd_fp32_4096_counters.txt")
+DIRECT_FILES = ["line_direct.hip", "direct_core.h", "line_pass.h", "adi.hip", "problem.h"]
 
 
-def counter_traffic():
-    """Bytes per launch of the dominant kernel from the committed counter
-    summary, or None when it is missing or the kernel sources changed."""
+def counter_traffic(path=None, files=None, key="traffic_bytes_per_dispatch"):
+    """Bytes per launch of the dominant kernel (or per pass, by key) from a
+    committed counter summary, or None when it is missing or the kernel
+    sources changed."""
     import hashlib
-    if not os.path.exists(COUNTERS):
+    path, files = path or COUNTERS, files or KERNEL_FILES
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line and not line.startswith(("#", " ")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.split("(")[0].strip()
     h = hashlib.sha256()
-    for n in sorted(KERNEL_FILES):
+    for n in sorted(files):
         path = os.path.join(HERE, "paper_2006_07583_amd", "csrc", n)
         h.update(path.rsplit("/", 1)[-1].encode())
         h.update(open(path, "rb").read())
     if kv.get("source_hash") != h.hexdigest()[:16]:
         return None
-    return float(kv["traffic_bytes_per_dispatch"])
+    return float(kv[key])
 
 
 def parse():
@@ -154,6 +158,16 @@ def direct_case(n, steps):
             alg = alg_bytes_per_pass(method, n, elem, True, False)
             out[f"{mname}_{dname}"] = {"pass_us": r["per_pass"] * 1e6, "pt_steps_s": n * n / (2 * r["per_pass"]),
                                        "alg_GBs": alg / r["per_pass"] / 1e9, "finite": r["finite"]}
+    # roofline of the mimetic FP32 direct pass (its three launches together)
+    m = out["mfd_fp32"]
+    achieved = m["alg_GBs"]
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": counter_traffic(DIRECT_COUNTERS, DIRECT_FILES, "traffic_bytes_per_pass")
+                       if n == 4096 else None,
+                       "traffic_unit": "bytes per pass (counters)",
+                       "alg_bytes": alg_bytes_per_pass(1, n, 4, True, False),
+                       "kernel": "line_direct_kernel<float, MFD, *> (windowed banded LU, mimetic FP32)"}
     return out
 
 

@@ -8,8 +8,9 @@
  * discretisation factored with the Peaceman-Rachford split (eqs. CN, PR two
  * stages).  Each stage couples pressure and one velocity component along the
  * grid lines of one direction and is solved by a fixed, even number of
- * fixed-point sweeps (eqs. adiSolve, adiSolve2; Algorithms 3 and 4).  Two
- * spatial discretisations are offered:
+ * fixed-point sweeps (eqs. adiSolve, adiSolve2; Algorithms 3 and 4), or
+ * exactly (params.sweeps = 0, the limit of infinitely many sweeps; see
+ * below).  Two spatial discretisations are offered:
  *   ADI_CFD  nodal fourth-order compact differences, P4/Q4 and the reduced
  *            Pbar4/Qbar4 (Section 2.1, Appendix A): every derivative along a
  *            line is one tridiagonal solve;
@@ -74,7 +75,8 @@ typedef struct adi_params {
     int32_t dtype;       /* adi_dtype */
     int32_t order;       /* 0: x-implicit stage first (the paper's order); 1: y-implicit first */
     int32_t nx, ny;      /* cells per direction, each >= 8 */
-    int32_t sweeps;      /* fixed-point sweeps per stage: even, >= 2 (paper: 6-8) */
+    int32_t sweeps;      /* fixed-point sweeps per stage: even, in [2, 16] (paper: 6-8);
+                            0 = direct (exact) line solves, see below */
     int32_t src_i, src_j;/* pressure index (column i, row j) of the Ricker point
                             source, both interior; -1 = no source */
     int32_t reserved0;
@@ -97,6 +99,23 @@ const char* adi_status_string(int status);
 
 /* Message of the last error raised on this host thread ("" if none). */
 const char* adi_last_error(void);
+
+/* Direct line solves (params.sweeps = 0).  Each stage's coupled line
+ * systems (Section 2.1, eqs. ecua2:PR and ecua3:PR2 along every grid line)
+ * are solved exactly instead of by fixed-point sweeps: the step is the
+ * Peaceman-Rachford step itself, with no iteration error and no step-size
+ * limit from the iteration (the sweeps diverge at cfl 1.155 compact and
+ * 0.816 mimetic; adi_create rejects those step sizes when sweeps > 0).
+ * Each line system is rewritten as a banded system (mimetic: the pressure
+ * system after eliminating the velocity; compact: the two derivative
+ * unknowns interleaved) and solved by LU without pivoting over overlapping
+ * windows of the line, whose margins come from the decay of the inverse of
+ * the line matrix at the largest a c / h (to 1e-17 of its peak in FP64,
+ * 1e-9 in FP32).  The workspace (adi_workspace_size) then also holds the
+ * factors of every window, about (window + margin) x 4..7 values per line
+ * slot.  Scope: ADI_FP32 and ADI_FP64, single problems; adi_create rejects
+ * ADI_FP32C and step sizes whose margin exceeds 4096 slots, and batches,
+ * servers and adi_set_tolerance refuse such problems (ADI_EINVAL). */
 
 /* Fill *p with defaults: CFD, FP32, order 0, 6 sweeps, no source,
  * kappa0 = rinv0 = 1, struct_size set.  Sizes, h, dt, c_max left zero. */
