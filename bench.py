@@ -425,7 +425,8 @@ def main():
     if args.direct_steps > 0:
         dc = direct_case(n, args.direct_steps)
         print("# direct line solves: " + ", ".join(
-            f"{k} {v['pass_us']:.0f} us/pass ({v['alg_GBs']:.0f} GB/s alg)" for k, v in dc.items() if k != "workload"),
+            f"{k} {v['pass_us']:.0f} us/pass ({v['alg_GBs']:.0f} GB/s alg)" for k, v in dc.items()
+            if isinstance(v, dict) and "pass_us" in v),
               file=sys.stderr, flush=True)
         out["direct"] = dc
     if args.batch_steps > 0:

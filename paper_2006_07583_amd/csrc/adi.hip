@@ -646,18 +646,29 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     g.mode = d.mode == adi::LINE_FINAL ? 1 : 0;
     g.src_q = d.mode == adi::LINE_FINAL ? -1 : a.src_q;
     g.src_s = a.src_s;
-    // windows before dwa and after dwb reach the closure rows
-    auto go = [&](int wbase, int wcount, bool wide) {
-        if (wcount <= 0) return hipSuccess;
+    // windows before dwa and after dwb reach the closure rows: they run on
+    // the second stream beside the interior windows, each launch with its
+    // own part of the factor store
+    const int nv_wide = adi::direct_values_per_row(d.method), nv_narrow = 4;
+    T* fs = (T*)pb->dfs;
+    // windows [wbase, wbase + n1) and [wbase2, wbase2 + n2) in one launch
+    auto go = [&](int wbase, int n1, int wbase2, int n2, bool wide, hipStream_t s) {
         g.wbase = wbase;
-        g.wcount = wcount;
-        g.nthr = (int64_t)pl.dnlp * wcount;
-        return adi::launch_direct<T>(g, d.method, wide, pb->st);
+        g.wsplit = n1;
+        g.wbase2 = wbase2;
+        g.wcount = n1 + n2;
+        g.nthr = (int64_t)pl.dnlp * g.wcount;
+        g.fs = fs;
+        fs += g.nthr * pl.drows * (wide ? nv_wide : nv_narrow);
+        return adi::launch_direct<T>(g, d.method, wide, s);
     };
-    if (pl.dwa > pl.dwb) return go(0, pl.dnwin, true);
-    hipError_t e = go(0, pl.dwa, true);
-    if (e == hipSuccess) e = go(pl.dwa, pl.dwb - pl.dwa + 1, false);
-    if (e == hipSuccess) e = go(pl.dwb + 1, pl.dnwin - pl.dwb - 1, true);
+    if (pl.dwa > pl.dwb) return go(0, pl.dnwin, 0, 0, true, pb->st);
+    hipError_t e = hipEventRecord(pb->dev_in, pb->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pb->dst2, pb->dev_in, 0);
+    if (e == hipSuccess) e = go(0, pl.dwa, pl.dwb + 1, pl.dnwin - pl.dwb - 1, true, pb->dst2);
+    if (e == hipSuccess) e = hipEventRecord(pb->dev_out, pb->dst2);
+    if (e == hipSuccess) e = go(pl.dwa, pl.dwb - pl.dwa + 1, 0, 0, false, pb->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pb->st, pb->dev_out, 0);
     return e;
 }
 
@@ -841,6 +852,11 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
         pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
     }
+    if (p.sweeps == 0 && !pb->dst2) {
+        HIP_TRY(hipStreamCreateWithFlags(&pb->dst2, hipStreamNonBlocking), "direct solves: second stream");
+        HIP_TRY(hipEventCreateWithFlags(&pb->dev_in, hipEventDisableTiming), "direct solves: event");
+        HIP_TRY(hipEventCreateWithFlags(&pb->dev_out, hipEventDisableTiming), "direct solves: event");
+    }
     pb->U = U; pb->V = V; pb->W = W;
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];
     pb->vcur = pb->wcur = 0;
@@ -935,11 +951,15 @@ int adi_sweep_stats(adi_problem* pb, int64_t* passes, int64_t* sweeps) {
 
 int adi_destroy(adi_problem* pb) {
     if (!pb) return ADI_OK;
-    if ((pb->own_ws && pb->ws) || pb->eps_buf) {
+    if ((pb->own_ws && pb->ws) || pb->eps_buf || pb->dst2) {
         (void)hipSetDevice(pb->dev);
         (void)hipStreamSynchronize(pb->st);
+        if (pb->dst2) (void)hipStreamSynchronize(pb->dst2);
         if (pb->own_ws && pb->ws) (void)hipFree(pb->ws);
         if (pb->eps_buf) (void)hipFree(pb->eps_buf);
+        if (pb->dev_in) (void)hipEventDestroy(pb->dev_in);
+        if (pb->dev_out) (void)hipEventDestroy(pb->dev_out);
+        if (pb->dst2) (void)hipStreamDestroy(pb->dst2);
     }
     delete pb;
     return ADI_OK;

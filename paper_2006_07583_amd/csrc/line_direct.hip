@@ -37,7 +37,8 @@ template <typename T, int METHOD, bool WIDE>
 __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
     const int64_t tid = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (tid >= p.nthr) return;
-    const int q = (int)(tid % p.nlp), w = p.wbase + (int)(tid / p.nlp);
+    const int q = (int)(tid % p.nlp), wi = (int)(tid / p.nlp);
+    const int w = wi < p.wsplit ? p.wbase + wi : p.wbase2 + (wi - p.wsplit);
     const bool live = q < p.nlines;
     const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live};
     const int src = (live && q == p.src_q) ? p.src_s : -1;
@@ -48,8 +49,8 @@ __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
 
 template <typename T>
 hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st) {
-    if (p.wcount <= 0 || p.wbase < 0 || p.wbase + p.wcount > p.nwin || p.nlp % 64 ||
-        (int64_t)p.nlp * p.wcount != p.nthr)
+    if (p.wcount <= 0 || p.wsplit < 0 || p.wsplit > p.wcount || p.wbase < 0 || p.wbase + p.wsplit > p.nwin ||
+        p.wbase2 < 0 || p.wbase2 + (p.wcount - p.wsplit) > p.nwin || p.nlp % 64 || (int64_t)p.nlp * p.wcount != p.nthr)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(p.nthr / 64)), block(64);
     if (method == LINE_MFD) {

@@ -102,8 +102,9 @@ int line3_lanes(int dtype);
 hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int attempts, double eps, int K,
                             int kmin, int kmax, long long* stats, hipStream_t st);
 
-// Direct (exact) line pass (line_direct.hip): thread t solves window
-// wbase + t / nlp of line t % nlp (lines padded to nlp, a multiple of 64).  Element
+// Direct (exact) line pass (line_direct.hip): thread t solves the
+// (t / nlp)-th window of the launch on line t % nlp (lines padded to nlp, a
+// multiple of 64).  Element
 // (line q, slot s) of each array sits at base[q * x_l + s * x_s]; A and K are
 // pressure-type (slots 1..n-1 for CFD, 1..n for MFD), B, R, V velocity-type
 // (slots 0..n).  mode 0 writes 2 Ubar - A (+ aF at (src_q, src_s)) and
@@ -121,7 +122,9 @@ struct DirectArgs {
     T inv_h, aF;
     int nlines, nlp, n, S, H, nwin, mode;
     int src_q, src_s;
-    int wbase, wcount;   // this launch solves windows wbase .. wbase + wcount - 1
+    // this launch solves wcount windows: wbase + i for i < wsplit, then
+    // wbase2 + (i - wsplit)
+    int wbase, wcount, wsplit, wbase2;
     int drows;           // kept rows per thread in fs (the largest over the windows)
     int64_t nthr;        // nlp * wcount
 };

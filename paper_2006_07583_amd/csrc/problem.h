@@ -89,6 +89,10 @@ struct adi_problem {
     // part of the workspace
     void* dfs = nullptr;
     void* dconst = nullptr;
+    // second stream and its two events: the windows at the line ends run
+    // beside the interior windows
+    hipStream_t dst2 = nullptr;
+    hipEvent_t dev_in = nullptr, dev_out = nullptr;
 };
 
 namespace adi {
