@@ -53,6 +53,10 @@ constexpr double G0[6] = {-47888.0 / 14245.0, 1790.0 / 407.0, -14545.0 / 9768.0,
                           8997.0 / 16280.0, -2335.0 / 22792.0, 25.0 / 9768.0};
 constexpr double G1[5] = {16.0 / 105.0, -31.0 / 24.0, 29.0 / 24.0, -3.0 / 40.0, 1.0 / 168.0};
 constexpr double ST[4] = {1.0 / 24.0, -9.0 / 8.0, 9.0 / 8.0, -1.0 / 24.0};
+// Appendix A closure rows without 1/h: h Q row 0 on nodes 0..3 (row n is
+// its negated mirror) and h Qbar at node 1 on nodes 0..3 (node n-1 alike).
+constexpr double Q0[4] = {-17.0, 9.0, 9.0, -1.0};
+constexpr double QB1[4] = {-1.0, -9.0, 9.0, 1.0};
 
 // Bandwidths of the window systems: with the closure rows of the line ends
 // (WIDE) and of interior rows only, (3, 3) for both methods.
@@ -170,7 +174,7 @@ DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
             e[ML - 3] = -qh * io.K(s - 1);
         }
         return;
-    }
+    } else {
     if ((i & 1) == 0) {
         // z row: Pbar z + Qbar (ar y) = Qbar B on interior nodes; z_0 = z_n = 0
         if (s == 0 || s == n) { e[ML] = T(1); return; }
@@ -183,15 +187,22 @@ DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
             e[ML - 2] = T(1); e[ML] = T(4); e[ML + 2] = T(1);
         }
         if (s == 1 || s == n - 1) {
-            const int j0 = s == 1 ? 0 : n - 3;
-            const T q[4] = {T(-1), T(-9), T(9), T(1)};
+            // nodes j0..j0+3 = 0..3 (offsets 2k - 1) or n-3..n (2k - 3); the
+            // entries are placed by value selects so every index is fixed
+            const bool first = s == 1;
+            const int j0 = first ? 0 : n - 3;
+            T ent[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int j = j0 + k;
-                const T qh = q[k] * inv_h;
-                rhs = fma(qh, io.B(j), rhs);
-                e[ML + 2 * (j - s) + 1] = qh * io.R(j);
+                const T qh = T(QB1[k]) * inv_h;
+                rhs = fma(qh, io.B(j0 + k), rhs);
+                ent[k] = qh * io.R(j0 + k);
             }
+            e[ML - 3] = first ? T(0) : ent[0];
+            e[ML - 1] = first ? ent[0] : ent[1];
+            e[ML + 1] = first ? ent[1] : ent[2];
+            e[ML + 3] = first ? ent[2] : ent[3];
+            e[ML + 5] = first ? ent[3] : T(0);
         } else {
             const T qh = T(3) * inv_h;
             rhs = qh * (io.B(s + 1) - io.B(s - 1));
@@ -210,17 +221,25 @@ DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
         e[ML - 2] = T(1); e[ML] = T(4); e[ML + 2] = T(1);
     }
     if (s == 0 || s == n) {
-        const T q0[4] = {T(-17), T(9), T(9), T(-1)};
-        const T qn[4] = {T(1), T(-9), T(-9), T(17)};
-        const int j0 = s == 0 ? 0 : n - 3;
+        // nodes 1..3 (offsets 2k - 1) or n-3..n-1 (offsets 2k - 7); the
+        // boundary node carries no unknown and is not read
+        const bool first = s == 0;
+        const int j0 = first ? 0 : n - 3;
+        T ent[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int j = j0 + k;
-            if (j < 1 || j > n - 1) continue;
-            const T qh = (s == 0 ? q0[k] : qn[k]) * inv_h;
+            const bool valid = first ? k >= 1 : k <= 2;
+            const int j = valid ? j0 + k : (first ? 1 : n - 1);
+            const T qh = valid ? (first ? T(Q0[k]) : T(-Q0[3 - k])) * inv_h : T(0);
             rhs = fma(qh, io.A(j), rhs);
-            e[ML + 2 * (j - s) - 1] = qh * io.K(j);
+            ent[k] = qh * io.K(j);
         }
+        e[ML - 7] = first ? T(0) : ent[0];
+        e[ML - 5] = first ? T(0) : ent[1];
+        e[ML - 3] = first ? T(0) : ent[2];
+        e[ML + 1] = first ? ent[1] : T(0);
+        e[ML + 3] = first ? ent[2] : T(0);
+        e[ML + 5] = first ? ent[3] : T(0);
     } else {
         const T qh = T(3) * inv_h;
         if (s + 1 <= n - 1) {
@@ -231,6 +250,7 @@ DIRECT_HD void row_cfd(const IO& io, int n, T inv_h, int i, T* e, T& rhs) {
             rhs = fma(-qh, io.A(s - 1), rhs);
             e[ML - 3] = -qh * io.K(s - 1);
         }
+    }
     }
 }
 
@@ -249,6 +269,63 @@ DIRECT_HD void put_face(const IO& io, int n, int f, int c, int fo0, int fo1, con
     g *= inv_h;
     const T B = io.B(f), rr = io.R(f);
     io.putV(f, mode == OUT_NEXT ? fma(T(-2) * rr, g, B) : fma(-rr, g, B));
+}
+
+// One forward row: drop the unknowns outside the window, eliminate with the
+// previous ML normalised U rows (ur[0] is row i - ML), push the new row and
+// store it as kept row i - rb (rows before rb go to slot 0, which row rb
+// overwrites: a store without a branch).
+template <typename T, int ML, int MU, class IO>
+DIRECT_HD void fwd_row(const IO& io, int i, int r0, int r1, int rb, T (&e)[ML + MU + 1], T r, T (&ur)[ML][MU],
+                       T (&yr)[ML]) {
+    constexpr int NB = ML + MU + 1;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int col = i - ML + k;
+        if (col < r0 || col > r1) e[k] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < ML; ++c) {
+        const T f = e[c];
+#pragma unroll
+        for (int t = 1; t <= MU; ++t)
+            if (c + t < NB) e[c + t] = fma(-f, ur[c][t - 1], e[c + t]);
+        r = fma(-f, yr[c], r);
+    }
+    const T inv = T(1) / e[ML];
+#pragma unroll
+    for (int j = 0; j < ML - 1; ++j) {
+        yr[j] = yr[j + 1];
+#pragma unroll
+        for (int t = 0; t < MU; ++t) ur[j][t] = ur[j + 1][t];
+    }
+    yr[ML - 1] = r * inv;
+#pragma unroll
+    for (int t = 0; t < MU; ++t) ur[ML - 1][t] = e[ML + 1 + t] * inv;
+    const int si = i >= rb ? i - rb : 0;
+    io.st(si, 0, yr[ML - 1]);
+#pragma unroll
+    for (int t = 0; t < MU; ++t) io.st(si, t + 1, ur[ML - 1][t]);
+}
+
+// One backward row: x_i = y_i - sum_t u_{i,t} x_{i+t}, pushed into x.
+template <typename T, int MU, class IO>
+DIRECT_HD T back_row(const IO& io, int i, int rb, T (&x)[MU + 1]) {
+    T v = io.ld(i - rb, 0);
+#pragma unroll
+    for (int t = MU; t >= 1; --t) x[t] = x[t - 1];
+#pragma unroll
+    for (int t = 1; t <= MU; ++t) v = fma(-io.ld(i - rb, t), x[t], v);
+    x[0] = v;
+    return v;
+}
+
+// MFD pressure output of cell c from its solved value v.
+template <typename T, class IO>
+DIRECT_HD void put_cell(const IO& io, int c, T v, int mode, int src_s, T aF) {
+    const T A = io.A(c);
+    const T u = mode == OUT_NEXT ? fma(T(2), v, -A) : v;
+    io.putU(c, u + (mode == OUT_NEXT && c == src_s ? aF : T(0)));
 }
 
 // Solve window w of one line and write its output slots.  mode OUT_NEXT
@@ -274,74 +351,84 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, i
 #pragma unroll
         for (int t = 0; t < MU; ++t) ur[j][t] = T(0);
     }
+    T x[MU + 1];   // backward ring: x[0] = x_i, x[t] = x_{i+t}
+#pragma unroll
+    for (int t = 0; t <= MU; ++t) x[t] = T(0);
+
+    if constexpr (!WIDE) {
+        // interior windows: branch-free loop bodies (unrolling them raised
+        // the registers past the occupancy that hides the loads: kept rolled)
+        if constexpr (METHOD == MFD) {
+#pragma unroll 1
+            for (int i = r0; i <= r1; ++i) {
+                T e[NB], r;
+                row_mfd<T, ML, NB, false>(io, n, inv_h, i, e, r);
+                fwd_row<T, ML, MU>(io, i, r0, r1, rb, e, r, ur, yr);
+            }
+            int i = r1;
+#pragma unroll 1
+            for (; i > W.o1; --i) back_row<T, MU>(io, i, rb, x);
+            // cell o1: its face o1 + 1 belongs to the next window
+            {
+                const T v = back_row<T, MU>(io, W.o1, rb, x);
+                put_cell<T>(io, W.o1, v, mode, src_s, aF);
+            }
+#pragma unroll 1
+            for (i = W.o1 - 1; i >= W.o0; --i) {
+                const T v = back_row<T, MU>(io, i, rb, x);
+                put_cell<T>(io, i, v, mode, src_s, aF);
+                put_face<T, MU>(io, n, i + 1, i, W.o0, W.o1, x, inv_h, mode);
+            }
+            // face o0, whose lowest cell is o0 - 1
+            back_row<T, MU>(io, W.o0 - 1, rb, x);
+            put_face<T, MU>(io, n, W.o0, W.o0 - 1, W.o0, W.o1, x, inv_h, mode);
+        } else {
+#pragma unroll 1
+            for (int sl = W.w0; sl <= W.w1; ++sl) {
+                T e[NB], r;
+                row_cfd<T, ML, NB, false>(io, n, inv_h, 2 * sl, e, r);
+                fwd_row<T, ML, MU>(io, 2 * sl, r0, r1, rb, e, r, ur, yr);
+                row_cfd<T, ML, NB, false>(io, n, inv_h, 2 * sl + 1, e, r);
+                fwd_row<T, ML, MU>(io, 2 * sl + 1, r0, r1, rb, e, r, ur, yr);
+            }
+#pragma unroll 1
+            for (int i = r1; i > 2 * W.o1 + 1; --i) back_row<T, MU>(io, i, rb, x);
+#pragma unroll 1
+            for (int sl = W.o1; sl >= W.o0; --sl) {
+                const T y = back_row<T, MU>(io, 2 * sl + 1, rb, x);
+                const T B = io.B(sl), rr = io.R(sl);
+                io.putV(sl, mode == OUT_NEXT ? fma(T(-2) * rr, y, B) : fma(-rr, y, B));
+                const T z = back_row<T, MU>(io, 2 * sl, rb, x);
+                const T A = io.A(sl), kk = io.K(sl);
+                const T u = mode == OUT_NEXT ? fma(T(-2) * kk, z, A) : fma(-kk, z, A);
+                io.putU(sl, u + (mode == OUT_NEXT && sl == src_s ? aF : T(0)));
+            }
+        }
+        return;
+    }
+
     for (int i = r0; i <= r1; ++i) {
         T e[NB], r;
         if constexpr (METHOD == MFD) row_mfd<T, ML, NB, WIDE>(io, n, inv_h, i, e, r);
         else row_cfd<T, ML, NB, WIDE>(io, n, inv_h, i, e, r);
-        // unknowns outside the window are dropped
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int col = i - ML + k;
-            if (col < r0 || col > r1) e[k] = T(0);
-        }
-        // eliminate with rows i-ML .. i-1 (ur[0] is row i-ML)
-#pragma unroll
-        for (int c = 0; c < ML; ++c) {
-            const T f = e[c];
-#pragma unroll
-            for (int t = 1; t <= MU; ++t)
-                if (c + t < NB) e[c + t] = fma(-f, ur[c][t - 1], e[c + t]);
-            r = fma(-f, yr[c], r);
-        }
-        const T inv = T(1) / e[ML];
-#pragma unroll
-        for (int j = 0; j < ML - 1; ++j) {
-            yr[j] = yr[j + 1];
-#pragma unroll
-            for (int t = 0; t < MU; ++t) ur[j][t] = ur[j + 1][t];
-        }
-        yr[ML - 1] = r * inv;
-#pragma unroll
-        for (int t = 0; t < MU; ++t) ur[ML - 1][t] = e[ML + 1 + t] * inv;
-        if (i >= rb) {
-            io.st(i - rb, 0, yr[ML - 1]);
-#pragma unroll
-            for (int t = 0; t < MU; ++t) io.st(i - rb, t + 1, ur[ML - 1][t]);
-        }
+        fwd_row<T, ML, MU>(io, i, r0, r1, rb, e, r, ur, yr);
     }
 
-    // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}; x[0] = x_i, x[t] = x_{i+t}
-    T x[MU + 1];
-#pragma unroll
-    for (int t = 0; t <= MU; ++t) x[t] = T(0);
+    // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}
     for (int i = r1; i >= rb; --i) {
-        T v = io.ld(i - rb, 0);
-#pragma unroll
-        for (int t = MU; t >= 1; --t) x[t] = x[t - 1];
-#pragma unroll
-        for (int t = 1; t <= MU; ++t) v = fma(-io.ld(i - rb, t), x[t], v);
-        x[0] = v;
+        const T v = back_row<T, MU>(io, i, rb, x);
         if constexpr (METHOD == MFD) {
             const int c = i;
-            if (c >= W.o0 && c <= W.o1) {
-                const T A = io.A(c);
-                T u = mode == OUT_NEXT ? fma(T(2), v, -A) : v;
-                if (mode == OUT_NEXT && c == src_s) u += aF;
-                io.putU(c, u);
-            }
+            if (c >= W.o0 && c <= W.o1) put_cell<T>(io, c, v, mode, src_s, aF);
             // faces whose lowest cell is c
             const int fo0 = w == 0 ? 0 : W.o0;
-            if constexpr (WIDE) {
-                if (c == 1) {
-                    put_face<T, MU>(io, n, 0, c, fo0, W.o1, x, inv_h, mode);
-                    put_face<T, MU>(io, n, 1, c, fo0, W.o1, x, inv_h, mode);
-                }
-                if (c + 1 <= n - 2) put_face<T, MU>(io, n, c + 1, c, fo0, W.o1, x, inv_h, mode);
-                if (c == n - 3) put_face<T, MU>(io, n, n - 1, c, fo0, W.o1, x, inv_h, mode);
-                if (c == n - 4) put_face<T, MU>(io, n, n, c, fo0, W.o1, x, inv_h, mode);
-            } else {
-                put_face<T, MU>(io, n, c + 1, c, fo0, W.o1, x, inv_h, mode);
+            if (c == 1) {
+                put_face<T, MU>(io, n, 0, c, fo0, W.o1, x, inv_h, mode);
+                put_face<T, MU>(io, n, 1, c, fo0, W.o1, x, inv_h, mode);
             }
+            if (c + 1 <= n - 2) put_face<T, MU>(io, n, c + 1, c, fo0, W.o1, x, inv_h, mode);
+            if (c == n - 3) put_face<T, MU>(io, n, n - 1, c, fo0, W.o1, x, inv_h, mode);
+            if (c == n - 4) put_face<T, MU>(io, n, n, c, fo0, W.o1, x, inv_h, mode);
         } else {
             const int s = i >> 1;
             if (s >= W.o0 && s <= W.o1) {
