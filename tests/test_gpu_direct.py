@@ -96,3 +96,20 @@ def test_direct_scope_errors():
     p = adi.make_params(adi.MFD, adi.FP64, 64, 64, 1 / 64, 2.0 / 64, 1.0, sweeps=6)
     with pytest.raises(adi.AdiError):
         adi.Problem(p)
+
+
+def test_direct_problems_refused_by_batches_and_servers():
+    import torch
+    n = 64
+    f = inputs.random_fields(adi.MFD, n, n, 2)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float32)
+    p = adi.make_params(adi.MFD, adi.FP32, n, n, 1 / n, 0.5 / n, 1.0, sweeps=0)
+    pb = adi.Problem(p).bind(t(f["U"]), t(f["V"]), t(f["W"]))
+    with pytest.raises(adi.AdiError):
+        adi.Batch([pb])
+    pb.close()
+    srv = adi.Server(hbm_budget_bytes=64 << 20, max_active=4)
+    arr = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    with pytest.raises(adi.AdiError):
+        srv.submit(p, arr(f["U"]), arr(f["V"]), arr(f["W"]), nsteps=1)
+    srv.close()
