@@ -4,6 +4,8 @@
 //                               A, B, K, R (n + 2 values each); prints U, V
 //                               (n + 2 values each) after solving every window
 //   direct_core_check margin method c2 tol : prints the window margin
+//   direct_core_check plan    : checks the window-plan invariants, prints the
+//                               number of violations (exit status 0 = none)
 #define DIRECT_HD inline
 #define DIRECT_HOST_ONLY
 #include "direct_core.h"
@@ -19,6 +21,39 @@ int main(int argc, char** argv) {
     if (argc >= 5 && !std::strcmp(argv[1], "margin")) {
         std::printf("%d\n", direct_margin(std::atoi(argv[2]), std::atof(argv[3]), std::atof(argv[4])));
         return 0;
+    }
+    if (argc >= 2 && !std::strcmp(argv[1], "plan")) {
+        // window-plan invariants over many sizes: exact partition of the
+        // output slots, interior-band windows inside the interior rows, kept
+        // rows within the per-thread stride, and the lowest row the interior
+        // backward loop reads (MFD: o0 - 1) among the kept rows
+        int bad = 0;
+        for (int method = 0; method <= 1; ++method)
+            for (int n = 8; n <= 700; n += (n < 64 ? 1 : 37))
+                for (int H = 6; H <= 140; H += 7)
+                    for (int S : {H, 2 * H, 16, 40, 128, n + 1}) {
+                        if (S <= 0) continue;
+                        const int smin = direct_smin(method), nw = direct_nwin(method, n, S);
+                        const int rows = direct_rows(method, n, S, H);
+                        int wa, wb, next = smin;
+                        narrow_range(method, n, S, H, wa, wb);
+                        const int lo = method == MFD ? 4 : 2, hi = method == MFD ? n - 3 : n - 2;
+                        for (int w = 0; w < nw; ++w) {
+                            const Win W = window(smin, n, S, H, w);
+                            const int r1 = method == MFD ? W.w1 : 2 * W.w1 + 1;
+                            const int rb = first_kept_row(method, W);
+                            bad += W.o0 != next || W.o1 < W.o0 || W.w0 > W.o0 || W.w1 < W.o1;
+                            bad += r1 - rb + 1 > rows || rb < (method == MFD ? W.w0 : 2 * W.w0);
+                            next = W.o1 + 1;
+                            if (w >= wa && w <= wb) {
+                                bad += W.w0 < lo || W.w1 > hi || w == 0 || w == nw - 1;
+                                if (method == MFD) bad += W.o0 - 1 < rb;
+                            }
+                        }
+                        bad += next != n + 1;
+                    }
+        std::printf("%d\n", bad);
+        return bad ? 1 : 0;
     }
     if (argc < 2 || std::strcmp(argv[1], "solve")) return 2;
     int method, n, S, H, mode, src_s;

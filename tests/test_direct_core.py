@@ -113,3 +113,11 @@ def test_margin_grows_with_step(exe):
         hs = [_margin(exe, method, c2, 1e-17) for c2 in (0.04, 0.16, 1.0, 4.0)]
         assert all(b > a for a, b in zip(hs, hs[1:])), hs
         assert _margin(exe, method, 0.16, 1e-9) < hs[1]
+
+
+def test_window_plan_invariants(exe):
+    """The windows the kernels are launched over partition each line, the
+    interior-band windows stay inside the interior rows, and every kept row
+    fits the per-thread factor store (host check of the index ranges)."""
+    res = subprocess.run([exe, "plan"], capture_output=True, text=True)
+    assert res.returncode == 0 and res.stdout.strip() == "0", res.stdout + res.stderr
