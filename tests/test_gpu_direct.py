@@ -113,3 +113,13 @@ def test_direct_problems_refused_by_batches_and_servers():
     with pytest.raises(adi.AdiError):
         srv.submit(p, arr(f["U"]), arr(f["V"]), arr(f["W"]), nsteps=1)
     srv.close()
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (9, 12)])
+def test_direct_tiny_grids(method, nx, ny):
+    """The smallest grids: one window per line, every closure row of both
+    ends in it (n = 8 leaves two interior mimetic rows)."""
+    log(f"direct tiny method={method} {nx}x{ny}")
+    errs = _compare(method, adi.FP64, _case(method, nx, ny, 17, 1.5), 4)
+    assert max(errs) <= TOL64, errs
