@@ -206,14 +206,14 @@ int direct_margin_of(const adi_params& p) {
 }
 
 // Windows of the direct solves along one direction: enough windows for
-// about 2^19 threads (8 waves per SIMD of the interior-band kernel), each
+// about 2^18 threads (measured best of 2^17..2^20 on 4096^2 lines), each
 // keeping at least twice its margin.
 void direct_plan(Plan& pl, const adi_params& p) {
     const int m = p.method == ADI_MFD ? adi::direct::MFD : adi::direct::CFD;
     const int ns = pl.n - adi::direct::direct_smin(m) + 1;
     pl.dH = direct_margin_of(p);
     pl.dnlp = (pl.nlines + 63) / 64 * 64;
-    const int want = std::max(1, (1 << 19) / pl.dnlp);
+    const int want = std::max(1, (1 << 18) / pl.dnlp);
     int S = std::max({2 * pl.dH, 16, (ns + want - 1) / want});
     pl.dS = std::min(S, ns);
     pl.dnwin = adi::direct::direct_nwin(m, pl.n, pl.dS);
