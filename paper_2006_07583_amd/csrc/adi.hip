@@ -216,9 +216,12 @@ void direct_plan(Plan& pl, const adi_params& p) {
     const int want = std::max(1, (1 << 18) / pl.dnlp);
     int S = std::max({2 * pl.dH, 16, (ns + want - 1) / want});
     pl.dS = std::min(S, ns);
-    pl.dnwin = adi::direct::direct_nwin(m, pl.n, pl.dS);
-    pl.drows = adi::direct::direct_rows(m, pl.n, pl.dS, pl.dH);
-    adi::direct::narrow_range(m, pl.n, pl.dS, pl.dH, pl.dwa, pl.dwb);
+    // the end windows keep H + 4 slots: short chains for the wide band,
+    // and the next window starts inside the interior rows
+    pl.dSe = pl.dH + 4;
+    pl.dnwin = adi::direct::direct_nwin(m, pl.n, pl.dS, pl.dSe);
+    pl.drows = adi::direct::direct_rows(m, pl.n, pl.dS, pl.dSe, pl.dH);
+    adi::direct::narrow_range(m, pl.n, pl.dS, pl.dSe, pl.dH, pl.dwa, pl.dwb);
 }
 
 int validate(const adi_params* p) {
@@ -640,6 +643,7 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     g.nlp = pl.dnlp;
     g.n = a.n;
     g.S = pl.dS;
+    g.Se = pl.dSe;
     g.H = pl.dH;
     g.nwin = pl.dnwin;
     g.drows = pl.drows;

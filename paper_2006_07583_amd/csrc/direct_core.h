@@ -85,13 +85,31 @@ DIRECT_HD double gco(int n, int f, int c) {
 }
 
 // Window bounds in slots: output slots [o0, o1], solved slots [w0, w1].
+// Windows of S output slots; with Se > 0 (and a line longer than 2 Se) the
+// first and the last window keep only Se slots, so the windows that reach
+// the closure rows are short.
 struct Win {
     int o0, o1, w0, w1;
 };
-DIRECT_HD Win window(int smin, int smax, int S, int H, int w) {
+DIRECT_HD Win window(int smin, int smax, int S, int Se, int H, int w) {
     Win r;
-    r.o0 = smin + w * S;
-    r.o1 = r.o0 + S - 1 < smax ? r.o0 + S - 1 : smax;
+    const int ns = smax - smin + 1;
+    if (Se <= 0 || ns <= 2 * Se) {
+        r.o0 = smin + w * S;
+        r.o1 = r.o0 + S - 1 < smax ? r.o0 + S - 1 : smax;
+    } else {
+        const int m = (ns - 2 * Se + S - 1) / S;   // windows between the end windows
+        if (w == 0) {
+            r.o0 = smin;
+            r.o1 = smin + Se - 1;
+        } else if (w <= m) {
+            r.o0 = smin + Se + (w - 1) * S;
+            r.o1 = r.o0 + S - 1 < smax - Se ? r.o0 + S - 1 : smax - Se;
+        } else {
+            r.o0 = smax - Se + 1;
+            r.o1 = smax;
+        }
+    }
     r.w0 = r.o0 - H > smin ? r.o0 - H : smin;
     r.w1 = r.o1 + H < smax ? r.o1 + H : smax;
     return r;
@@ -335,10 +353,11 @@ DIRECT_HD void put_cell(const IO& io, int c, T v, int mode, int src_s, T aF) {
 // WIDE = false is for windows whose rows are all interior rows (see
 // narrow_range).
 template <typename T, int METHOD, bool WIDE, class IO>
-DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, int mode, int src_s, T aF) {
+DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T inv_h, int mode, int src_s,
+                            T aF) {
     constexpr int ML = BandOf<METHOD, WIDE>::ML, MU = BandOf<METHOD, WIDE>::MU, NB = ML + MU + 1;
     const int smin = METHOD == MFD ? 1 : 0;
-    const Win W = window(smin, n, S, H, w);
+    const Win W = window(smin, n, S, Se, H, w);
     const int r0 = METHOD == MFD ? W.w0 : 2 * W.w0;
     const int r1 = METHOD == MFD ? W.w1 : 2 * W.w1 + 1;
     const int rb = first_kept_row(METHOD, W);
@@ -448,16 +467,17 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int H, int w, T inv_h, i
 
 // Slots and kept unknown rows of the windows of a line.
 DIRECT_HD int direct_smin(int method) { return method == MFD ? 1 : 0; }
-inline int direct_nwin(int method, int n, int S) {
+inline int direct_nwin(int method, int n, int S, int Se) {
     const int ns = n - direct_smin(method) + 1;
-    return (ns + S - 1) / S;
+    if (Se <= 0 || ns <= 2 * Se) return (ns + S - 1) / S;
+    return (ns - 2 * Se + S - 1) / S + 2;
 }
 // Largest number of kept rows over the windows (factor store per thread).
-inline int direct_rows(int method, int n, int S, int H) {
+inline int direct_rows(int method, int n, int S, int Se, int H) {
     int best = 0;
-    const int nw = direct_nwin(method, n, S), smin = direct_smin(method);
+    const int nw = direct_nwin(method, n, S, Se), smin = direct_smin(method);
     for (int w = 0; w < nw; ++w) {
-        const Win W = window(smin, n, S, H, w);
+        const Win W = window(smin, n, S, Se, H, w);
         const int r1 = method == MFD ? W.w1 : 2 * W.w1 + 1;
         const int rows = r1 - first_kept_row(method, W) + 1;
         if (rows > best) best = rows;
@@ -468,13 +488,13 @@ inline int direct_rows(int method, int n, int S, int H) {
 // Windows wa..wb hold interior rows only (MFD cells 4..n-3, CFD slots
 // 2..n-2) and are solved with the (3, 3) band; wa > wb when there are none.
 // The window starts and ends grow with w, so the set is contiguous.
-inline void narrow_range(int method, int n, int S, int H, int& wa, int& wb) {
-    const int nw = direct_nwin(method, n, S), smin = direct_smin(method);
+inline void narrow_range(int method, int n, int S, int Se, int H, int& wa, int& wb) {
+    const int nw = direct_nwin(method, n, S, Se), smin = direct_smin(method);
     const int lo = method == MFD ? 4 : 2, hi = method == MFD ? n - 3 : n - 2;
     wa = nw;
     wb = -1;
     for (int w = 0; w < nw; ++w) {
-        const Win W = window(smin, n, S, H, w);
+        const Win W = window(smin, n, S, Se, H, w);
         if (W.w0 >= lo && W.w1 <= hi) {
             if (wa > w) wa = w;
             wb = w;
@@ -512,8 +532,8 @@ inline int direct_margin(int method, double c2, double tol) {
             V(n + 2, 0.0), F((size_t)2 * (n + 2) * 8, 0.0);
         A[L] = 1.0;
         HostLine<double> io{A.data(), B.data(), K.data(), R.data(), U.data(), V.data(), F.data(), 0};
-        if (method == MFD) solve_window<double, MFD, true>(io, n, n, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
-        else solve_window<double, CFD, true>(io, n, n + 1, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        if (method == MFD) solve_window<double, MFD, true>(io, n, n, 0, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
+        else solve_window<double, CFD, true>(io, n, n + 1, 0, 0, 0, 1.0, OUT_STAGE, -1, 0.0);
         double peak = 0.0;
         for (int s = 0; s <= n; ++s) peak = std::fmax(peak, std::fmax(std::fabs(U[s]), std::fabs(V[s])));
         int far = -1;

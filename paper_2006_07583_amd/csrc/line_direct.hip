@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
     const bool live = q < p.nlines;
     const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live};
     const int src = (live && q == p.src_q) ? p.src_s : -1;
-    direct::solve_window<T, METHOD, WIDE>(io, p.n, p.S, p.H, w, p.inv_h, p.mode, src, p.aF);
+    direct::solve_window<T, METHOD, WIDE>(io, p.n, p.S, p.Se, p.H, w, p.inv_h, p.mode, src, p.aF);
 }
 
 }  // namespace

@@ -120,7 +120,7 @@ struct DirectArgs {
     T* v; int64_t v_l, v_s;
     T* fs;
     T inv_h, aF;
-    int nlines, nlp, n, S, H, nwin, mode;
+    int nlines, nlp, n, S, Se, H, nwin, mode;   // Se: output slots of the end windows
     int src_q, src_s;
     // this launch solves wcount windows: wbase + i for i < wsplit, then
     // wbase2 + (i - wsplit)

@@ -16,10 +16,11 @@ struct Plan {
                    // compensated mode) or 3 (line_pass3.hip)
     int cfg = 0;   // tile shape of the single-window kernel
     int seg = 0;   // slots per lane segment of the multi-window kernel
-    // direct (exact) line solves: output slots per window, margin, windows,
+    // direct (exact) line solves: output slots per window (and of the two
+    // end windows), margin, windows,
     // kept rows per window, lines padded to a multiple of 64
     // interior-band windows dwa..dwb
-    int dS = 0, dH = 0, dnwin = 0, drows = 0, dnlp = 0, dwa = 0, dwb = -1;
+    int dS = 0, dSe = 0, dH = 0, dnwin = 0, drows = 0, dnlp = 0, dwa = 0, dwb = -1;
 };
 
 // One pass, ready to launch.

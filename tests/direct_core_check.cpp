@@ -1,6 +1,6 @@
 // Host driver of the exact line-solve core (paper_2006_07583_amd/csrc/
 // direct_core.h), built with g++ for the CPU tests.
-//   direct_core_check solve   : stdin "method n S H mode inv_h src_s aF" then
+//   direct_core_check solve   : stdin "method n S Se H mode inv_h src_s aF" then
 //                               A, B, K, R (n + 2 values each); prints U, V
 //                               (n + 2 values each) after solving every window
 //   direct_core_check margin method c2 tol : prints the window margin
@@ -31,15 +31,16 @@ int main(int argc, char** argv) {
         for (int method = 0; method <= 1; ++method)
             for (int n = 8; n <= 700; n += (n < 64 ? 1 : 37))
                 for (int H = 6; H <= 140; H += 7)
-                    for (int S : {H, 2 * H, 16, 40, 128, n + 1}) {
+                    for (int S : {H, 2 * H, 16, 40, 128, n + 1})
+                      for (int Se : {0, H + 4}) {
                         if (S <= 0) continue;
-                        const int smin = direct_smin(method), nw = direct_nwin(method, n, S);
-                        const int rows = direct_rows(method, n, S, H);
+                        const int smin = direct_smin(method), nw = direct_nwin(method, n, S, Se);
+                        const int rows = direct_rows(method, n, S, Se, H);
                         int wa, wb, next = smin;
-                        narrow_range(method, n, S, H, wa, wb);
+                        narrow_range(method, n, S, Se, H, wa, wb);
                         const int lo = method == MFD ? 4 : 2, hi = method == MFD ? n - 3 : n - 2;
                         for (int w = 0; w < nw; ++w) {
-                            const Win W = window(smin, n, S, H, w);
+                            const Win W = window(smin, n, S, Se, H, w);
                             const int r1 = method == MFD ? W.w1 : 2 * W.w1 + 1;
                             const int rb = first_kept_row(method, W);
                             bad += W.o0 != next || W.o1 < W.o0 || W.w0 > W.o0 || W.w1 < W.o1;
@@ -56,28 +57,29 @@ int main(int argc, char** argv) {
         return bad ? 1 : 0;
     }
     if (argc < 2 || std::strcmp(argv[1], "solve")) return 2;
-    int method, n, S, H, mode, src_s;
+    int method, n, S, Se, H, mode, src_s;
     double inv_h, aF;
-    if (std::scanf("%d %d %d %d %d %lf %d %lf", &method, &n, &S, &H, &mode, &inv_h, &src_s, &aF) != 8) return 3;
+    if (std::scanf("%d %d %d %d %d %d %lf %d %lf", &method, &n, &S, &Se, &H, &mode, &inv_h, &src_s, &aF) != 9)
+        return 3;
     std::vector<double> a(n + 2), b(n + 2), k(n + 2), r(n + 2), u(n + 2, 0.0), v(n + 2, 0.0);
     for (auto* arr : {&a, &b, &k, &r})
         for (auto& x : *arr)
             if (std::scanf("%lf", &x) != 1) return 4;
-    const int rows = direct_rows(method, n, S, H);
+    const int rows = direct_rows(method, n, S, Se, H);
     std::vector<double> fs((size_t)rows * 8, 0.0);
     HostLine<double> io{a.data(), b.data(), k.data(), r.data(), u.data(), v.data(), fs.data(), rows};
     // the library's dispatch: windows 1..narrow_last with the interior band
-    const int nw = direct_nwin(method, n, S);
+    const int nw = direct_nwin(method, n, S, Se);
     int wa, wb;
-    narrow_range(method, n, S, H, wa, wb);
+    narrow_range(method, n, S, Se, H, wa, wb);
     for (int w = 0; w < nw; ++w) {
         const bool narrow = w >= wa && w <= wb;
         if (method == MFD) {
-            if (narrow) solve_window<double, MFD, false>(io, n, S, H, w, inv_h, mode, src_s, aF);
-            else solve_window<double, MFD, true>(io, n, S, H, w, inv_h, mode, src_s, aF);
+            if (narrow) solve_window<double, MFD, false>(io, n, S, Se, H, w, inv_h, mode, src_s, aF);
+            else solve_window<double, MFD, true>(io, n, S, Se, H, w, inv_h, mode, src_s, aF);
         } else {
-            if (narrow) solve_window<double, CFD, false>(io, n, S, H, w, inv_h, mode, src_s, aF);
-            else solve_window<double, CFD, true>(io, n, S, H, w, inv_h, mode, src_s, aF);
+            if (narrow) solve_window<double, CFD, false>(io, n, S, Se, H, w, inv_h, mode, src_s, aF);
+            else solve_window<double, CFD, true>(io, n, S, Se, H, w, inv_h, mode, src_s, aF);
         }
     }
     std::fprintf(stderr, "windows %d, interior-band windows %d\n", nw, wb >= wa ? wb - wa + 1 : 0);

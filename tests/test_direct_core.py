@@ -25,8 +25,8 @@ def exe():
     return path
 
 
-def _solve(exe, method, n, S, H, mode, h, A, B, K, R, src_s=-1, aF=0.0):
-    head = f"{method} {n} {S} {H} {mode} {1.0 / h!r} {src_s} {aF!r}\n"
+def _solve(exe, method, n, S, H, mode, h, A, B, K, R, src_s=-1, aF=0.0, Se=0):
+    head = f"{method} {n} {S} {Se} {H} {mode} {1.0 / h!r} {src_s} {aF!r}\n"
     body = "\n".join(" ".join(repr(float(x)) for x in arr) for arr in (A, B, K, R))
     res = subprocess.run([exe, "solve"], input=head + body, capture_output=True, text=True, check=True)
     lines = res.stdout.strip().splitlines()
@@ -84,7 +84,8 @@ def test_whole_line_solve_satisfies_stage_equations(exe, method, cfl):
 
 @pytest.mark.parametrize("method", [O.CFD, O.MFD])
 @pytest.mark.parametrize("cfl,S", [(0.8, 23), (3.0, 61)])
-def test_windows_with_margin_equal_whole_line(exe, method, cfl, S):
+@pytest.mark.parametrize("short_ends", [False, True])
+def test_windows_with_margin_equal_whole_line(exe, method, cfl, S, short_ends):
     """Windows of S output slots (ragged last window) with the margin sized
     for FP64 equal the single-window solve to 1e-13, in both output modes;
     the fused mode is 2 Ubar - A (+ aF at the source) and 2 vel - B."""
@@ -96,11 +97,12 @@ def test_windows_with_margin_equal_whole_line(exe, method, cfl, S):
     assert 0 < H < 400
     ns = n if method == O.MFD else n + 1
     U1, V1 = _solve(exe, method, n, ns, 0, 1, h, A, B, K, R)
-    Uw, Vw = _solve(exe, method, n, S, H, 1, h, A, B, K, R)
+    Se = H + 4 if short_ends else 0
+    Uw, Vw = _solve(exe, method, n, S, H, 1, h, A, B, K, R, Se=Se)
     scale = max(np.abs(U1).max(), np.abs(V1).max())
     assert np.abs(Uw - U1).max() < 1e-13 * scale and np.abs(Vw - V1).max() < 1e-13 * scale
     src = n // 3
-    Un, Vn = _solve(exe, method, n, S, H, 0, h, A, B, K, R, src_s=src, aF=0.25)
+    Un, Vn = _solve(exe, method, n, S, H, 0, h, A, B, K, R, src_s=src, aF=0.25, Se=Se)
     lo, hi = (1, n) if method == O.MFD else (1, n - 1)
     want_u = 2 * U1[lo:hi + 1] - A[lo:hi + 1]
     want_u[src - lo] += 0.25
