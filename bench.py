@@ -5,8 +5,11 @@ Workload: the layered-medium seismic configuration at 4096 x 4096 cells
 (h = 5 m, 3-8 seeded layers 1500-4500 m/s, 15 Hz Ricker source near the top,
 dt at CFL 0.8, rho = 1, 6 sweeps per stage).  One benchmark step is one ADI
 time step of each spatial variant (compact CFD and mimetic MFD) on that grid,
-FP32; the FP64 figures of the same step are reported beside it.  Inputs are
-resident in HBM before the timed region.
+FP32; the FP64 and compensated-FP32 figures of the same step are reported
+beside it, each with its error against the FP64 oracle after the oracle's
+step count from the same initial state.  Inputs are resident in HBM before
+the timed region; the timed region ends with the state written out
+(adi_get_state).
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -63,9 +66,10 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--sweeps", type=int, default=6)
     ap.add_argument("--methods", default="cfd,mfd")
-    ap.add_argument("--dtypes", default="fp32,fp64")
+    ap.add_argument("--dtypes", default="fp32,fp64,fp32c")
     ap.add_argument("--cpu-baseline-steps", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle legs (timing and the per-variant errors)")
     ap.add_argument("--tolerance-steps", type=int, default=40,
                     help="steps of the tolerance-tested leg (0 = skip)")
     ap.add_argument("--direct-steps", type=int, default=10,
@@ -91,6 +95,34 @@ def alg_bytes_per_pass(method, n, elem, k_varies, r_varies):
     return elem * (2 * nu + 2 * nv + (nu if k_varies else 0) + (nv if r_varies else 0))
 
 
+def gpu_error(method, dtype, n, steps, ref, sweeps=6):
+    """Error of the GPU state after `steps` steps of the layered problem
+    against the oracle's state `ref` (same inputs): per field, max-relative
+    for FP64 and relative L2 for the FP32 modes, over the entries the method
+    writes."""
+    import torch
+    from paper_2006_07583_amd import adi, inputs
+    pr = inputs.seismic_problem(method, n, seed=0)
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", tdt)
+    U, V, W, K = t(pr["U"]), t(pr["V"]), t(pr["W"]), t(pr["K"])
+    p = adi.make_params(method, dtype, n, n, pr["h"], pr["dt"], pr["cmax"], sweeps=sweeps, src=pr["src"])
+    pb = adi.Problem(p).bind(U, V, W, K)
+    pb.run(steps)
+    pb.get_state()
+    got = [x.double().cpu().numpy() for x in (U, V, W)]
+    pb.close()
+    parts = lambda u, v, w: (u[1:-1, 1:-1], v[1:-1, :], w[:, 1:-1])
+    out = {}
+    for name, g, r in zip("UVW", parts(*got), parts(*ref)):
+        if dtype == adi.FP64:
+            out[name] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-300))
+        else:
+            out[name] = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+    return {"kind": "max_rel" if dtype == adi.FP64 else "rel_l2", "steps": steps,
+            "bar": 1e-12 if dtype == adi.FP64 else 1e-4, "per_field": out, "max": max(out.values())}
+
+
 def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
     import torch
     from paper_2006_07583_amd import adi, inputs
@@ -113,6 +145,7 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
         w0 = time.perf_counter()
         e0.record(stream)
         pb.run(k)
+        pb.get_state()
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e-3, time.perf_counter() - w0
@@ -336,21 +369,49 @@ def serve_case(count, rate, budget_gb, pool_gb=24.0):
             "peak_active": st["peak_active"], "ticks": st["ticks"], "grouped_launches": st["launches"]}
 
 
-def cpu_baseline(n, steps, methods):
+def cpu_baseline(n, steps, methods, steps1=2):
+    """The oracle timed on the host: `steps` steps of each method on the
+    n^2 layered grid with every host thread (the paper's OpenMP role; its
+    results also serve the per-variant errors), `steps1` steps with one
+    thread (the paper's sequential C++ role), and the 1024^2 mimetic standing
+    mode (20 steps of h/2) with both thread counts."""
     import oracle as O
     from paper_2006_07583_amd import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    total_t, total_pts = 0.0, 0
+    names = "+".join("CFD" if m == 0 else "MFD" for m in methods)
+    total_t, total_pts, refs = 0.0, 0, {}
     for m in methods:
         pr = inputs.seismic_problem(m, n, seed=0)
         t0 = time.perf_counter()
-        O.run(m, pr["U"], pr["V"], pr["W"], h=pr["h"], dt=pr["dt"], nsteps=steps, sweeps=6,
-              K=pr["K"], src=pr["src"], threads=threads)
+        refs[m] = O.run(m, pr["U"], pr["V"], pr["W"], h=pr["h"], dt=pr["dt"], nsteps=steps, sweeps=6,
+                        K=pr["K"], src=pr["src"], threads=threads)
         total_t += time.perf_counter() - t0
         total_pts += n * n * steps
-    return {"value": total_pts / total_t, "unit": "grid-point-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of each of {'+'.join('CFD' if m == 0 else 'MFD' for m in methods)} "
-                      f"on the {n}x{n} layered grid, FP64 oracle, {threads} OpenMP threads, {total_t:.1f} s"}
+    t1, pts1 = 0.0, 0
+    for m in methods:
+        pr = inputs.seismic_problem(m, n, seed=0)
+        t0 = time.perf_counter()
+        O.run(m, pr["U"], pr["V"], pr["W"], h=pr["h"], dt=pr["dt"], nsteps=steps1, sweeps=6, K=pr["K"],
+              src=pr["src"], threads=1)
+        t1 += time.perf_counter() - t0
+        pts1 += n * n * steps1
+    N = 1024
+    f = inputs.standing_mode(1, N, N, 1.0 / N, 2, 3)
+    c2 = {}
+    for th in (threads, 1):
+        t0 = time.perf_counter()
+        O.run(1, f["U"], f["V"], f["W"], h=1.0 / N, dt=0.5 / N, nsteps=20, sweeps=6, threads=th)
+        c2[th] = N * N * 20 / (time.perf_counter() - t0)
+    out = {"value": total_pts / total_t, "unit": "grid-point-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} steps of each of {names} on the {n}x{n} layered grid, FP64 oracle, "
+                     f"{threads} OpenMP threads, {total_t:.1f} s",
+           "single_thread": {"value": pts1 / t1, "unit": "grid-point-steps/s", "cores": 1,
+                             "sample": f"{steps1} steps of each of {names} on the {n}x{n} layered grid, "
+                                       f"one thread, {t1:.1f} s"},
+           "mimetic_standing_mode_1024": {"unit": "grid-point-steps/s", "steps": 20,
+                                          "all_threads": c2[threads], "one_thread": c2[1]},
+           "paper_context": "GTX 960 CUDA over sequential C++ at N=1024: 7.21x (CFD), 15.81x (MFD)"}
+    return out, refs
 
 
 def main():
@@ -361,7 +422,8 @@ def main():
         sys.exit(2)
     from paper_2006_07583_amd import adi
     mmap = {"cfd": adi.CFD, "mfd": adi.MFD}
-    dmap = {"fp32": adi.FP32, "fp64": adi.FP64}
+    dmap = {"fp32": adi.FP32, "fp64": adi.FP64, "fp32c": adi.FP32C}
+    dname = {adi.FP32: "fp32", adi.FP64: "fp64", adi.FP32C: "fp32c"}
     methods = [mmap[m] for m in args.methods.split(",")]
     dtypes = [dmap[d] for d in args.dtypes.split(",")]
     n, K, W = args.n, args.steps, args.warmup
@@ -373,18 +435,25 @@ def main():
         torch.cuda.synchronize()
         print("# copy calibration: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
         del src, dst
+    cpu, refs = (None, {}) if args.no_cpu_baseline else cpu_baseline(n, args.cpu_baseline_steps, methods)
+    if cpu:
+        print(f"# oracle: {cpu['value']:.4g} pt-steps/s on {cpu['cores']} threads, "
+              f"{cpu['single_thread']['value']:.4g} on one", file=sys.stderr, flush=True)
     res = {}
     for d in dtypes:
         for m in methods:
             r = gpu_case(m, d, n, K, W, args.sweeps)
-            elem = 4 if d == adi.FP32 else 8
+            elem = 8 if d == adi.FP64 else 4
+            if m in refs:
+                r["error"] = gpu_error(m, d, n, args.cpu_baseline_steps, refs[m], args.sweeps)
             r["alg_bytes_pass"] = alg_bytes_per_pass(m, n, elem, True, False)
             r["gbs"] = r["alg_bytes_pass"] / r["per_pass"] / 1e9
             r["pt_steps_s"] = n * n * K / r["t"]
             res[(m, d)] = r
-            print(f"# {'CFD' if m == 0 else 'MFD'} {'fp32' if d == 0 else 'fp64'}: "
+            err = f", error {r['error']['kind']} {r['error']['max']:.3g}" if "error" in r else ""
+            print(f"# {'CFD' if m == 0 else 'MFD'} {dname[d]}: "
                   f"{r['pt_steps_s']:.4g} pt-steps/s, {r['t'] / K * 1e3:.3f} ms/step, "
-                  f"pass {r['per_pass'] * 1e6:.1f} us, {r['gbs']:.0f} GB/s alg, finite={r['finite']}",
+                  f"pass {r['per_pass'] * 1e6:.1f} us, {r['gbs']:.0f} GB/s alg, finite={r['finite']}{err}",
                   file=sys.stderr, flush=True)
     head = adi.FP32 if adi.FP32 in dtypes else dtypes[0]
     tt = sum(res[(m, head)]["t"] for m in methods)
@@ -394,10 +463,10 @@ def main():
     rd = res[(dom, head)]
     variants = {}
     for (m, d), r in res.items():
-        variants[f"{'cfd' if m == 0 else 'mfd'}_{'fp32' if d == 0 else 'fp64'}"] = {
+        variants[f"{'cfd' if m == 0 else 'mfd'}_{dname[d]}"] = {
             "pt_steps_s": r["pt_steps_s"], "ms_per_step": r["t"] / K * 1e3,
             "line_pass_us": r["per_pass"] * 1e6, "alg_GBs": r["gbs"], "hbm_frac": r["gbs"] / HBM_PEAK_GBS,
-            "finite": r["finite"]}
+            "finite": r["finite"], "error_vs_oracle": r.get("error")}
     out = {
         "metric": "ADI grid-point-steps/s at 4096^2 FP32 vs FP64 + %HBM peak; p50/p99 solve latency",
         "value": value, "unit": "grid-point-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -441,8 +510,8 @@ def main():
               f"p99 {sv['latency_p99_s']:.3f} s, {sv['pt_steps_s']:.4g} pt-steps/s served "
               f"(offered {sv['offered_pt_steps_s']:.4g}), peak {sv['peak_active']} active", file=sys.stderr, flush=True)
         out["serving"] = sv
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_steps, methods)
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -60,11 +60,11 @@ typedef enum adi_status {
 } adi_status;
 
 typedef enum adi_method { ADI_CFD = 0, ADI_MFD = 1 } adi_method;
-/* ADI_FP32C: FP32 arithmetic and FP32 caller arrays; within a run the state
- * carried between passes is kept as (value, low word) pairs and every pass
+/* ADI_FP32C: FP32 arithmetic and FP32 caller arrays; the state carried
+ * between passes is kept as (value, low word) pairs and every pass
  * accumulates its FP32 increment with TwoSum, so rounding does not build up
- * over many steps.  The low words live in the workspace for the duration of
- * one adi_run call (the caller's arrays receive the rounded sum). */
+ * over many steps.  The low words live in the workspace with the rest of the
+ * state (adi_get_state writes the rounded sums). */
 typedef enum adi_dtype { ADI_FP32 = 0, ADI_FP64 = 1, ADI_FP32C = 2 } adi_dtype;
 
 /* Problem description.  Set struct_size = sizeof(adi_params); fill the rest
@@ -132,21 +132,32 @@ int adi_create(const adi_params* p, void* hip_stream, adi_problem** out);
 int adi_workspace_size(const adi_params* p, int has_K, int has_Rv, int has_Rw,
                        size_t* bytes);
 
-/* Attach the caller's device arrays (shapes above).  U, V, W hold the state
- * and are updated in place by adi_step / adi_run; K, Rv, Rw may be NULL
- * (constant kappa0 / rinv0) and are read during this call only.  ld[0..5]
+/* Attach the caller's device arrays (shapes above).  U, V, W hold the
+ * initial state (time level 0, see adi_set_step): the first adi_run reads
+ * them into the workspace, where the state then stays between runs;
+ * adi_get_state writes it out.  K, Rv, Rw may be NULL (constant kappa0 /
+ * rinv0) and are read during this call only.  ld[0..5]
  * are the leading dimensions (elements) of U, V, W, K, Rv, Rw; NULL or 0
  * entries mean densely packed rows.  workspace may be NULL (the library then
  * allocates and owns it) or caller memory of at least adi_workspace_size
  * bytes, 256-byte aligned, which the caller keeps alive until adi_destroy.
  * The call returns after the device has consumed K, Rv, Rw.  Resets the step
- * counter to 0. */
+ * counter to 0.
+ * The step size was validated for c_max: ADI_EINVAL if the bound materials
+ * exceed it, i.e. if (max kappa) (max 1/rho) over the interior points the
+ * passes read (kappa0, rinv0 for absent arrays) is above c_max^2 by more than
+ * rounding. */
 int adi_bind(adi_problem* pb, void* U, void* V, void* W,
              const void* K, const void* Rv, const void* Rw,
              const int64_t* ld, void* workspace, size_t workspace_bytes);
 
 /* Queue nsteps Peaceman-Rachford steps (Algorithm 1 / 2 loop body) on the
- * problem's stream.  On completion U, V, W hold time level m + nsteps. */
+ * problem's stream, advancing the state from time level m to m + nsteps.
+ * The state stays in the workspace in the layouts of the line passes (the
+ * pressure hand-off and velocities of the next pass), so consecutive runs
+ * continue without copies; the bound U, V, W are not written (adi_get_state
+ * does that).  Runs with tolerance-tested stages (adi_set_tolerance) instead
+ * start from and end in the bound arrays, as if adi_get_state followed. */
 int adi_run(adi_problem* pb, int64_t nsteps);
 
 /* adi_run(pb, 1). */
@@ -155,7 +166,20 @@ int adi_step(adi_problem* pb);
 /* Wait for all queued work of the problem. */
 int adi_sync(adi_problem* pb);
 
-/* Current time level m (time t0 + m dt) / set it (checkpoint resume). */
+/* Write the state of the current time level m into the device arrays U, V,
+ * W (shapes and leading dimensions of the bound arrays; NULL = the bound
+ * array itself) and wait for it.  Only the entries the method updates are
+ * written: interior pressure points, interior rows of V, interior columns
+ * of W (Dirichlet boundary values and the unused velocity rows/columns are
+ * left as they are).  The workspace state is not changed: runs continue from
+ * m either way.  Cost: the pass that ended the last step run once more in its
+ * final form (pressure U^m and its velocity instead of the next step's
+ * hand-off), plus transposed copies of the velocities. */
+int adi_get_state(adi_problem* pb, void* U, void* V, void* W);
+
+/* Current time level m (time t0 + m dt) / set it (checkpoint resume).
+ * Setting another level while the state is in the workspace first writes the
+ * state into the bound arrays; the next run starts from them. */
 int adi_get_step(const adi_problem* pb, int64_t* m);
 int adi_set_step(adi_problem* pb, int64_t m);
 
@@ -174,7 +198,9 @@ int adi_set_step(adi_problem* pb, int64_t m);
  *   min_sweeps  even, in [2, params.sweeps].
  * Applies to FP32 and FP64 problems whose lines are longer than 512 slots in
  * both directions (nx, ny >= 512 for CFD, >= 511 for MFD), run with adi_run /
- * adi_step; such a problem cannot join a batch.  Clears the counters of
+ * adi_step; such a problem cannot join a batch.  If runs have left the
+ * state in the workspace it is first written into the bound arrays, where
+ * tolerance-tested runs start and end.  Clears the counters of
  * adi_sweep_stats.  Allocates 32 bytes of device memory per workgroup of
  * the wave-per-line kernel (about 150 KiB at 4096^2) the first time.
  * Errors: ADI_EINVAL for a NULL problem, eps < 0 or not finite, min_sweeps
@@ -196,7 +222,8 @@ int adi_destroy(adi_problem* pb);
  * half-step of all problems is one launch per kernel variant (tile shape x
  * method x mode, at most a few), each workgroup picking its problem and
  * line group from a table.  Results are identical, bit for bit, to running
- * every problem alone with adi_run. */
+ * every problem alone with adi_run; as after adi_run, each problem's state
+ * stays in its workspace (read it with adi_get_state). */
 typedef struct adi_batch adi_batch;
 
 /* Replay the launches of the steady-state steps from a captured hipGraph. */
@@ -212,9 +239,11 @@ int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, 
                      adi_batch** out);
 
 /* Queue nsteps steps of every problem of the batch (each problem ends at
- * its own time level m + nsteps, as after adi_run(problem, nsteps)).  The
- * call allocates a descriptor buffer on first use and blocks until the
- * previous run of the batch has finished. */
+ * its own time level m + nsteps, as after adi_run(problem, nsteps); a
+ * problem may have been run alone or in other batches before).  The call
+ * allocates a descriptor buffer on first use and blocks until the previous
+ * run of the batch has finished.  adi_get_state on a problem waits for the
+ * batch's work through the problem's stream. */
 int adi_batch_run(adi_batch* b, int64_t nsteps);
 
 /* Wait for the batch's queued work. */
@@ -230,7 +259,8 @@ int adi_batch_destroy(adi_batch* b);
 /* ---- Served problems ---------------------------------------------------
  * A server takes requests (a problem description, host arrays and a step
  * count) at any time and returns each result in the request's own host
- * arrays.  Every tick advances all admitted problems by one step with the
+ * arrays, or, for requests flagged ADI_REQUEST_HOLD, keeps it on the device
+ * until adi_fetch copies it out.  Every tick advances all admitted problems by one step with the
  * grouped launches of the batched form (bit-for-bit the result of running
  * the problem alone).  Device memory is one arena of hbm_budget_bytes
  * allocated by adi_server_create; a request is admitted, first come first
@@ -248,13 +278,19 @@ typedef struct adi_server_params {
     uint64_t hbm_budget_bytes;   /* device arena (arrays + workspaces) */
 } adi_server_params;
 
+/* adi_request.flags: keep the result in the server's device memory after
+ * completion (the request's host arrays are then inputs only) until
+ * adi_fetch; held results count against hbm_budget_bytes. */
+#define ADI_REQUEST_HOLD 1
+
 typedef struct adi_request {
     uint32_t struct_size;        /* sizeof(adi_request) */
-    int32_t reserved0;
+    int32_t flags;               /* 0 or ADI_REQUEST_HOLD */
     adi_params params;           /* as for adi_create; order, sweeps, source included */
     int64_t nsteps;              /* >= 1 */
-    void *U, *V, *W;             /* host arrays (shapes of adi_bind), overwritten with
-                                    time level nsteps when the request completes */
+    void *U, *V, *W;             /* host arrays (shapes of adi_bind) with time level 0,
+                                    overwritten with time level nsteps when the request
+                                    completes (unless ADI_REQUEST_HOLD) */
     const void *K, *Rv, *Rw;     /* host arrays or NULL (kappa0 / rinv0) */
     int64_t ld[6];               /* leading dimensions (elements) of U, V, W, K, Rv, Rw;
                                     0 = densely packed */
@@ -282,6 +318,14 @@ int adi_poll(adi_server* s, uint64_t ticket, int* state);
 
 /* Block until the request is done; returns its status. */
 int adi_wait(adi_server* s, uint64_t ticket);
+
+/* Block until the request is done and copy its result (time level nsteps)
+ * into the host arrays U, V, W, laid out like the request's arrays (same
+ * shapes and leading dimensions; NULL skips an array).  A held request
+ * (ADI_REQUEST_HOLD) is copied from device memory, which is then released:
+ * it can be fetched once (ADI_EINVAL afterwards).  Otherwise the result is
+ * copied from the request's own host arrays.  Returns the request's status. */
+int adi_fetch(adi_server* s, uint64_t ticket, void* U, void* V, void* W);
 
 /* Seconds since the server's creation (steady clock) at submission, at the
  * first step and at completion (results in the host arrays). */

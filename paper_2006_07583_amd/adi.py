@@ -19,14 +19,15 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
           -4: "ADI_EBUSY", -5: "ADI_ENOTREADY", -6: "ADI_ENUMERIC"}
 
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
-           "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync",
+           "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
            "adi_get_step", "adi_set_step", "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
-           "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait",
+           "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait", "adi_fetch",
            "adi_request_times", "adi_server_get_stats", "adi_server_destroy")
 
 BATCH_GRAPH = 1
+REQUEST_HOLD = 1
 
 
 class AdiParams(ctypes.Structure):
@@ -47,7 +48,7 @@ class AdiServerParams(ctypes.Structure):
 
 
 class AdiRequest(ctypes.Structure):
-    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved0", ctypes.c_int32), ("params", AdiParams),
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_int32), ("params", AdiParams),
                 ("nsteps", ctypes.c_int64),
                 ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("W", ctypes.c_void_p),
                 ("K", ctypes.c_void_p), ("Rv", ctypes.c_void_p), ("Rw", ctypes.c_void_p),
@@ -89,6 +90,7 @@ def lib():
         L.adi_run.argtypes = [vp, i64]
         L.adi_step.argtypes = [vp]
         L.adi_sync.argtypes = [vp]
+        L.adi_get_state.argtypes = [vp, vp, vp, vp]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
         L.adi_set_step.argtypes = [vp, i64]
         L.adi_set_tolerance.argtypes = [vp, ctypes.c_double, ctypes.c_int]
@@ -104,6 +106,7 @@ def lib():
         L.adi_submit.argtypes = [vp, ctypes.POINTER(AdiRequest), ctypes.POINTER(ctypes.c_uint64)]
         L.adi_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
         L.adi_wait.argtypes = [vp, ctypes.c_uint64]
+        L.adi_fetch.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
         dp = ctypes.POINTER(ctypes.c_double)
         L.adi_request_times.argtypes = [vp, ctypes.c_uint64, dp, dp, dp]
         L.adi_server_get_stats.argtypes = [vp, ctypes.POINTER(AdiServerStats)]
@@ -145,8 +148,10 @@ def _dptr(t):
 class Problem:
     """One ADI problem: ``adi_create`` + ``adi_bind`` on torch device tensors.
 
-    U, V, W are updated in place by :meth:`run`; K, Rv, Rw are read at bind.
-    Rows of every tensor must be contiguous (row stride = leading dimension).
+    U, V, W hold the initial state; :meth:`run` keeps the state in the
+    library's workspace and :meth:`get_state` writes it out (into U, V, W by
+    default).  K, Rv, Rw are read at bind.  Rows of every tensor must be
+    contiguous (row stride = leading dimension).
     """
 
     def __init__(self, params: AdiParams, stream=None):
@@ -183,6 +188,14 @@ class Problem:
 
     def sync(self):
         _check(lib().adi_sync(self._h))
+
+    def get_state(self, U=None, V=None, W=None):
+        """adi_get_state: write the current state into U, V, W (tensors laid
+        out like the bound ones; None = the bound tensor) and wait for it."""
+        for t, b in zip((U, V, W), self._keep[:3]):
+            if t is not None and (t.shape != b.shape or t.stride() != b.stride() or t.dtype != b.dtype):
+                raise ValueError("get_state targets must match the bound arrays' shape, strides and dtype")
+        _check(lib().adi_get_state(self._h, _dptr(U), _dptr(V), _dptr(W)))
 
     @property
     def step_index(self) -> int:
@@ -271,13 +284,16 @@ class Server:
         _check(lib().adi_server_create(ctypes.byref(p), ctypes.byref(self._h)))
         self._keep = {}
 
-    def submit(self, params: AdiParams, U, V, W, K=None, Rv=None, Rw=None, nsteps=1) -> int:
+    def submit(self, params: AdiParams, U, V, W, K=None, Rv=None, Rw=None, nsteps=1, hold=False) -> int:
         """Queue a request; U, V, W (numpy, C-ordered rows, the params' dtype)
-        receive the result.  The arrays are kept referenced until done."""
+        receive the result (with hold=True they are inputs only and the
+        result waits on the device for :meth:`fetch`).  The arrays are kept
+        referenced until done."""
         import numpy as np
         want = np.float64 if params.dtype == FP64 else np.float32
         r = AdiRequest()
         r.struct_size = ctypes.sizeof(AdiRequest)
+        r.flags = REQUEST_HOLD if hold else 0
         r.params = params
         r.nsteps = int(nsteps)
         arrs = (U, V, W, K, Rv, Rw)
@@ -300,6 +316,18 @@ class Server:
 
     def wait(self, ticket: int):
         _check(lib().adi_wait(self._h, int(ticket)))
+        self._keep.pop(int(ticket), None)
+
+    def fetch(self, ticket: int, U, V, W):
+        """adi_fetch: wait for the request and copy its result into the numpy
+        arrays U, V, W (laid out like the request's arrays)."""
+        keep = self._keep.get(int(ticket))
+        if keep is not None:
+            for a, b in zip((U, V, W), keep[:3]):
+                if a is not None and (a.shape != b.shape or a.strides != b.strides or a.dtype != b.dtype):
+                    raise ValueError("fetch targets must match the request's arrays")
+        ptr = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)
+        _check(lib().adi_fetch(self._h, int(ticket), ptr(U), ptr(V), ptr(W)))
         self._keep.pop(int(ticket), None)
 
     def times(self, ticket: int):

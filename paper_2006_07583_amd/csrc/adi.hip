@@ -8,9 +8,13 @@
 //   WSb  2 x [y node][x interior]   W* (vertical velocity after the explicit part)
 //   aK, aKT, aRvT, aRw              a*kappa and a/rho in both line layouts
 //   coefX, coefY                    compact-scheme factor tables per window
-// A run of n steps is: transpose V in, one explicit column pass (A, W* of
-// step m), then n x [row pass, column pass], the last column pass writing
-// U^{m+n} and W^{m+n} into the caller's arrays, and V transposed back out.
+//   Vs                              spare velocity of the direction that ends a step
+// The first run after adi_bind transposes U, V, W in and runs one explicit
+// column pass (A, W* of step m); every step is then [row pass, column pass],
+// the column pass leaving the next step's A and W*, so the state stays in
+// the workspace between runs.  adi_get_state re-runs the last column pass in
+// its final form (U^{m}, W^{m} instead of the hand-off) into the target
+// arrays and transposes V out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -156,13 +160,19 @@ double ricker(const adi_params& p, double t) {
 
 namespace {
 
-// Workspace regions of one direction: P, V0, V1, K, R, Plo, V0lo, V1lo, coef.
+// Workspace regions of one direction: P, V0, V1, K, R, Plo, V0lo, V1lo, coef,
+// Vs, Vslo.
 struct Layout {
-    size_t off[2][9];
-    size_t fs_off;   // factor store of the direct solves (shared by both directions)
-    size_t dc_off;   // their constant materials
+    size_t off[2][11];
+    size_t fs_off;    // factor store of the direct solves (shared by both directions)
+    size_t dc_off;    // their constant materials
+    size_t red_off;   // per-block partial maxima of the material check at bind
     size_t total;
 };
+constexpr int kRedBlocks = 256;
+
+// Direction of the pass that ends a step.
+int last_dir(const adi_params& p) { return p.order == 0 ? 1 : 0; }
 
 // Offsets (bytes) of the workspace regions, each 256-byte aligned.
 Layout layout(const adi_problem& pb) {
@@ -175,9 +185,13 @@ Layout layout(const adi_problem& pb) {
         const Plan& pl = d == 0 ? pb.px : pb.py;
         const size_t pe = (size_t)D.rows_p * D.ld, ve = (size_t)D.rows_v * D.ld;
         const bool hasR = d == 0 ? pb.hasRv : pb.hasRw;
-        const size_t sizes[9] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
-                                 comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : 0};
-        for (int i = 0; i < 9; ++i) {
+        // the final re-run of adi_get_state writes its velocity here unless it
+        // can go straight into the target (slot-major column passes)
+        const bool spare = d == last_dir(p) && (d == 0 || D.lm);
+        const size_t sizes[11] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
+                                  comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : 0,
+                                  spare ? ve : 0, spare && comp ? ve : 0};
+        for (int i = 0; i < 11; ++i) {
             L.off[d][i] = cur;
             cur += (sizes[i] * pb.esz + 255) / 256 * 256;
         }
@@ -192,6 +206,8 @@ Layout layout(const adi_problem& pb) {
     }
     L.dc_off = cur;
     if (p.sweeps == 0) cur += 256;
+    L.red_off = cur;
+    cur += 3 * kRedBlocks * sizeof(double);
     L.total = cur;
     return L;
 }
@@ -480,12 +496,13 @@ int run_begin(adi_problem* pb, hipStream_t st) {
         HIP_TRY(launch_pass<T>(d, st), "explicit row pass");
         pb->vcur ^= 1;
     }
+    pb->ready = true;
     return ADI_OK;
 }
 
 template <typename T>
-PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab) {
-    const bool last = s == nsteps - 1;
+PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, bool final_pass, const T* aFtab) {
+    const bool last = final_pass;
     const T f1 = (T)source_term(*pb, pb->step + s + 1);
     T* U = (T*)pb->U;
     T* W = (T*)pb->W;
@@ -531,6 +548,7 @@ int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps) {
         HIP_TRY(vel_from_dir<T>(pb, 1, W, pb->ldW, vel<T>(pb, 1, pb->wcur), st), "W out");
     HIP_TRY(vel_from_dir<T>(pb, 0, V, pb->ldV, vel<T>(pb, 0, pb->vcur), st), "V out");
     pb->step += nsteps;
+    pb->ready = false;
     return ADI_OK;
 }
 
@@ -545,8 +563,8 @@ template hipError_t launch_grouped<float>(const PassDesc<float>&, const GroupArg
 template hipError_t launch_grouped<double>(const PassDesc<double>&, const GroupArgs<double>&, hipStream_t);
 template int run_begin<float>(adi_problem*, hipStream_t);
 template int run_begin<double>(adi_problem*, hipStream_t);
-template PassDesc<float> run_pass<float>(adi_problem*, int64_t, int, int64_t, const float*);
-template PassDesc<double> run_pass<double>(adi_problem*, int64_t, int, int64_t, const double*);
+template PassDesc<float> run_pass<float>(adi_problem*, int64_t, int, bool, const float*);
+template PassDesc<double> run_pass<double>(adi_problem*, int64_t, int, bool, const double*);
 template int run_end<float>(adi_problem*, hipStream_t, int64_t);
 template int run_end<double>(adi_problem*, hipStream_t, int64_t);
 template hipError_t launch_pass<float>(const PassDesc<float>&, hipStream_t);
@@ -676,21 +694,111 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     return e;
 }
 
+// The state of a ready problem into U, V, W (the bound leading dimensions):
+// the pass that ended the last step is run again in its final form.  Its
+// inputs are still in the workspace (that pass wrote the other ping-pong
+// buffer and the other direction's hand-off); it writes U^m and its
+// direction's velocity instead of the next step's hand-off, the velocity
+// into the spare buffer (or straight into the target for slot-major column
+// passes).  The other velocity is current in its ping-pong buffer.
+template <typename T>
+int materialize_ready(adi_problem* pb, T* U, T* V, T* W) {
+    const int dl = last_dir(pb->p), o = 1 - dl;
+    const int cur = dl == 0 ? pb->vcur : pb->wcur;
+    const auto& D = pb->d[dl];
+    const Buf<T> uin = pres<T>(pb, dl), vin = vel<T>(pb, dl, 1 - cur);
+    const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU};
+    const Buf<T> spare{(T*)D.Vs, (T*)D.Vslo, D.ld};
+    const bool straight = dl == 1 && !D.lm;
+    const Buf<T> vout = straight ? Buf<T>{W + 1, nullptr, pb->ldW} : spare;
+    const auto d = make_pass<T>(pb, dl, uin, vin, vout, Uu, dl == 0 ? 1 : 0, T(0), nullptr, adi::LINE_FINAL);
+    if (pb->p.sweeps == 0)
+        HIP_TRY(launch_direct_pass<T>(pb, d), "final direct pass");
+    else
+        HIP_TRY(adi::launch_pass<T>(d, pb->st), "final line pass");
+    if (!straight)
+        HIP_TRY(vel_from_dir<T>(pb, dl, dl == 0 ? V : W, dl == 0 ? pb->ldV : pb->ldW, spare, pb->st), "velocity out");
+    const int co = o == 0 ? pb->vcur : pb->wcur;
+    HIP_TRY(vel_from_dir<T>(pb, o, o == 0 ? V : W, o == 0 ? pb->ldV : pb->ldW, vel<T>(pb, o, co), pb->st),
+            "velocity out");
+    return ADI_OK;
+}
+
 template <typename T>
 int run_impl(adi_problem* pb, int64_t nsteps) {
-    int rc = adi::run_begin<T>(pb, pb->st);
+    const bool tested = pb->eps > 0.0;
+    int rc = ADI_OK;
+    if (tested && pb->ready) {
+        // tolerance-tested runs start from and end in the bound arrays
+        rc = materialize_ready<T>(pb, (T*)pb->U, (T*)pb->V, (T*)pb->W);
+        if (rc != ADI_OK) return rc;
+        pb->ready = false;
+    }
+    if (!pb->ready) rc = adi::run_begin<T>(pb, pb->st);
     if (rc != ADI_OK) return rc;
     for (int64_t s = 0; s < nsteps; ++s)
         for (int half = 0; half < 2; ++half) {
-            const auto d = adi::run_pass<T>(pb, s, half, nsteps, nullptr);
+            const bool fin = tested && half == 1 && s == nsteps - 1;
+            const auto d = adi::run_pass<T>(pb, s, half, fin, nullptr);
             if (pb->p.sweeps == 0)
                 HIP_TRY(launch_direct_pass<T>(pb, d), half == 0 ? "first direct pass" : "second direct pass");
-            else if (pb->eps > 0.0)
+            else if (tested)
                 HIP_TRY(launch_tested<T>(pb, d), half == 0 ? "first line pass" : "second line pass");
             else
                 HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
         }
-    return adi::run_end<T>(pb, pb->st, nsteps);
+    if (tested) return adi::run_end<T>(pb, pb->st, nsteps);
+    adi::run_advance(pb, nsteps);
+    return ADI_OK;
+}
+
+// rows x cols of U, V, W
+void state_shapes(const adi_params& p, int64_t rows[3], int64_t cols[3]) {
+    const bool cfd = p.method == ADI_CFD;
+    rows[0] = cfd ? p.ny + 1 : p.ny + 2; cols[0] = cfd ? p.nx + 1 : p.nx + 2;
+    rows[1] = cfd ? p.ny + 1 : p.ny + 2; cols[1] = p.nx + 1;
+    rows[2] = p.ny + 1;                  cols[2] = cfd ? p.nx + 1 : p.nx + 2;
+}
+
+}  // namespace
+
+namespace adi {
+
+int materialize(adi_problem* pb, void* U, void* V, void* W) {
+    if (pb->ready)
+        return pb->p.dtype == ADI_FP64 ? materialize_ready<double>(pb, (double*)U, (double*)V, (double*)W)
+                                       : materialize_ready<float>(pb, (float*)U, (float*)V, (float*)W);
+    int64_t rows[3], cols[3];
+    state_shapes(pb->p, rows, cols);
+    void* dst[3] = {U, V, W};
+    const void* src[3] = {pb->U, pb->V, pb->W};
+    const int64_t ld[3] = {pb->ldU, pb->ldV, pb->ldW};
+    for (int i = 0; i < 3; ++i)
+        if (dst[i] != src[i])
+            HIP_TRY(hipMemcpy2DAsync(dst[i], ld[i] * pb->esz, src[i], ld[i] * pb->esz, cols[i] * pb->esz, rows[i],
+                                     hipMemcpyDeviceToDevice, pb->st),
+                    "state copy");
+    return ADI_OK;
+}
+
+}  // namespace adi
+
+namespace {
+
+// Per-block maxima of x[0..n) (non-negative values) into out[blockIdx.x].
+template <typename T>
+__global__ void __launch_bounds__(256) block_max_kernel(const T* __restrict__ x, int64_t n, double* out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = fmax(m, (double)x[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 template <typename T>
@@ -708,6 +816,33 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
         if (K) HIP_TRY(pres_to_dir<T>(pb, d, (T*)pb->d[d].K, K, ldK, a, st), "a kappa");
         const T* R = d == 0 ? Rv : Rw;
         if (R) HIP_TRY(vel_to_dir<T>(pb, d, (T*)pb->d[d].R, R, d == 0 ? ldRv : ldRw, a, st), "a / rho");
+    }
+    // The step size was validated, and the margins of the direct solves
+    // planned, for c_max: the bound materials must not exceed it.  Largest
+    // a kappa and a / rho over the interior points the passes read.
+    {
+        double* part = (double*)(pb->ws + layout(*pb).red_off);
+        const void* arr[3] = {pb->d[0].K, pb->d[0].R, pb->d[1].R};
+        const int64_t n[3] = {pb->d[0].rows_p * pb->d[0].ld, pb->d[0].rows_v * pb->d[0].ld,
+                              pb->d[1].rows_v * pb->d[1].ld};
+        for (int i = 0; i < 3; ++i)
+            if (arr[i]) {
+                hipLaunchKernelGGL(block_max_kernel<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)arr[i], n[i],
+                                   part + i * kRedBlocks);
+                HIP_TRY(hipGetLastError(), "material check");
+            }
+        double host[3 * kRedBlocks];
+        HIP_TRY(hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, st), "material check");
+        HIP_TRY(hipStreamSynchronize(st), "material check");
+        double mx[3] = {pb->a * p.kappa0, pb->a * p.rinv0, pb->a * p.rinv0};
+        for (int i = 0; i < 3; ++i)
+            if (arr[i]) {
+                mx[i] = 0.0;
+                for (int b = 0; b < kRedBlocks; ++b) mx[i] = std::max(mx[i], host[i * kRedBlocks + b]);
+            }
+        const double c2 = mx[0] * std::max(mx[1], mx[2]) / (pb->a * pb->a);
+        if (!(c2 <= p.c_max * p.c_max * (1.0 + 1e-5)))
+            return fail(ADI_EINVAL, "max kappa * max 1/rho = %.6g exceeds c_max^2 = %.6g", c2, p.c_max * p.c_max);
     }
     if (p.method == ADI_CFD) {
         // factor tables of the single-window kernel (the multi-window kernel
@@ -853,6 +988,8 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         D.Vlo[0] = comp ? w + L.off[d][6] : nullptr;
         D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
         D.coef = w + L.off[d][8];
+        D.Vs = L.off[d][9] != L.off[d][10] ? w + L.off[d][9] : nullptr;
+        D.Vslo = comp && D.Vs ? w + L.off[d][10] : nullptr;
         pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
         pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
     }
@@ -865,6 +1002,7 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
     pb->ldU = l[0]; pb->ldV = l[1]; pb->ldW = l[2];
     pb->vcur = pb->wcur = 0;
     pb->step = 0;
+    pb->ready = false;
     int rc = p.dtype != ADI_FP64
                  ? bind_materials<float>(pb, (const float*)K, (const float*)Rv, (const float*)Rw, l[3], l[4], l[5])
                  : bind_materials<double>(pb, (const double*)K, (const double*)Rv, (const double*)Rw, l[3], l[4], l[5]);
@@ -885,6 +1023,17 @@ int adi_run(adi_problem* pb, int64_t nsteps) {
 
 int adi_step(adi_problem* pb) { return adi_run(pb, 1); }
 
+int adi_get_state(adi_problem* pb, void* U, void* V, void* W) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!pb->bound) return fail(ADI_ENOTREADY, "problem has no bound arrays");
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    const int rc = adi::materialize(pb, U ? U : pb->U, V ? V : pb->V, W ? W : pb->W);
+    if (rc != ADI_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    return ADI_OK;
+}
+
 int adi_sync(adi_problem* pb) {
     g_err.clear();
     if (!pb) return fail(ADI_EINVAL, "problem is NULL");
@@ -902,6 +1051,15 @@ int adi_get_step(const adi_problem* pb, int64_t* m) {
 int adi_set_step(adi_problem* pb, int64_t m) {
     if (!pb) return fail(ADI_EINVAL, "problem is NULL");
     if (m < 0) return fail(ADI_EINVAL, "step < 0");
+    if (pb->ready && m != pb->step) {
+        // the hand-off in the workspace holds the forcing of the old time
+        // level: the state goes back to the bound arrays and the next run
+        // starts from them
+        HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+        const int rc = adi::materialize(pb, pb->U, pb->V, pb->W);
+        if (rc != ADI_OK) return rc;
+        pb->ready = false;
+    }
     pb->step = m;
     return ADI_OK;
 }
@@ -926,6 +1084,12 @@ int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
                     "(nx, ny >= %d for CFD, >= %d for MFD)",
                     adi::LINE_WS, adi::LINE_WS, adi::LINE_WS - 1);
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    if (pb->ready) {
+        // tolerance-tested runs start from the bound arrays
+        const int rc = adi::materialize(pb, pb->U, pb->V, pb->W);
+        if (rc != ADI_OK) return rc;
+        pb->ready = false;
+    }
     HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
     if (!pb->eps_buf) HIP_TRY(hipMalloc(&pb->eps_buf, eps_bytes(pb)), "tolerance state");
     // flags: attempt 0 of the next pass runs; counters cleared

@@ -8,11 +8,12 @@
 // mode) and issued as one grid per variant; each workgroup finds its pass
 // by a binary search over the prefix sums of the block counts.  The pass
 // descriptors depend on the step only through the ping-pong parity and the
-// source term, so three descriptor sets (even steps, odd steps, last step)
-// are uploaded once per run and the source term is read from a per-run
-// table indexed by a device-side step counter.  With ADI_BATCH_GRAPH the
-// launches of two consecutive steps are captured once into a hipGraph and
-// replayed.
+// source term, so the descriptor sets (even steps, odd steps, last step) are
+// uploaded once per run and the source term is read from a per-run table
+// indexed by a device-side step counter.  With ADI_BATCH_GRAPH the launches
+// of two consecutive steps are captured once into a hipGraph and replayed.
+// As after adi_run, every problem's state stays in its workspace
+// (adi_get_state writes it out).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,14 +106,14 @@ void build_sets(adi_batch* b, TypedPart<T>& part, int64_t nsteps, std::vector<si
         const int v0 = pb->vcur, w0 = pb->wcur;
         const T* tab = (const T*)(uintptr_t)(aF_index[np_idx[k]] + 1);   // placeholder: index + 1
         if (nsteps >= 2)
-            for (int h = 0; h < 2; ++h) part.set[0][h].push_back(adi::run_pass<T>(pb, 0, h, nsteps, tab));
+            for (int h = 0; h < 2; ++h) part.set[0][h].push_back(adi::run_pass<T>(pb, 0, h, false, tab));
         if (nsteps >= 3)
-            for (int h = 0; h < 2; ++h) part.set[1][h].push_back(adi::run_pass<T>(pb, 1, h, nsteps, tab));
+            for (int h = 0; h < 2; ++h) part.set[1][h].push_back(adi::run_pass<T>(pb, 1, h, false, tab));
         pb->vcur = v0;
         pb->wcur = w0;
         if ((nsteps - 1) % 2)
-            for (int h = 0; h < 2; ++h) (void)adi::run_pass<T>(pb, 0, h, nsteps, tab);
-        for (int h = 0; h < 2; ++h) part.set[2][h].push_back(adi::run_pass<T>(pb, nsteps - 1, h, nsteps, tab));
+            for (int h = 0; h < 2; ++h) (void)adi::run_pass<T>(pb, 0, h, false, tab);
+        for (int h = 0; h < 2; ++h) part.set[2][h].push_back(adi::run_pass<T>(pb, nsteps - 1, h, false, tab));
     }
 }
 
@@ -201,9 +202,11 @@ int run_batch(adi_batch* b, int64_t nsteps) {
     HIP_TRY(hipStreamSynchronize(b->st), "hipStreamSynchronize");
     drop_graph(b);
 
-    // set-up copies and explicit pass of every problem
+    // set-up copies and explicit pass of every problem whose state is still
+    // in its bound arrays
     for (size_t i = 0; i < np; ++i) {
         adi_problem* pb = b->probs[i];
+        if (pb->ready) continue;
         const int rc = pb->p.dtype == ADI_FP64 ? adi::run_begin<double>(pb, b->st) : adi::run_begin<float>(pb, b->st);
         if (rc != ADI_OK) return rc;
     }
@@ -277,12 +280,7 @@ int run_batch(adi_batch* b, int64_t nsteps) {
         if (rc != ADI_OK) return rc;
     }
 
-    for (size_t i = 0; i < np; ++i) {
-        adi_problem* pb = b->probs[i];
-        const int rc = pb->p.dtype == ADI_FP64 ? adi::run_end<double>(pb, b->st, nsteps)
-                                               : adi::run_end<float>(pb, b->st, nsteps);
-        if (rc != ADI_OK) return rc;
-    }
+    for (size_t i = 0; i < np; ++i) adi::run_advance(b->probs[i], nsteps);
     // later work on a problem's own stream waits for the batch
     HIP_TRY(hipEventRecord(b->done, b->st), "hipEventRecord");
     for (size_t i = 0; i < np; ++i)

@@ -54,6 +54,10 @@ struct adi_problem {
     double a = 0.0;
     int64_t step = 0;
     bool bound = false;
+    // ready: the state of time level `step` lives in the workspace (the
+    // pressure hand-off and velocities of the next pass); otherwise it is in
+    // the bound arrays U, V, W
+    bool ready = false;
     void *U = nullptr, *V = nullptr, *W = nullptr;
     int64_t ldU = 0, ldV = 0, ldW = 0;
     bool hasK = false, hasRv = false, hasRw = false;
@@ -76,6 +80,9 @@ struct adi_problem {
         void *K = nullptr, *R = nullptr;      // a*kappa, a/rho (NULL when constant)
         void *Plo = nullptr, *Vlo[2] = {nullptr, nullptr};   // compensated low words
         void *coef = nullptr;                 // single-window compact tables
+        // spare velocity buffer (and its low words) of the direction whose
+        // pass ends a step: adi_get_state re-runs that pass into it
+        void *Vs = nullptr, *Vslo = nullptr;
     } d[2];
     int vcur = 0, wcur = 0;
     adi::Plan px, py;
@@ -98,17 +105,28 @@ struct adi_problem {
 
 namespace adi {
 
-// A run of nsteps steps of one problem is
-//   run_begin, then for s = 0..nsteps-1 the passes run_pass(s, 0) and
-//   run_pass(s, 1), then run_end.
-// run_begin queues the set-up copies and the explicit pass of step m on st;
-// run_pass returns the pass (and advances the ping-pong buffers); its source
-// term is aF(m + s + 1), taken from aFtab[tick] when aFtab is given (grouped
-// launches) and computed on the host otherwise.
+// Steps of one problem are
+//   run_begin (when the state is not ready), then for s = 0..nsteps-1 the
+//   passes run_pass(s, 0) and run_pass(s, 1), then either
+//   run_end (the last pass final: the state goes back to the bound arrays)
+//   or nothing (every pass a sweep pass: the state stays in the workspace,
+//   step advanced by the caller through run_advance).
+// run_begin queues the set-up copies and the explicit pass of step m on st
+// and marks the state ready; run_pass returns the pass (and advances the
+// ping-pong buffers); its source term is aF(m + s + 1), taken from
+// aFtab[tick] when aFtab is given (grouped launches) and computed on the host
+// otherwise.  `final_pass` (half 1 only) writes U^{m+s+1} into the bound U
+// instead of the next step's hand-off.
 template <typename T> int run_begin(adi_problem* pb, hipStream_t st);
 template <typename T>
-PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, int64_t nsteps, const T* aFtab);
+PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, bool final_pass, const T* aFtab);
 template <typename T> int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps);
+inline void run_advance(adi_problem* pb, int64_t nsteps) { pb->step += nsteps; }
+// Write the state of time level `step` into U, V, W (device arrays with the
+// bound leading dimensions) on the problem's stream; a ready problem's
+// workspace state is left as it was, a problem that is not ready is copied
+// from its bound arrays where the targets differ.
+int materialize(adi_problem* pb, void* U, void* V, void* W);
 template <typename T> hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st);
 // One grouped launch of passes sharing the kernel variant of `proto`.
 template <typename T> hipError_t launch_grouped(const PassDesc<T>& proto, const GroupArgs<T>& ga, hipStream_t st);

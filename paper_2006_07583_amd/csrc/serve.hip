@@ -8,7 +8,8 @@
 // Device memory comes from an arena of hbm_budget_bytes allocated once at
 // creation: admission is first come, first served, as soon as the request's
 // arrays and workspace fit; nothing is allocated or freed on the device
-// while serving.  Results are written back into the request's host arrays.
+// while serving.  Results are written back into the request's host arrays,
+// or held in the arena until adi_fetch (ADI_REQUEST_HOLD).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,6 +92,8 @@ struct Req {
     int64_t s = 0;
     int state = ST_QUEUED;
     int status = ADI_OK;
+    bool held = false;       // result kept in the arena until adi_fetch
+    bool fetching = false;
     double t_submit = 0, t_start = 0, t_done = 0;
     hipEvent_t ev = nullptr;
 };
@@ -205,9 +208,9 @@ int tick(adi_server* S) {
         std::vector<adi::PassDesc<double>> vd;
         for (Req* r : S->active) {
             if (r->pb->p.dtype == ADI_FP64)
-                vd.push_back(adi::run_pass<double>(r->pb, r->s, h, r->r.nsteps, nullptr));
+                vd.push_back(adi::run_pass<double>(r->pb, r->s, h, h == 1 && r->s == r->r.nsteps - 1, nullptr));
             else
-                vf.push_back(adi::run_pass<float>(r->pb, r->s, h, r->r.nsteps, nullptr));
+                vf.push_back(adi::run_pass<float>(r->pb, r->s, h, h == 1 && r->s == r->r.nsteps - 1, nullptr));
         }
         int rc = stage_and_launch<float>(S, vf, sl.host, sl.dev, used);
         if (rc == ADI_OK) rc = stage_and_launch<double>(S, vd, sl.host, sl.dev, used);
@@ -319,9 +322,11 @@ int start_request(adi_server* S, Req* r) {
     return adi_set_step(r->pb, 0);
 }
 
-// Copy the results of a finished request back into its host arrays.
+// Copy the results of a finished request back into its host arrays (held
+// requests only wait for their last step).
 int finish_request(adi_server* S, Req* r) {
     HIP_TRY(hipEventSynchronize(r->ev), "hipEventSynchronize");
+    if (r->r.flags & ADI_REQUEST_HOLD) return ADI_OK;
     const adi_params& p = r->r.params;
     const size_t esz = p.dtype == ADI_FP64 ? 8 : 4;
     int64_t rows[6], cols[6];
@@ -398,7 +403,10 @@ void downloader(adi_server* S) {
         }
         adi_destroy(fin->pb);
         fin->pb = nullptr;
-        S->arena.release(fin->off, fin->bytes);
+        if (fin->r.flags & ADI_REQUEST_HOLD)
+            fin->held = true;
+        else
+            S->arena.release(fin->off, fin->bytes);
         fin->state = ST_DONE;
         fin->t_done = now_s(S->t0);
         ++S->done;
@@ -502,6 +510,7 @@ int adi_submit(adi_server* S, const adi_request* rq, uint64_t* ticket) {
     if (!rq->U || !rq->V || !rq->W) return fail(ADI_EINVAL, "U, V and W are required");
     if (rq->nsteps < 1) return fail(ADI_EINVAL, "nsteps must be >= 1");
     if (rq->params.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) are not served");
+    if (rq->flags & ~ADI_REQUEST_HOLD) return fail(ADI_EINVAL, "unknown request flags 0x%x", rq->flags);
     size_t ws = 0;
     int rc = adi_workspace_size(&rq->params, rq->K != nullptr, rq->Rv != nullptr, rq->Rw != nullptr, &ws);
     if (rc != ADI_OK) return rc;
@@ -566,6 +575,50 @@ int adi_wait(adi_server* S, uint64_t ticket) {
     Req* r = it->second;
     S->cv.wait(lk, [&] { return r->state == ST_DONE; });
     return r->status == ADI_OK ? ADI_OK : fail(r->status, "request failed");
+}
+
+int adi_fetch(adi_server* S, uint64_t ticket, void* U, void* V, void* W) {
+    if (!S) return fail(ADI_EINVAL, "server is NULL");
+    Req* r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return fail(ADI_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        r = it->second;
+        S->cv.wait(lk, [&] { return r->state == ST_DONE; });
+        if (r->status != ADI_OK) return fail(r->status, "request failed");
+        if (r->r.flags & ADI_REQUEST_HOLD) {
+            if (!r->held || r->fetching) return fail(ADI_EINVAL, "result of ticket %llu already fetched",
+                                                     (unsigned long long)ticket);
+            r->fetching = true;   // this thread copies; the arena block stays reserved
+        }
+    }
+    const adi_params& p = r->r.params;
+    const size_t esz = p.dtype == ADI_FP64 ? 8 : 4;
+    int64_t rows[6], cols[6];
+    array_shapes(p, rows, cols);
+    void* dst[3] = {U, V, W};
+    const void* hsrc[3] = {r->r.U, r->r.V, r->r.W};
+    int rc = ADI_OK;
+    for (int i = 0; i < 3 && rc == ADI_OK; ++i) {
+        if (!dst[i]) continue;
+        if (r->held) {
+            const hipError_t e = hipMemcpy2D(dst[i], r->ld[i] * esz, S->mem + r->off + r->arr_off[i], cols[i] * esz,
+                                             cols[i] * esz, rows[i], hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = hip_fail(e, "result download");
+        } else if (dst[i] != hsrc[i]) {
+            for (int64_t j = 0; j < rows[i]; ++j)
+                std::memcpy((char*)dst[i] + j * r->ld[i] * esz, (const char*)hsrc[i] + j * r->ld[i] * esz,
+                            cols[i] * esz);
+        }
+    }
+    if (r->held) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->arena.release(r->off, r->bytes);
+        r->held = false;
+        S->cv.notify_all();
+    }
+    return rc;
 }
 
 int adi_request_times(adi_server* S, uint64_t ticket, double* t_submit, double* t_start, double* t_done) {

@@ -28,7 +28,7 @@ def run_gpu(method, dtype, fields, *, h, dt, c_max, nsteps, sweeps=6, K=None, Rv
     pb = adi.Problem(p).bind(U, V, W, t(K), t(Rv), t(Rw))
     for c in (chunks or [nsteps]):
         pb.run(c)
-    pb.sync()
+    pb.get_state()
     out = tuple(x.double().cpu().numpy() for x in (U, V, W))
     pb.close()
     return out

@@ -1,6 +1,7 @@
 """Batched runs (adi_batch_*): every problem of a mixed batch must come out
 bit for bit equal to the same problem run alone with adi_run, with and
-without graph replay, and across consecutive runs."""
+without graph replay, and across consecutive runs, and match the oracle
+(FP64 max-relative 1e-12, FP32 relative L2 1e-4 per field)."""
 import math
 
 import torch
@@ -8,8 +9,9 @@ import torch
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2006_07583_amd import adi, inputs
-from tests.gpu_util import log
+from tests.gpu_util import log, max_rel, rel_l2, written_parts
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +45,7 @@ def make(method, dtype, nx, ny, order, seed, stream):
     mats = [t(med[k]) for k in ("K", "Rv", "Rw")]
     p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src, order=order)
     pb = adi.Problem(p, stream).bind(*arrs, *mats)
+    pb.inputs = dict(h=h, dt=dt, f=f, med=med, src=src, order=order)
     return pb, arrs
 
 
@@ -60,10 +63,13 @@ def test_batch_equals_individual_runs_bitwise(graph):
     for pb, _ in alone:
         for c in chunks:
             pb.run(c)
+        pb.get_state()
     b = adi.Batch([pb for pb, _ in batch], st, graph=graph)
     for c in chunks:
         b.run(c)
     b.sync()
+    for pb, _ in batch:
+        pb.get_state()
     torch.cuda.synchronize()
     for i, ((pa, xa), (pbb, xb)) in enumerate(zip(alone, batch)):
         assert pa.step_index == pbb.step_index == sum(chunks)
@@ -82,4 +88,27 @@ def test_batch_launch_count_is_per_variant_not_per_problem():
     log(f"grouped launches for 6 steps of {len(MIX)} problems: {n}")
     # at most one launch per variant per half-step; far fewer than one per pass
     assert 12 <= n < 6 * 2 * len(MIX)
+    b.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(graph):
+    """Every problem of the mixed batch (all tile shapes, both kernels of
+    long lines, both orders, FP64, FP32 and compensated FP32) against the
+    oracle after two batched runs."""
+    st = torch.cuda.Stream()
+    probs = build(400, st)
+    b = adi.Batch([pb for pb, _ in probs], st, graph=graph)
+    for c in (5, 4):
+        b.run(c)
+    b.sync()
+    for i, (pb, arrs) in enumerate(probs):
+        pb.get_state()
+        x = pb.inputs
+        ref = O.run(MIX[i][0], x["f"]["U"], x["f"]["V"], x["f"]["W"], h=x["h"], dt=x["dt"], nsteps=9, sweeps=6,
+                    K=x["med"]["K"], Rv=x["med"]["Rv"], Rw=x["med"]["Rw"], src=x["src"], order=x["order"])
+        got = [t.double().cpu().numpy() for t in arrs]
+        for g, r in zip(written_parts(MIX[i][0], *got), written_parts(MIX[i][0], *ref)):
+            err = max_rel(g, r) if MIX[i][1] == adi.FP64 else rel_l2(g, r)
+            assert err <= (1e-12 if MIX[i][1] == adi.FP64 else 1e-4), (i, MIX[i], err)
     b.close()

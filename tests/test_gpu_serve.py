@@ -1,6 +1,7 @@
 """Served problems (adi_server_*): each request's result, returned in its own
-host arrays, equals bit for bit the same problem run alone with adi_run;
-admission respects the memory budget and the active-problem bound."""
+host arrays, equals bit for bit the same problem run alone with adi_run and
+matches the oracle; admission respects the memory budget and the
+active-problem bound."""
 import math
 
 import torch  # noqa: F401  (first import on a fresh box is slow)
@@ -8,8 +9,9 @@ import torch  # noqa: F401  (first import on a fresh box is slow)
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2006_07583_amd import adi, inputs
-from tests.gpu_util import log, run_gpu
+from tests.gpu_util import log, max_rel, rel_l2, run_gpu, written_parts
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +41,8 @@ def request(method, dtype, nx, ny, order, nsteps, seed):
     arrs = {k: np.ascontiguousarray(f[k], dtype=npdt) for k in ("U", "V", "W")}
     mats = {k: np.ascontiguousarray(med[k], dtype=npdt) for k in ("K", "Rv", "Rw")}
     p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src, order=order)
-    return dict(p=p, arrs=arrs, mats=mats, h=h, dt=dt, cmax=cmax, src=src, nsteps=nsteps, order=order)
+    return dict(p=p, arrs=arrs, mats=mats, h=h, dt=dt, cmax=cmax, src=src, nsteps=nsteps, order=order, f=f,
+                med=med)
 
 
 def solo(method, dtype, rq):
@@ -70,4 +73,11 @@ def test_served_results_equal_solo_runs(budget, max_active):
         assert 0 <= ts <= t1 <= t2
         for name, got, want in zip("UVW", (rq["arrs"][k] for k in "UVW"), r):
             assert np.array_equal(got.astype(np.float64), want), (i, MIX[i], name)
+        f, med = rq["f"], rq["med"]
+        oref = O.run(MIX[i][0], f["U"], f["V"], f["W"], h=rq["h"], dt=rq["dt"], nsteps=rq["nsteps"], sweeps=6,
+                     K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=rq["src"], order=rq["order"])
+        got = [rq["arrs"][k].astype(np.float64) for k in "UVW"]
+        for g, o in zip(written_parts(MIX[i][0], *got), written_parts(MIX[i][0], *oref)):
+            err = max_rel(g, o) if MIX[i][1] == adi.FP64 else rel_l2(g, o)
+            assert err <= (1e-12 if MIX[i][1] == adi.FP64 else 1e-4), (i, MIX[i], err)
     srv.close()

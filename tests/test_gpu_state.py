@@ -1,0 +1,180 @@
+"""The state between runs (adi_get_state), held server results (adi_fetch)
+and the material check of adi_bind, through the C ABI.
+
+Runs keep the state in the workspace; adi_get_state re-runs the pass that
+ended the last step in its final form.  So n + n steps with a read-out
+between them must equal 2n steps bit for bit, a read-out into other arrays
+must equal one into the bound arrays, and the oracle must agree at every
+read-out."""
+import math
+
+import torch
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_07583_amd import adi, inputs
+from tests.gpu_util import log, max_rel, rel_l2, written_parts
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-4
+
+# (method, dtype, nx, ny, order, sweeps): single-window, multi-window (both
+# layouts of the pass that ends a step), compensated, y-first, direct
+CASES = [
+    (adi.CFD, adi.FP64, 60, 45, 0, 6),
+    (adi.MFD, adi.FP32, 600, 530, 0, 6),
+    (adi.CFD, adi.FP32, 530, 90, 1, 6),
+    (adi.MFD, adi.FP64, 90, 600, 1, 6),
+    (adi.CFD, adi.FP32C, 600, 100, 0, 6),
+    (adi.MFD, adi.FP32C, 64, 520, 1, 6),
+    (adi.MFD, adi.FP64, 150, 120, 0, 0),
+    (adi.CFD, adi.FP32, 600, 530, 0, 0),
+]
+
+
+def setup(method, dtype, nx, ny, order, sweeps, seed):
+    h = 1.0 / max(nx, ny)
+    f = inputs.random_fields(method, nx, ny, seed)
+    med = inputs.random_medium(method, nx, ny, seed + 1)
+    cmax = math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    dt = 0.6 * h / cmax
+    src = {"i": max(1, nx // 3), "j": max(1, ny // 2), "f0": 4.0, "t0": 0.1, "amp": 1.0}
+    return h, f, med, cmax, dt, src
+
+
+def tensors(f, dtype):
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
+    return [torch.from_numpy(np.ascontiguousarray(f[k])).to("cuda:0", tdt) for k in ("U", "V", "W")]
+
+
+def problem(method, dtype, nx, ny, order, sweeps, h, f, med, cmax, dt, src):
+    U, V, W = tensors(f, dtype)
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
+    K, Rv, Rw = (torch.from_numpy(np.ascontiguousarray(med[k])).to("cuda:0", tdt) for k in ("K", "Rv", "Rw"))
+    p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, sweeps=sweeps, src=src, order=order)
+    return adi.Problem(p).bind(U, V, W, K, Rv, Rw), (U, V, W)
+
+
+def np3(ts):
+    return tuple(t.double().cpu().numpy() for t in ts)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_get_state_between_runs(case):
+    method, dtype, nx, ny, order, sweeps = case
+    h, f, med, cmax, dt, src = setup(*case, seed=61)
+    log(f"case get_state {case}")
+    a, xa = problem(*case, h, f, med, cmax, dt, src)
+    b, xb = problem(*case, h, f, med, cmax, dt, src)
+    # before any run: the initial state
+    a.get_state()
+    for t, k in zip(xa, "UVW"):
+        assert np.array_equal(t.double().cpu().numpy(), f[k].astype(t.cpu().numpy().dtype).astype(np.float64))
+    a.run(3)
+    mid = [torch.full_like(t, 7.0) for t in xa]
+    a.get_state(*mid)          # into other arrays: the bound ones are not touched
+    assert np.array_equal(np3(xa)[0], np3(tensors(f, dtype))[0])
+    a.get_state()
+    a.run(4)
+    a.get_state()
+    b.run(7)
+    b.get_state()
+    assert a.step_index == b.step_index == 7
+    for name, u, v in zip("UVW", xa, xb):
+        assert torch.equal(u, v), (name, float((u - v).abs().max()))
+    # the read-out into other arrays equals the one into the bound arrays
+    # on the entries the method writes
+    run = O.run_direct if sweeps == 0 else O.run
+    kw = {} if sweeps == 0 else {"sweeps": sweeps}
+    for steps, got in ((3, np3(mid)), (7, np3(xa))):
+        ref = run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=steps, K=med["K"], Rv=med["Rv"],
+                  Rw=med["Rw"], src=src, order=order, **kw)
+        for g, r in zip(written_parts(method, *got), written_parts(method, *ref)):
+            err = max_rel(g, r) if dtype == adi.FP64 else rel_l2(g, r)
+            assert err <= (TOL64 if dtype == adi.FP64 else TOL32), (steps, err)
+    a.close()
+    b.close()
+
+
+def test_set_step_moves_the_source_time():
+    """Resuming at another time level (checkpoint restart): the state goes
+    back to the bound arrays and the next run starts from them with the
+    forcing of the new level, as the oracle does with t0 shifted."""
+    case = (adi.MFD, adi.FP64, 70, 60, 0, 6)
+    h, f, med, cmax, dt, src = setup(*case, seed=71)
+    pb, x = problem(*case, h, f, med, cmax, dt, src)
+    pb.run(2)
+    pb.step_index = 10
+    pb.run(3)
+    pb.get_state()
+    s2 = O.run(adi.MFD, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=2, K=med["K"], Rv=med["Rv"], Rw=med["Rw"],
+               src=src)
+    ref = O.run(adi.MFD, *s2, h=h, dt=dt, nsteps=3, K=med["K"], Rv=med["Rv"], Rw=med["Rw"], src=src,
+                t0=10 * dt)
+    for g, r in zip(written_parts(adi.MFD, *np3(x)), written_parts(adi.MFD, *ref)):
+        assert max_rel(g, r) <= TOL64
+    pb.close()
+
+
+@pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
+def test_bind_refuses_materials_above_c_max(method):
+    """The step size and the direct solves' margins were planned for c_max:
+    kappa0 = 4 (c = 2) with c_max = 1 is refused at bind, as are arrays whose
+    largest kappa exceeds c_max^2."""
+    n = 64
+    f = inputs.random_fields(method, n, n, 3)
+    U, V, W = tensors(f, adi.FP64)
+    for sweeps in (0, 6):
+        p = adi.make_params(method, adi.FP64, n, n, 1.0 / n, 0.5 / n, 1.0, sweeps=sweeps, kappa0=4.0)
+        pb = adi.Problem(p)
+        with pytest.raises(adi.AdiError, match="c_max"):
+            pb.bind(U, V, W)
+        pb.close()
+    K = torch.ones_like(U)
+    K[n // 2, n // 3] = 1.21
+    p = adi.make_params(method, adi.FP64, n, n, 1.0 / n, 0.5 / n, 1.0)
+    pb = adi.Problem(p)
+    with pytest.raises(adi.AdiError, match="c_max"):
+        pb.bind(U, V, W, K)
+    p = adi.make_params(method, adi.FP64, n, n, 1.0 / n, 0.5 / n, 1.1)
+    pb = adi.Problem(p).bind(U, V, W, K)   # c_max = 1.1 covers it
+    pb.close()
+
+
+def test_held_requests_fetched_once():
+    """ADI_REQUEST_HOLD keeps the result in the server's memory until
+    adi_fetch; it equals the result returned in the request's arrays and the
+    oracle; a second fetch is refused; the memory goes back to the arena."""
+    method, dtype, nx, ny = adi.MFD, adi.FP64, 90, 70
+    h, f, med, cmax, dt, src = setup(method, dtype, nx, ny, 0, 6, seed=81)
+    p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src)
+    arr = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    mats = [arr(med[k]) for k in ("K", "Rv", "Rw")]
+    srv = adi.Server(hbm_budget_bytes=64 << 20, max_active=4)
+    plain = [arr(f[k]) for k in "UVW"]
+    held = [arr(f[k]) for k in "UVW"]
+    t1 = srv.submit(p, *plain, *mats, nsteps=5)
+    t2 = srv.submit(p, *held, *mats, nsteps=5, hold=True)
+    srv.wait(t1)
+    srv.wait(t2)
+    for a, k in zip(held, "UVW"):
+        assert np.array_equal(a, f[k])            # inputs only
+    assert srv.stats()["arena_used"] > 0           # the held result
+    out = [np.zeros_like(a) for a in held]
+    srv.fetch(t2, *out)
+    assert srv.stats()["arena_used"] == 0
+    with pytest.raises(adi.AdiError, match="already fetched"):
+        srv.fetch(t2, *[np.zeros_like(a) for a in held])
+    copy = [np.zeros_like(a) for a in plain]
+    srv.fetch(t1, *copy)                           # plain request: from its own arrays
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=5, K=med["K"], Rv=med["Rv"], Rw=med["Rw"],
+                src=src)
+    for a, b, c in zip(written_parts(method, *out), written_parts(method, *plain), written_parts(method, *ref)):
+        assert np.array_equal(a, b)
+        assert max_rel(a, c) <= TOL64
+    for a, b in zip(copy, plain):
+        assert np.array_equal(a, b)
+    srv.close()

@@ -46,8 +46,8 @@ def _gpu(method, dtype, c, nsteps, cap, eps=None, kmin=2):
     if eps is not None:
         pb.set_tolerance(eps, kmin)
     pb.run(nsteps)
+    pb.get_state()
     stats = pb.sweep_stats()
-    pb.sync()
     out = tuple(x.double().cpu().numpy() for x in (U, V, W))
     pb.close()
     return out, stats
