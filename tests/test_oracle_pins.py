@@ -321,6 +321,63 @@ def test_rates_mfd():
     assert _trimmed(rs) > 3.9 and min(rs) > 3.5, rs
 
 
+def pr_mode_state(alpha, beta, a, nsteps, kappa, rinv):
+    """Closed-form PR-CN state of the mode (sin a x sin b y, cos sin, sin cos)
+    with constant kappa and 1/rho and exact derivatives, from pressure 1 and
+    zero velocities: the coefficients of pressure, x- and y-velocity after
+    nsteps steps.  u_t = -kappa div v and v_t = -(1/rho) grad u act on the
+    mode through the two direction blocks A1 (x) and A2 (y)."""
+    A1 = np.array([[0, kappa * alpha, 0], [-rinv * alpha, 0, 0], [0, 0, 0.0]])
+    A2 = np.array([[0, 0, kappa * beta], [0, 0, 0], [-rinv * beta, 0, 0.0]])
+    I = np.eye(3)
+    M = np.linalg.solve(I - a * A2, I + a * A1) @ np.linalg.solve(I - a * A1, I + a * A2)
+    return np.linalg.matrix_power(M, nsteps)[:, 0]
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_constant_materials_follow_closed_form(method):
+    """No material arrays: kappa0 = 2.25 and 1/rho0 = 0.64 (c = 1.2, kappa0
+    and 1/rho0 distinct).  Pressure and both velocities of the standing mode
+    (1, 2) follow the closed-form amplification with these constants, with
+    fourth-order spatial error; exchanging the constants keeps c, hence the
+    pressure, but scales the velocities by (1/rho0) / kappa0, which fails."""
+    errs = {}
+    for N in (64, 128):
+        h = 1.0 / N
+        f = inputs.standing_mode(method, N, N, h, 1, 2)
+        dt, nsteps = 0.5 * h / 1.2, 40
+        xp, xn = inputs.pressure_coords(method, N, h), inputs.node_coords(N, h)
+        al, be = math.pi, 2 * math.pi
+        u, v, w = pr_mode_state(al, be, dt / 2, nsteps, 2.25, 0.64)
+        Ue = u * np.outer(np.sin(be * xp), np.sin(al * xp))
+        Ve = v * np.outer(np.sin(be * xp), np.cos(al * xn))
+        We = w * np.outer(np.cos(be * xn), np.sin(al * xp))
+        for kap, rin in ((2.25, 0.64), (0.64, 2.25)):
+            U, V, W = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, kappa0=kap, rinv0=rin)
+            errs[(N, kap)] = (np.abs(U - Ue)[1:-1, 1:-1].max(), np.abs(V - Ve)[1:-1, :].max(),
+                              np.abs(W - We)[:, 1:-1].max())
+    assert max(errs[(64, 2.25)]) < 5e-6, errs
+    assert all(e64 / e128 > 12 for e64, e128 in zip(errs[(64, 2.25)], errs[(128, 2.25)])), errs
+    assert min(errs[(64, 0.64)][1:]) > 0.1, errs
+
+
+@pytest.mark.slow
+def test_mfd_config2_mode_time_error_full_size():
+    """The mimetic standing mode sin(2 pi x) sin(3 pi y) on 1024^2 cells,
+    1000 steps of h/2 (T = 0.48828125): the max error against the exact mode
+    equals the closed-form PR-CN time error 6.556e-6 within 1 %."""
+    N = 1024
+    h = 1.0 / N
+    f = inputs.standing_mode(O.MFD, N, N, h, 2, 3)
+    U, _, _ = O.run(O.MFD, f["U"], f["V"], f["W"], h=h, dt=h / 2, nsteps=1000, sweeps=6)
+    T = 1000 * h / 2
+    err = np.abs(U - f["U"] * math.cos(math.sqrt(13) * math.pi * T)).max()
+    g = pr_mode_factor(2 * math.pi, 3 * math.pi, h / 4, 1000)
+    assert abs(g - math.cos(math.sqrt(13) * math.pi * T)) == pytest.approx(6.556e-6, rel=1e-3)
+    assert err == pytest.approx(6.556e-6, rel=1e-2)
+    assert np.abs(U - g * f["U"]).max() < 1e-2 * err
+
+
 def test_mfd_config2_mode_time_error_small_grid():
     """Same closed form for the MFD mode on a 128 grid, 100 steps of h/2."""
     N = 128
