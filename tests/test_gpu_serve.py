@@ -38,7 +38,7 @@ def request(method, dtype, nx, ny, order, nsteps, seed):
     dt = 0.6 * h / cmax
     src = {"i": max(1, nx // 3), "j": max(1, ny // 2), "f0": 4.0, "t0": 0.1, "amp": 1.0}
     npdt = np.float64 if dtype == adi.FP64 else np.float32
-    arrs = {k: np.ascontiguousarray(f[k], dtype=npdt) for k in ("U", "V", "W")}
+    arrs = {k: np.array(f[k], dtype=npdt) for k in ("U", "V", "W")}   # copies: results overwrite them
     mats = {k: np.ascontiguousarray(med[k], dtype=npdt) for k in ("K", "Rv", "Rw")}
     p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src, order=order)
     return dict(p=p, arrs=arrs, mats=mats, h=h, dt=dt, cmax=cmax, src=src, nsteps=nsteps, order=order, f=f,

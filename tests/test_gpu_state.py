@@ -151,7 +151,7 @@ def test_held_requests_fetched_once():
     method, dtype, nx, ny = adi.MFD, adi.FP64, 90, 70
     h, f, med, cmax, dt, src = setup(method, dtype, nx, ny, 0, 6, seed=81)
     p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src)
-    arr = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    arr = lambda a: np.array(a, dtype=np.float64)   # copies: results overwrite them
     mats = [arr(med[k]) for k in ("K", "Rv", "Rw")]
     srv = adi.Server(hbm_budget_bytes=64 << 20, max_active=4)
     plain = [arr(f[k]) for k in "UVW"]
