@@ -141,11 +141,10 @@ double coef_Pbar(int r, int which, int n) {
 }
 
 // Factor tables of the single-window kernel (one window per line): [6][WS],
-// WS = window of the plan's tile shape.
-void build_tables(const Plan& p, std::vector<double>& out) {
+// WS = window of the plan's tile shape, into t[0 .. 6 WS).
+void build_tables(const Plan& p, double* t) {
     const int WS = adi::line_ws(p.cfg);
-    out.assign((size_t)6 * WS, 0.0);
-    double* t = out.data();
+    for (int i = 0; i < 6 * WS; ++i) t[i] = 0.0;
     factor_rows(0, p.n, 0, p.n, 0, coef_P, p.n, t, t + WS, t + 2 * WS);
     factor_rows(1, p.n - 1, 1, p.n - 1, 0, coef_Pbar, p.n, t + 3 * WS, t + 4 * WS, t + 5 * WS);
 }
@@ -785,6 +784,11 @@ int materialize(adi_problem* pb, void* U, void* V, void* W) {
 
 namespace {
 
+__global__ void __launch_bounds__(256) clear_kernel(uint4* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Per-block maxima of x[0..n) (non-negative values) into out[blockIdx.x].
 template <typename T>
 __global__ void __launch_bounds__(256) block_max_kernel(const T* __restrict__ x, int64_t n, double* out) {
@@ -808,7 +812,22 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
     const T a = (T)pb->a;
     // the workspace starts zeroed: line-major arrays keep zeros on the
     // boundary slots and on the padding lines
-    HIP_TRY(hipMemsetAsync(pb->ws, 0, pb->ws_bytes, st), "workspace clear");
+    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)std::min<size_t>(4096, (pb->ws_bytes / 16 + 255) / 256)),
+                       dim3(256), 0, st, (uint4*)pb->ws, pb->ws_bytes / 16);
+    HIP_TRY(hipGetLastError(), "workspace clear");
+    // factor tables of the compact single-window kernel (the multi-window
+    // kernel uses compile-time constants); the host copies live until the
+    // synchronisation below
+    T tab[2][6 * adi::LINE_WS];
+    for (int d = 0; d < 2 && p.method == ADI_CFD; ++d) {
+        const Plan& pl = d == 0 ? pb->px : pb->py;
+        if (pl.ver != 1) continue;
+        double t64[6 * adi::LINE_WS];
+        build_tables(pl, t64);
+        const int cnt = 6 * adi::line_ws(pl.cfg);
+        for (int i = 0; i < cnt; ++i) tab[d][i] = (T)t64[i];
+        HIP_TRY(hipMemcpyAsync(pb->d[d].coef, tab[d], cnt * sizeof(T), hipMemcpyHostToDevice, st), "factor tables");
+    }
     const T dconst[2] = {(T)(pb->a * p.kappa0), (T)(pb->a * p.rinv0)};
     if (pb->dconst)
         HIP_TRY(hipMemcpyAsync(pb->dconst, dconst, sizeof(dconst), hipMemcpyHostToDevice, st), "constant materials");
@@ -844,24 +863,50 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
         if (!(c2 <= p.c_max * p.c_max * (1.0 + 1e-5)))
             return fail(ADI_EINVAL, "max kappa * max 1/rho = %.6g exceeds c_max^2 = %.6g", c2, p.c_max * p.c_max);
     }
-    if (p.method == ADI_CFD) {
-        // factor tables of the single-window kernel (the multi-window kernel
-        // uses compile-time constants)
-        std::vector<double> tx, ty;
-        if (pb->px.ver == 1) build_tables(pb->px, tx);
-        if (pb->py.ver == 1) build_tables(pb->py, ty);
-        std::vector<T> cx(tx.begin(), tx.end()), cy(ty.begin(), ty.end());
-        if (!cx.empty())
-            HIP_TRY(hipMemcpyAsync(pb->d[0].coef, cx.data(), cx.size() * sizeof(T), hipMemcpyHostToDevice, st),
-                    "x tables");
-        if (!cy.empty())
-            HIP_TRY(hipMemcpyAsync(pb->d[1].coef, cy.data(), cy.size() * sizeof(T), hipMemcpyHostToDevice, st),
-                    "y tables");
-        HIP_TRY(hipStreamSynchronize(st), "bind sync");
-        return ADI_OK;
-    }
     HIP_TRY(hipStreamSynchronize(st), "bind sync");
     return ADI_OK;
+}
+
+// Leading dimensions of U, V, W, K, Rv, Rw: ld[i] when given and non-zero
+// (at least the row length), else the row length.
+int leading_dims(const adi_params& p, const int64_t* ld, int64_t l[6]) {
+    const bool cfd = p.method == ADI_CFD;
+    const int64_t colsU = cfd ? p.nx + 1 : p.nx + 2, colsV = p.nx + 1, colsW = cfd ? p.nx + 1 : p.nx + 2;
+    const int64_t c[6] = {colsU, colsV, colsW, colsU, colsV, colsW};
+    for (int i = 0; i < 6; ++i) {
+        l[i] = c[i];
+        if (ld && ld[i] != 0) {
+            if (ld[i] < c[i])
+                return fail(ADI_EINVAL, "ld[%d] = %lld below the row length %lld", i, (long long)ld[i], (long long)c[i]);
+            l[i] = ld[i];
+        }
+    }
+    return ADI_OK;
+}
+
+// Point the problem's device arrays into the workspace w laid out by L.
+void place(adi_problem* pb, const Layout& L, char* w) {
+    const auto& p = pb->p;
+    const bool comp = p.dtype == ADI_FP32C;
+    pb->ws = w;
+    pb->ws_bytes = L.total;
+    for (int d = 0; d < 2; ++d) {
+        auto& D = pb->d[d];
+        const bool hasR = d == 0 ? pb->hasRv : pb->hasRw;
+        D.P = w + L.off[d][0];
+        D.V[0] = w + L.off[d][1];
+        D.V[1] = w + L.off[d][2];
+        D.K = pb->hasK ? w + L.off[d][3] : nullptr;
+        D.R = hasR ? w + L.off[d][4] : nullptr;
+        D.Plo = comp ? w + L.off[d][5] : nullptr;
+        D.Vlo[0] = comp ? w + L.off[d][6] : nullptr;
+        D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
+        D.coef = w + L.off[d][8];
+        D.Vs = L.off[d][9] != L.off[d][10] ? w + L.off[d][9] : nullptr;
+        D.Vslo = comp && D.Vs ? w + L.off[d][10] : nullptr;
+    }
+    pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
+    pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
 }
 
 }  // namespace
@@ -939,16 +984,9 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
     if (!pb) return fail(ADI_EINVAL, "problem is NULL");
     if (!U || !V || !W) return fail(ADI_EINVAL, "U, V and W are required");
     const auto& p = pb->p;
-    const bool cfd = p.method == ADI_CFD;
-    const int64_t colsU = cfd ? p.nx + 1 : p.nx + 2, colsV = p.nx + 1, colsW = cfd ? p.nx + 1 : p.nx + 2;
-    int64_t l[6] = {colsU, colsV, colsW, colsU, colsV, colsW};
-    if (ld)
-        for (int i = 0; i < 6; ++i)
-            if (ld[i] != 0) {
-                if (ld[i] < l[i]) return fail(ADI_EINVAL, "ld[%d] = %lld below the row length %lld", i,
-                                              (long long)ld[i], (long long)l[i]);
-                l[i] = ld[i];
-            }
+    int64_t l[6];
+    int rc = leading_dims(p, ld, l);
+    if (rc != ADI_OK) return rc;
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
     if (pb->own_ws && pb->ws) {
         (void)hipFree(pb->ws);
@@ -973,26 +1011,7 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->ws = (char*)mem;
         pb->own_ws = true;
     }
-    pb->ws_bytes = L.total;
-    for (int d = 0; d < 2; ++d) {
-        auto& D = pb->d[d];
-        const bool hasR = d == 0 ? pb->hasRv : pb->hasRw;
-        const bool comp = p.dtype == ADI_FP32C;
-        char* w = pb->ws;
-        D.P = w + L.off[d][0];
-        D.V[0] = w + L.off[d][1];
-        D.V[1] = w + L.off[d][2];
-        D.K = pb->hasK ? w + L.off[d][3] : nullptr;
-        D.R = hasR ? w + L.off[d][4] : nullptr;
-        D.Plo = comp ? w + L.off[d][5] : nullptr;
-        D.Vlo[0] = comp ? w + L.off[d][6] : nullptr;
-        D.Vlo[1] = comp ? w + L.off[d][7] : nullptr;
-        D.coef = w + L.off[d][8];
-        D.Vs = L.off[d][9] != L.off[d][10] ? w + L.off[d][9] : nullptr;
-        D.Vslo = comp && D.Vs ? w + L.off[d][10] : nullptr;
-        pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
-        pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
-    }
+    place(pb, L, pb->ws);
     if (p.sweeps == 0 && !pb->dst2) {
         HIP_TRY(hipStreamCreateWithFlags(&pb->dst2, hipStreamNonBlocking), "direct solves: second stream");
         HIP_TRY(hipEventCreateWithFlags(&pb->dev_in, hipEventDisableTiming), "direct solves: event");
@@ -1003,7 +1022,7 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
     pb->vcur = pb->wcur = 0;
     pb->step = 0;
     pb->ready = false;
-    int rc = p.dtype != ADI_FP64
+    rc = p.dtype != ADI_FP64
                  ? bind_materials<float>(pb, (const float*)K, (const float*)Rv, (const float*)Rw, l[3], l[4], l[5])
                  : bind_materials<double>(pb, (const double*)K, (const double*)Rv, (const double*)Rw, l[3], l[4], l[5]);
     if (rc != ADI_OK) return rc;
