@@ -65,12 +65,12 @@ constexpr double kDelta = 3.7320508075688772935;   // 2 + sqrt 3, interior pivot
 
 int64_t pad_to(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-Plan make_plan(int method, int dtype, int n, int nlines, int sweeps) {
+Plan make_plan(int method, int dtype, int n, int nlines, int sweeps, double cfl) {
     Plan p;
     p.n = n;
     p.ns = method == ADI_CFD ? n + 1 : n + 2;
     p.nlines = nlines;
-    p.H = adi::line_halo(dtype, method, sweeps);
+    p.H = adi::line_halo(dtype, method, sweeps, cfl);
     if (p.ns <= adi::LINE_WS) {
         // single window: the smallest tile shape whose window holds the line
         p.ver = 1;
@@ -284,8 +284,9 @@ void derive(adi_problem* pb) {
     pb->niy = p.method == ADI_CFD ? p.ny - 1 : p.ny;
     pb->a = 0.5 * p.dt;
     const int64_t padm = 256 / (int64_t)pb->esz;   // 256-byte rows
-    pb->px = make_plan(p.method, p.dtype, p.nx, pb->niy, p.sweeps);
-    pb->py = make_plan(p.method, p.dtype, p.ny, pb->nix, p.sweeps);
+    const double cfl = p.dt * p.c_max / p.h;
+    pb->px = make_plan(p.method, p.dtype, p.nx, pb->niy, p.sweeps, cfl);
+    pb->py = make_plan(p.method, p.dtype, p.ny, pb->nix, p.sweeps, cfl);
     if (p.sweeps == 0) {
         direct_plan(pb->px, p);
         direct_plan(pb->py, p);

@@ -74,7 +74,7 @@ hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t
 
 int line_lanes(int dtype, int cfg);
 int line_ws(int cfg);
-int line_halo(int dtype, int method, int sweeps);
+int line_halo(int dtype, int method, int sweeps, double cfl);
 
 // Multi-window variant (line_pass2.hip): lines per workgroup and slots per
 // lane segment.

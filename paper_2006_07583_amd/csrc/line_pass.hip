@@ -575,15 +575,19 @@ int line_ws(int cfg) {
 // Overlap of neighbouring windows, in slots.  Mimetic: the dependence cone
 // of K sweeps plus the final derivative is 3K + 2 slots; two slots spare.
 // Compact: the window-edge error decays like (2 - sqrt 3)^d times a
-// polynomial in d of the degree of the number of chained solves (2K + 1).
-// For K = 6 a dense model of one line pass gives a relative error at
-// distance 30 of 7e-11 at CFL 0.8 and 2.8e-8 at the CFL limit 1.15, below
-// the FP32 rounding unit; FP64 (and the compensated mode) keep a wider
-// margin.  All margins are even (K is even): the windows of the
-// wave-per-line kernel then start on multiples of 4 slots.
-int line_halo(int dtype, int method, int sweeps) {
+// polynomial in d of the degree of the number of chained solves (2K + 1),
+// and faster at smaller step sizes.  A model of one line pass on a whole
+// line and on a window cut out of it (the outside dropped, the interior
+// pivot at the window's first row) puts the truncation at these margins
+// below 2^-24 (FP32) and at the FP64 rounding level (FP64 and the
+// compensated mode) for K = 2..16 and every cfl up to 1.149; for K = 6 the
+// FP32 margin leaves 3e-10 at cfl 0.8 and 2e-8 at 1.149.  All margins are
+// even (K is even): the windows of the wave-per-line kernel then start on
+// multiples of 4 slots.
+int line_halo(int dtype, int method, int sweeps, double cfl) {
     if (method == LINE_MFD) return 3 * sweeps + 4;
-    return dtype == 0 ? 18 + 2 * sweeps : 40 + 3 * sweeps;
+    if (dtype == 0) return 18 + 2 * sweeps;
+    return cfl <= 0.85 ? 36 + 2 * sweeps : 40 + 3 * sweeps;
 }
 
 template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, int);
