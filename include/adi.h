@@ -177,6 +177,24 @@ int adi_sync(adi_problem* pb);
  * hand-off), plus transposed copies of the velocities. */
 int adi_get_state(adi_problem* pb, void* U, void* V, void* W);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): create,
+ * bind, run nsteps steps (as adi_run) and write the state into U, V, W (as
+ * adi_get_state) in one call, with no problem object and no allocation.  The
+ * arguments are those of adi_create, adi_bind and adi_run; the workspace is
+ * a static device array of 64 MiB per GPU (held from the library's first
+ * use of that GPU until the process ends), so problems whose
+ * adi_workspace_size exceeds 64 MiB are refused (ADI_EINVAL), as are direct
+ * solves (sweeps 0).  The call waits for the stream once (the material check
+ * of adi_bind) and returns with the steps and the write-out queued on
+ * hip_stream.  Every call on a GPU shares that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller; calls queued on
+ * one stream are ordered. */
+int adi_run_noalloc(const adi_params* p, void* hip_stream, void* U, void* V, void* W,
+                    const void* K, const void* Rv, const void* Rw, const int64_t* ld,
+                    int64_t nsteps);
+
 /* Current time level m (time t0 + m dt) / set it (checkpoint resume).
  * Setting another level while the state is in the workspace first writes the
  * state into the bound arrays; the next run starts from them. */

@@ -20,7 +20,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
-           "adi_get_step", "adi_set_step", "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
+           "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
            "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait", "adi_fetch",
@@ -91,6 +91,8 @@ def lib():
         L.adi_step.argtypes = [vp]
         L.adi_sync.argtypes = [vp]
         L.adi_get_state.argtypes = [vp, vp, vp, vp]
+        L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(i64), i64]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
         L.adi_set_step.argtypes = [vp, i64]
         L.adi_set_tolerance.argtypes = [vp, ctypes.c_double, ctypes.c_int]
@@ -143,6 +145,23 @@ def workspace_size(params: AdiParams, has_K=False, has_Rv=False, has_Rw=False) -
 
 def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def run_noalloc(params: AdiParams, U, V, W, K=None, Rv=None, Rw=None, nsteps=1, stream=None):
+    """adi_run_noalloc: nsteps steps of the problem on torch device tensors
+    (U, V, W updated in place, asynchronously on `stream`) with the library's
+    static workspace: no device allocation."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ld = (ctypes.c_int64 * 6)()
+    for i, t in enumerate((U, V, W, K, Rv, Rw)):
+        if t is not None:
+            if t.dim() != 2 or t.stride(1) != 1:
+                raise ValueError("arrays must be 2-D with contiguous rows")
+            ld[i] = t.stride(0)
+    _check(lib().adi_run_noalloc(ctypes.byref(params), ctypes.c_void_p(stream.cuda_stream),
+                                 *[_dptr(t) for t in (U, V, W, K, Rv, Rw)], ld, int(nsteps)))
 
 
 class Problem:

@@ -22,6 +22,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -910,6 +911,27 @@ void place(adi_problem* pb, const Layout& L, char* w) {
     pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
 }
 
+// Workspace of adi_run_noalloc: one static device array per GPU, held until
+// the process ends.  Host code never names it in device work: the address
+// comes from hipGetSymbolAddress, once per device, with the device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+int scratch_of_device(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(ADI_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = (char*)ptr;
+    }
+    *out = g_scratch[dev];
+    return ADI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1060,6 +1082,46 @@ int adi_sync(adi_problem* pb) {
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
     return ADI_OK;
+}
+
+int adi_run_noalloc(const adi_params* p, void* hip_stream, void* U, void* V, void* W, const void* K,
+                    const void* Rv, const void* Rw, const int64_t* ld, int64_t nsteps) {
+    g_err.clear();
+    int rc = validate(p);
+    if (rc != ADI_OK) return rc;
+    if (p->sweeps == 0) return fail(ADI_EINVAL, "adi_run_noalloc runs fixed sweep counts, not direct solves");
+    if (!U || !V || !W) return fail(ADI_EINVAL, "U, V and W are required");
+    if (nsteps < 0) return fail(ADI_EINVAL, "nsteps < 0");
+    adi_problem pb;
+    pb.p = *p;
+    pb.st = (hipStream_t)hip_stream;
+    derive(&pb);
+    pb.hasK = K != nullptr;
+    pb.hasRv = Rv != nullptr;
+    pb.hasRw = Rw != nullptr;
+    const Layout L = layout(pb);
+    if (L.total > kScratchBytes)
+        return fail(ADI_EINVAL, "workspace of %zu bytes exceeds the %zu bytes of adi_run_noalloc", L.total,
+                    kScratchBytes);
+    int64_t l[6];
+    rc = leading_dims(pb.p, ld, l);
+    if (rc != ADI_OK) return rc;
+    HIP_TRY(hipGetDevice(&pb.dev), "hipGetDevice");
+    char* w = nullptr;
+    rc = scratch_of_device(pb.dev, &w);
+    if (rc != ADI_OK) return rc;
+    place(&pb, L, w);
+    pb.U = U; pb.V = V; pb.W = W;
+    pb.ldU = l[0]; pb.ldV = l[1]; pb.ldW = l[2];
+    rc = p->dtype != ADI_FP64
+             ? bind_materials<float>(&pb, (const float*)K, (const float*)Rv, (const float*)Rw, l[3], l[4], l[5])
+             : bind_materials<double>(&pb, (const double*)K, (const double*)Rv, (const double*)Rw, l[3], l[4], l[5]);
+    if (rc != ADI_OK) return rc;
+    pb.bound = true;
+    if (nsteps == 0) return ADI_OK;
+    rc = p->dtype != ADI_FP64 ? run_impl<float>(&pb, nsteps) : run_impl<double>(&pb, nsteps);
+    if (rc != ADI_OK) return rc;
+    return adi::materialize(&pb, U, V, W);
 }
 
 int adi_get_step(const adi_problem* pb, int64_t* m) {
