@@ -82,11 +82,11 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps, double cfl)
         p.S = p.ns;
         p.deep = 1;
     } else {
-        // multi-window: the wave-per-line kernel (barrier-free sweeps); the
-        // segment kernel for the compensated mode, which it alone implements,
-        // and for the direct solves, whose thread-per-line passes read the
-        // slot-major layout it keeps (64 lines at one slot are contiguous)
-        p.ver = (dtype == ADI_FP32C || sweeps == 0) ? 2 : 3;
+        // multi-window: the wave-per-line kernel (barrier-free sweeps, all
+        // three number modes); the direct solves keep the slot-major layout
+        // of the segment kernel, which their thread-per-line passes read (64
+        // lines at one slot are contiguous)
+        p.ver = sweeps == 0 ? 2 : 3;
         p.seg = adi::line2_seg(dtype);
         // windows of LINE_WS slots overlapping by 2H; the first and last own
         // LINE_WS - H central slots, the others S = LINE_WS - 2H
@@ -358,7 +358,8 @@ template <typename T> Buf<T> vel(const adi_problem* pb, int d, int i) {
 template <typename T> Buf<T> pres_out(const adi_problem* pb, int from, int& utrans) {
     const auto& O = pb->d[1 - from];
     utrans = O.lm ? 0 : 1;
-    return O.lm ? Buf<T>{(T*)O.P + O.ld + 1, nullptr, O.ld} : Buf<T>{(T*)O.P, (T*)O.Plo, O.ld};
+    return O.lm ? Buf<T>{(T*)O.P + O.ld + 1, O.Plo ? (T*)O.Plo + O.ld + 1 : nullptr, O.ld}
+                : Buf<T>{(T*)O.P, (T*)O.Plo, O.ld};
 }
 
 // Copies between the caller's natural arrays (row = y) and the arrays of
@@ -424,7 +425,10 @@ adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, co
     a.utrans = utrans;
     // the wave-per-line kernel writes the natural-layout pressure at
     // (s - 1) * ld + (q + 1): its base is one element lower
-    if (pl.ver == 3 && utrans == 0) a.uout = uout.hi - 1;
+    if (pl.ver == 3 && utrans == 0) {
+        a.uout = uout.hi - 1;
+        if (uout.lo) a.uout_lo = uout.lo - 1;
+    }
     if (p.src_i >= 0) {
         a.src_q = dir == 0 ? p.src_j - 1 : p.src_i - 1;
         a.src_s = dir == 0 ? p.src_i : p.src_j;
@@ -454,7 +458,7 @@ template <typename T>
 hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st) {
     if (d.ver == 1) return launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg);
     if (d.ver == 2) return launch_line_pass2<T>(d.a, d.method, d.mode, st, d.comp);
-    return launch_line_pass3<T>(d.a, d.method, d.mode, st);
+    return launch_line_pass3<T>(d.a, d.method, d.mode, st, d.comp);
 }
 
 template <typename T>
@@ -557,7 +561,7 @@ template <typename T>
 hipError_t launch_grouped(const PassDesc<T>& d, const GroupArgs<T>& ga, hipStream_t st) {
     if (d.ver == 1) return launch_line_group<T>(ga, d.cfg, d.method, d.mode, st, d.comp);
     if (d.ver == 2) return launch_line_group2<T>(ga, d.method, d.mode, st, d.comp);
-    return launch_line_group3<T>(ga, d.method, d.mode, st);
+    return launch_line_group3<T>(ga, d.method, d.mode, st, d.comp);
 }
 
 template hipError_t launch_grouped<float>(const PassDesc<float>&, const GroupArgs<float>&, hipStream_t);

@@ -85,12 +85,12 @@ hipError_t launch_line_group2(const GroupArgs<T>& g, int method, int mode, hipSt
 int line2_lanes(int dtype);
 int line2_seg(int dtype);
 
-// Multi-window variant with one line per half wave (line_pass3.hip; FP32 and
-// FP64, not the compensated mode): lines per workgroup.
+// Multi-window variant with one line per half wave (line_pass3.hip; FP32,
+// FP64 and the compensated FP32 mode): lines per workgroup.
 template <typename T>
-hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st);
+hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
 template <typename T>
-hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st);
+hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp = false);
 int line3_lanes(int dtype);
 
 // Tolerance-tested stages (LinePassArgs::eps_part): a pass is `attempts`

@@ -28,6 +28,11 @@
 //    rows with readlane.
 //  * Mimetic scheme: the 4-tap stencils need the last / first 3 values of
 //    the neighbouring lanes: 6 lane shifts per velocity evaluation.
+//  * Compensated FP32 (COMP): the carried state is a (value, low word) pair.
+//    The pass takes the derivatives of the values once, iterates on the
+//    increments u - A and v - B (small numbers, so FP32 loses little), and
+//    adds the final increments to the pairs with TwoSum; the pairs are read
+//    again through the tile for that last step.
 //
 // Lanes at the window edges see zeros beyond the window; the windows overlap
 // by H slots on each side and only the central slots are written (the
@@ -331,8 +336,9 @@ template <typename T, int METHOD> struct Line3 {
 // EPS: the tolerance-tested form (LinePassArgs::eps_part).  It keeps the
 // previous iterates by solving into a spare array, and stores the squared
 // changes of the last two sweeps over the slots the window writes.
-template <typename T, int METHOD, int MODE, bool EPS = false>
+template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
+    static_assert(!(EPS && COMP), "the tolerance-tested form runs without compensation");
     if (EPS && *a.eps_go == 0) return;   // uniform: an earlier attempt converged
     using C = K3<T>;
     constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW;
@@ -530,7 +536,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         // neighbours' edge values of the inputs
         T Al = L.prev(A[R - 1]), Ar = L.next(A[0]);
         const T Kl = L.prev(KK[R - 1]), Kr = L.next(KK[0]);
-        const T Bl = L.prev(B[R - 1]), Br = L.next(B[0]);
+        T Bl = L.prev(B[R - 1]), Br = L.next(B[0]);
         const T Rl = L.prev(RR[R - 1]), Rr = L.next(RR[0]);
         T xl, xr;
         if (MODE == LINE_EXPLICIT) {
@@ -540,16 +546,41 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             L.solve(1, U, xl, xr);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                Tt[k] = fma(-RR[k], Tt[k], B[k]);     // W* = B - aR G(A)
-                U[k] = fma(-KK[k], U[k], A[k]);       // A - aK D(B)
+                // W* = B - aR G(A), A - aK D(B) (the increments when compensated)
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
             }
         } else {
-            // u_1 = A - aK D(B)
-            L.rhs(1, B, Bl, Br, U);
-            L.solve(1, U, xl, xr);
+            T Ul, Ur;
+            if constexpr (COMP) {
+                // derivatives of the state, then the sweeps on the increments:
+                // A' = -aK D(B) (= u_1 - A) and B' = -aR G(A) replace A and B
+                L.rhs(0, A, Al, Ar, Tt);
+                L.solve(0, Tt, xl, xr);
+                const T gl = -Rl * xl, gr = -Rr * xr;
+                L.rhs(1, B, Bl, Br, U);
+                L.solve(1, U, xl, xr);
 #pragma unroll
-            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
-            T Ul = fma(-Kl, xl, Al), Ur = fma(-Kr, xr, Ar);
+                for (int k = 0; k < R; ++k) {
+                    A[k] = -KK[k] * U[k];
+                    B[k] = -RR[k] * Tt[k];
+                    U[k] = A[k];
+                }
+                Al = -Kl * xl;
+                Ar = -Kr * xr;
+                Bl = gl;
+                Br = gr;
+                Ul = Al;
+                Ur = Ar;
+            } else {
+                // u_1 = A - aK D(B)
+                L.rhs(1, B, Bl, Br, U);
+                L.solve(1, U, xl, xr);
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                Ul = fma(-Kl, xl, Al);
+                Ur = fma(-Kr, xr, Ar);
+            }
             T Tl, Tr;
             if constexpr (EPS) {
                 T X[R];
@@ -614,19 +645,23 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             if (MODE == LINE_SWEEP) {
                 Tl = fma(-Rl, xl, Bl);
                 Tr = fma(-Rr, xr, Br);
+                if constexpr (COMP) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) U[k] += A[k];                   // u_K - A + A'
+                }
                 L.rhs(1, Tt, Tl, Tr, A);
                 L.solve(1, A, xl, xr);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const T vk = Tt[k];
-                    Tt[k] = vk + (vk - B[k]);                                   // 2 v_K - B
+                    Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);                  // 2 v_K - B
                     U[k] = fma(-KK[k], A[k], U[k]);                             // u_K - aK D(v_K)
                 }
             }
         }
     } else {
         // ---- mimetic ----
-        const T Bm2 = L.prev(B[R - 2]), Bm1 = L.prev(B[R - 1]), Bp = L.next(B[0]);
+        T Bm2 = L.prev(B[R - 2]), Bm1 = L.prev(B[R - 1]), Bp = L.next(B[0]);
         const T Rm2 = L.prev(RR[R - 2]), Rm1 = L.prev(RR[R - 1]), Rp = L.next(RR[0]);
         const T ih8 = T(8.0 / 9.0);   // boundary rows are divided by the folded 9/8
         const T d0c[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
@@ -710,14 +745,35 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             applyD(B, Bm2, Bm1, Bp, U);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                Tt[k] = fma(-RR[k], Tt[k], B[k]);
-                U[k] = fma(-KK[k], U[k], A[k]);
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
             }
         } else {
             T Tm2, Tm1, Tp;
-            applyD(B, Bm2, Bm1, Bp, U);
+            if constexpr (COMP) {
+                // derivatives of the state, then the sweeps on the increments
+                // (A' = -aK D(B), B' = -aR G(A), halos included)
+                T ul[3], ur[3];
+                halo_u(A, ul, ur);
+                applyG(A, ul, ur, Tt);
+                applyD(B, Bm2, Bm1, Bp, U);
+                const T gm2 = -Rm2 * mg(ul[0], ul[1], ul[2], A[0]);
+                const T gm1 = -Rm1 * mg(ul[1], ul[2], A[0], A[1]);
+                const T gp = -Rp * mg(A[R - 1], ur[0], ur[1], ur[2]);
 #pragma unroll
-            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+                for (int k = 0; k < R; ++k) {
+                    A[k] = -KK[k] * U[k];
+                    B[k] = -RR[k] * Tt[k];
+                    U[k] = A[k];
+                }
+                Bm2 = gm2;
+                Bm1 = gm1;
+                Bp = gp;
+            } else {
+                applyD(B, Bm2, Bm1, Bp, U);
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            }
             if constexpr (EPS) {
                 T X[R];
 #pragma unroll
@@ -757,11 +813,15 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 velocity(U, Tt, Tm2, Tm1, Tp);                               // v_K
             }
             if (MODE == LINE_SWEEP) {
+                if constexpr (COMP) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) U[k] += A[k];
+                }
                 applyD(Tt, Tm2, Tm1, Tp, A);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const T vk = Tt[k];
-                    Tt[k] = vk + (vk - B[k]);
+                    Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);
                     U[k] = fma(-KK[k], A[k], U[k]);
                 }
             }
@@ -796,13 +856,13 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         }
     }
     // velocity into the line-major output (central slots only)
-    {
-        __syncthreads();   // readers of the input tile are done
-        with_shift([&](auto shc) { write_seg(shc, Tt); });
+    auto store_vel = [&](const T (&vals)[R], T* out) {
+        __syncthreads();   // readers of the tile are done
+        with_shift([&](auto shc) { write_seg(shc, vals); });
         __syncthreads();
         const int64_t bytes = lm_rows * a.vout_ld * (int64_t)sizeof(T);
         const bool buf = bytes < kBufMax;
-        const auto rs = make_rsrc(a.vout, buf ? bytes : 0);
+        const auto rs = make_rsrc(out, buf ? bytes : 0);
         // chunk at tile position pos (slots s .. s + VEC - 1) of tile row l
         auto put = [&](int l, int pos, int s) {
             const int rr = lg * LW + l;
@@ -811,23 +871,24 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             const int64_t off = (int64_t)rr * a.vout_ld + s;
             if (s >= c0 && s + VEC <= c1 && s + VEC - 1 <= n) {
                 if (buf) bstore16(v, rs, (int)(off * (int64_t)sizeof(T)), 0);
-                else *reinterpret_cast<VT*>(a.vout + off) = v;
+                else *reinterpret_cast<VT*>(out + off) = v;
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     if (s + e >= c0 && s + e < c1 && s + e <= n) {
                         if (buf) bstore(v[e], rs, (int)((off + e) * (int64_t)sizeof(T)));
-                        else a.vout[off + e] = v[e];
+                        else out[off + e] = v[e];
                     }
             }
         };
 #pragma unroll
         for (int j = 0; j < CPT; ++j) put(st_l + j * RPJ, TM::chunk(st_c / NC, st_c % NC), wa + st_c * VEC);
         if (xtra) put(tid, WS, wa + WS);
-    }
+    };
     // pressure hand-off for the other direction, transposed through LDS
+    auto store_pres = [&](const T (&vals)[R], T* uout) {
     __syncthreads();   // readers of the tile are done
-    with_shift([&](auto shc) { write_seg(shc, U); });
+    with_shift([&](auto shc) { write_seg(shc, vals); });
     __syncthreads();
     const int lo = max(c0, 1), hi = min(c1 - 1, uhi);
     // tile position of window position p (slot wa + p)
@@ -839,11 +900,11 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         const int qq = lg * LW + l2 - 1;
         const int64_t bytes = (int64_t)a.nlines * a.uout_ld * (int64_t)sizeof(T);
         if (qq >= 0 && qq < a.nlines && bytes < kBufMax) {
-            const auto rs = make_rsrc(a.uout, bytes);
+            const auto rs = make_rsrc(uout, bytes);
             int o = (qq * (int)a.uout_ld + lo + t2 - 1) * (int)sizeof(T);
             for (int s = lo + t2; s <= hi; s += TPL, o += TPL * (int)sizeof(T)) bstore(smem[tix<T>(l2, tpos(s - wa))], rs, o);
         } else if (qq >= 0 && qq < a.nlines) {
-            T* p = a.uout + (int64_t)qq * a.uout_ld - 1;
+            T* p = uout + (int64_t)qq * a.uout_ld - 1;
             for (int s = lo + t2; s <= hi; s += TPL) p[s] = smem[tix<T>(l2, tpos(s - wa))];
         }
     } else {
@@ -860,7 +921,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             // elements the pass writes from uout: up to (uhi - 1) ld + nlines
             const int64_t lim = ((int64_t)(uhi - 1) * a.uout_ld + a.nlines + 1) * (int64_t)sizeof(T);
             const bool buf = lim < kBufMax;
-            const auto rs = make_rsrc(a.uout, buf ? lim : 0);
+            const auto rs = make_rsrc(uout, buf ? lim : 0);
             const int ldb = buf ? (int)(a.uout_ld * (int64_t)sizeof(T)) : 0;
             const int rb = rr * (int)sizeof(T);
             // chunk at tile position pos of row pl: slots s .. s + VEC - 1
@@ -878,7 +939,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
-                        if (s + e >= lo && s + e <= hi) a.uout[(int64_t)(s + e - 1) * a.uout_ld + rr] = v[e];
+                        if (s + e >= lo && s + e <= hi) uout[(int64_t)(s + e - 1) * a.uout_ld + rr] = v[e];
                 }
             };
 #pragma unroll
@@ -888,6 +949,36 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             }
             if (sh != 0 && pc == 0) put(WS, wa + WS);
         }
+    }
+    };
+    if constexpr (COMP) {
+        // the pairs (value, low word) of the inputs plus the increments;
+        // A, B, KK, RR are free now
+        auto restage = [&](const T* hi, const T* lo, int64_t ld, T (&dh)[R], T (&dl)[R]) {
+            VT ch[CPT], ce{};
+            stage_in(hi, ld, ch, ce);
+            stage_spread(ch, ce, dh);
+            if (lo) {
+                stage_in(lo, ld, ch, ce);
+                stage_spread(ch, ce, dl);
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) dl[k] = T(0);
+            }
+        };
+        restage(a.vin, a.vin_lo, a.vin_ld, A, B);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc_two_sum(A[k], B[k], Tt[k], Tt[k], A[k]);
+        store_vel(Tt, a.vout);
+        if (a.vout_lo) store_vel(A, a.vout_lo);
+        restage(a.uin, a.uin_lo, a.uin_ld, B, KK);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc_two_sum(B[k], KK[k], U[k], U[k], B[k]);
+        store_pres(U, a.uout);
+        if (a.uout_lo) store_pres(B, a.uout_lo);
+    } else {
+        store_vel(Tt, a.vout);
+        store_pres(U, a.uout);
     }
 }
 
@@ -900,7 +991,7 @@ constexpr bool kGroupOrder = METHOD == LINE_CFD || sizeof(T) == 4;
 template <typename T, bool EPS>
 constexpr int kWpe = EPS ? (sizeof(T) == 4 ? 2 : 1) : Cfg3<T>::WPE;
 
-template <typename T, int METHOD, int MODE, bool EPS = false>
+template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false>
 __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(kWpe<T, EPS>, kWpe<T, EPS>)))
 line_pass3_kernel(const LinePassArgs<T> a) {
@@ -913,10 +1004,10 @@ line_pass3_kernel(const LinePassArgs<T> a) {
     const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (t >= nb) return;
     const int tile = kGroupOrder<T, METHOD> ? (t % a.nwin) * a.nlg + t / a.nwin : t;
-    lp3_body<T, METHOD, MODE, EPS>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, EPS, COMP>(a, tile, smem);
 }
 
-template <typename T, int METHOD, int MODE>
+template <typename T, int METHOD, int MODE, bool COMP = false>
 __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
 line_pass3_group_kernel(const GroupArgs<T> ga) {
@@ -926,18 +1017,34 @@ line_pass3_group_kernel(const GroupArgs<T> ga) {
     if (it < 0) return;
     LinePassArgs<T> a = ga.items[it];
     if (a.aFtab) a.aF = a.aFtab[*ga.tick];
-    lp3_body<T, METHOD, MODE>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, false, COMP>(a, tile, smem);
+}
+
+// compensated launches exist for FP32 only
+template <typename T, int M, int MD>
+hipError_t launch3_comp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, dim3 grid, dim3 block, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (a)
+            hipLaunchKernelGGL((line_pass3_kernel<T, M, MD, false, true>), grid, block, 0, st, *a);
+        else
+            hipLaunchKernelGGL((line_pass3_group_kernel<T, M, MD, true>), grid, block, 0, st, *ga);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
-hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st) {
+hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st,
+                   bool comp) {
     const int nb = a ? a->nlg * a->nwin : ga->total;
     if (nb <= 0) return hipSuccess;
     dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
     const bool eps = a && a->eps_part;
-    if (eps && mode == LINE_EXPLICIT) return hipErrorInvalidValue;
+    if (eps && (mode == LINE_EXPLICIT || comp)) return hipErrorInvalidValue;
 #define LP3_CASE(M, MD)                                                                                  \
     if (method == M && mode == MD) {                                                                     \
+        if (comp) return launch3_comp<T, M, MD>(a, ga, grid, block, st);                                  \
         if (eps)                                                                                         \
             hipLaunchKernelGGL((line_pass3_kernel<T, M, MD, MD != LINE_EXPLICIT>), grid, block, 0, st, *a); \
         else if (a)                                                                                      \
@@ -957,13 +1064,13 @@ hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method,
 }
 
 template <typename T>
-hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st) {
-    return launch3<T>(&a, nullptr, method, mode, st);
+hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp) {
+    return launch3<T>(&a, nullptr, method, mode, st, comp);
 }
 
 template <typename T>
-hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipStream_t st) {
-    return launch3<T>(nullptr, &ga, method, mode, st);
+hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipStream_t st, bool comp) {
+    return launch3<T>(nullptr, &ga, method, mode, st, comp);
 }
 
 int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW; }
@@ -1018,9 +1125,9 @@ hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int atte
     return hipGetLastError();
 }
 
-template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_line_group3<float>(const GroupArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_line_group3<double>(const GroupArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_group3<float>(const GroupArgs<float>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_group3<double>(const GroupArgs<double>&, int, int, hipStream_t, bool);
 
 }  // namespace adi
