@@ -483,6 +483,14 @@ def main():
                      "kernel": (f"line_pass3_kernel<{'float' if head == adi.FP32 else 'double'}, {dom}, SWEEP> "
                                 f"({'compact' if dom == 0 else 'mimetic'} line pass)")},
         "variants": variants,
+        # how long the FP32 bar (rel-L2 1e-4 against the FP64 oracle) holds on
+        # the layered workload (1024^2, measured; tests/test_gpu_workloads.py
+        # test_layered_seismic_long_horizons pins it): the compact scheme's
+        # boundary modes grow from rounding, the FP64 field itself by about
+        # 1.03 per step after 400 steps
+        "cfd_fp32_horizon": {"fp32_steps": 300, "fp32c_steps": 600, "fp64_within_1e-12_steps": 1000,
+                             "mimetic_fp32_steps": ">= 2000",
+                             "note": "compact FP32 timings of the 2000-step workload run on a diverging field"},
     }
     if args.tolerance_steps > 0:
         tc = tolerance_case(n, args.tolerance_steps)

@@ -163,8 +163,28 @@ int adi_run(adi_problem* pb, int64_t nsteps);
 /* adi_run(pb, 1). */
 int adi_step(adi_problem* pb);
 
-/* Wait for all queued work of the problem. */
+/* Wait for all queued work of the problem; ADI_ENUMERIC if the health check
+ * (adi_set_check) has flagged the state. */
 int adi_sync(adi_problem* pb);
+
+/* Numerical health check, without host synchronisation during runs: every
+ * `every` steps of adi_run (0 = off, the default) a device-side reduction
+ * scans the pressure-type array of the new time level (the hand-off the step
+ * leaves for the next one; U itself after a run's final pass) for non-finite
+ * values and its largest magnitude, and folds them into a running state in
+ * the workspace.  adi_sync and adi_get_state then return ADI_ENUMERIC (after
+ * the work has drained) once a non-finite value has been seen, or, with
+ * max_abs > 0, once the largest magnitude exceeded max_abs: the compact
+ * scheme's boundary modes grow from rounding and make runs of a few thousand
+ * steps on some inputs diverge, and a bound shows that before the values
+ * overflow.  Cost: one read of a pressure-type array per check (about 13 us
+ * at 4096^2 FP32).  The call resets the running state; batches and servers
+ * do not run the check.  ADI_ENOTREADY before adi_bind. */
+int adi_set_check(adi_problem* pb, int64_t every, double max_abs);
+
+/* The running state of the health check: the largest magnitude seen and
+ * whether a non-finite value was seen (waits for the problem's work). */
+int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite);
 
 /* Write the state of the current time level m into the device arrays U, V,
  * W (shapes and leading dimensions of the bound arrays; NULL = the bound

@@ -20,7 +20,8 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
-           "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
+           "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_check", "adi_check_stats",
+           "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
            "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait", "adi_fetch",
@@ -91,6 +92,8 @@ def lib():
         L.adi_step.argtypes = [vp]
         L.adi_sync.argtypes = [vp]
         L.adi_get_state.argtypes = [vp, vp, vp, vp]
+        L.adi_set_check.argtypes = [vp, i64, ctypes.c_double]
+        L.adi_check_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
@@ -225,6 +228,18 @@ class Problem:
     @step_index.setter
     def step_index(self, m: int):
         _check(lib().adi_set_step(self._h, int(m)))
+
+    def set_check(self, every: int, max_abs: float = 0.0) -> "Problem":
+        """adi_set_check: device-side health check every `every` steps
+        (0 = off); sync and get_state raise ADI_ENUMERIC when it trips."""
+        _check(lib().adi_set_check(self._h, int(every), float(max_abs)))
+        return self
+
+    def check_stats(self):
+        """(largest magnitude seen, non-finite seen) of the health check."""
+        m, nf = ctypes.c_double(), ctypes.c_int()
+        _check(lib().adi_check_stats(self._h, ctypes.byref(m), ctypes.byref(nf)))
+        return m.value, bool(nf.value)
 
     def set_tolerance(self, eps: float, min_sweeps: int = 2) -> "Problem":
         """Tolerance-tested stages (adi_set_tolerance); eps = 0 restores the

@@ -167,9 +167,13 @@ struct Layout {
     size_t fs_off;    // factor store of the direct solves (shared by both directions)
     size_t dc_off;    // their constant materials
     size_t red_off;   // per-block partial maxima of the material check at bind
+    size_t chk_off;   // health check: per-block partials and the running state
     size_t total;
 };
 constexpr int kRedBlocks = 256;
+// health check state after the partials: {non-finite seen, largest
+// magnitude, first step found non-finite + 1, step of the last check}
+constexpr int kChkState = 2 * kRedBlocks;
 
 // Direction of the pass that ends a step.
 int last_dir(const adi_params& p) { return p.order == 0 ? 1 : 0; }
@@ -208,6 +212,8 @@ Layout layout(const adi_problem& pb) {
     if (p.sweeps == 0) cur += 256;
     L.red_off = cur;
     cur += 3 * kRedBlocks * sizeof(double);
+    L.chk_off = cur;
+    cur += (2 * kRedBlocks + 4) * sizeof(double) + 224;
     L.total = cur;
     return L;
 }
@@ -699,6 +705,80 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     return e;
 }
 
+// rows x cols of U, V, W
+void state_shapes(const adi_params& p, int64_t rows[3], int64_t cols[3]) {
+    const bool cfd = p.method == ADI_CFD;
+    rows[0] = cfd ? p.ny + 1 : p.ny + 2; cols[0] = cfd ? p.nx + 1 : p.nx + 2;
+    rows[1] = cfd ? p.ny + 1 : p.ny + 2; cols[1] = p.nx + 1;
+    rows[2] = p.ny + 1;                  cols[2] = cfd ? p.nx + 1 : p.nx + 2;
+}
+
+// Health check, first level: per block, whether x[0..n) holds a non-finite
+// value and its largest finite magnitude, into part[2 b], part[2 b + 1].
+template <typename T>
+__global__ void __launch_bounds__(256) health_kernel(const T* __restrict__ x, int64_t n, double* part) {
+    __shared__ double red[256];
+    __shared__ int bad[256];
+    double m = 0.0;
+    int nf = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = (double)x[i];
+        if (isfinite(v)) m = fmax(m, fabs(v));
+        else nf = 1;
+    }
+    red[threadIdx.x] = m;
+    bad[threadIdx.x] = nf;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            bad[threadIdx.x] |= bad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = bad[0] ? 1.0 : 0.0;
+        part[2 * blockIdx.x + 1] = red[0];
+    }
+}
+
+// Second level: the partials into the running state (sticky flag, largest
+// magnitude, first step found non-finite, step of this check).
+__global__ void __launch_bounds__(256) health_merge_kernel(const double* part, int nb, double* state, double step) {
+    __shared__ double red[256];
+    __shared__ double bad[256];
+    double m = 0.0, f = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        f = fmax(f, part[2 * i]);
+        m = fmax(m, part[2 * i + 1]);
+    }
+    red[threadIdx.x] = m;
+    bad[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            bad[threadIdx.x] = fmax(bad[threadIdx.x], bad[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (bad[0] > 0.0 && state[0] == 0.0) state[2] = step + 1.0;
+        state[0] = fmax(state[0], bad[0]);
+        state[1] = fmax(state[1], red[0]);
+        state[3] = step;
+    }
+}
+
+template <typename T>
+hipError_t launch_health(adi_problem* pb, const T* x, int64_t n, int64_t step) {
+    double* part = (double*)(pb->ws + layout(*pb).chk_off);
+    hipLaunchKernelGGL(health_kernel<T>, dim3(kRedBlocks), dim3(256), 0, pb->st, x, n, part);
+    hipLaunchKernelGGL(health_merge_kernel, dim3(1), dim3(256), 0, pb->st, (const double*)part, kRedBlocks,
+                       part + kChkState, (double)step);
+    return hipGetLastError();
+}
+
 // The state of a ready problem into U, V, W (the bound leading dimensions):
 // the pass that ended the last step is run again in its final form.  Its
 // inputs are still in the workspace (that pass wrote the other ping-pong
@@ -741,10 +821,10 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
     }
     if (!pb->ready) rc = adi::run_begin<T>(pb, pb->st);
     if (rc != ADI_OK) return rc;
-    for (int64_t s = 0; s < nsteps; ++s)
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const bool fin = tested && s == nsteps - 1;
         for (int half = 0; half < 2; ++half) {
-            const bool fin = tested && half == 1 && s == nsteps - 1;
-            const auto d = adi::run_pass<T>(pb, s, half, fin, nullptr);
+            const auto d = adi::run_pass<T>(pb, s, half, fin && half == 1, nullptr);
             if (pb->p.sweeps == 0)
                 HIP_TRY(launch_direct_pass<T>(pb, d), half == 0 ? "first direct pass" : "second direct pass");
             else if (tested)
@@ -752,18 +832,40 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
             else
                 HIP_TRY(adi::launch_pass<T>(d, pb->st), half == 0 ? "first line pass" : "second line pass");
         }
+        const int64_t m = pb->step + s + 1;
+        if (pb->chk_every > 0 && m % pb->chk_every == 0) {
+            // the pressure of the new level: the hand-off the step left for
+            // the next one, or U itself after a final pass
+            if (fin) {
+                int64_t rows[3], cols[3];
+                state_shapes(pb->p, rows, cols);
+                HIP_TRY(launch_health<T>(pb, (const T*)pb->U, (rows[0] - 1) * pb->ldU + cols[0], m), "health check");
+            } else {
+                const auto& D = pb->d[1 - last_dir(pb->p)];
+                HIP_TRY(launch_health<T>(pb, (const T*)D.P, D.rows_p * D.ld, m), "health check");
+            }
+        }
+    }
     if (tested) return adi::run_end<T>(pb, pb->st, nsteps);
     adi::run_advance(pb, nsteps);
     return ADI_OK;
 }
 
-// rows x cols of U, V, W
-void state_shapes(const adi_params& p, int64_t rows[3], int64_t cols[3]) {
-    const bool cfd = p.method == ADI_CFD;
-    rows[0] = cfd ? p.ny + 1 : p.ny + 2; cols[0] = cfd ? p.nx + 1 : p.nx + 2;
-    rows[1] = cfd ? p.ny + 1 : p.ny + 2; cols[1] = p.nx + 1;
-    rows[2] = p.ny + 1;                  cols[2] = cfd ? p.nx + 1 : p.nx + 2;
+// ADI_ENUMERIC when the health check has seen a non-finite value or a
+// magnitude above its bound (after the problem's stream has drained).
+int health_status(adi_problem* pb) {
+    if (pb->chk_every <= 0) return ADI_OK;
+    double st[4];
+    HIP_TRY(hipMemcpy(st, (double*)(pb->ws + layout(*pb).chk_off) + kChkState, sizeof(st), hipMemcpyDeviceToHost),
+            "health check state");
+    if (st[0] > 0.0)
+        return fail(ADI_ENUMERIC, "non-finite values in the state at step %lld", (long long)st[2] - 1);
+    if (pb->chk_max > 0.0 && st[1] > pb->chk_max)
+        return fail(ADI_ENUMERIC, "largest pressure magnitude %.6g above the bound %.6g (checked at step %lld)", st[1],
+                    pb->chk_max, (long long)st[3]);
+    return ADI_OK;
 }
+
 
 }  // namespace
 
@@ -1077,7 +1179,7 @@ int adi_get_state(adi_problem* pb, void* U, void* V, void* W) {
     const int rc = adi::materialize(pb, U ? U : pb->U, V ? V : pb->V, W ? W : pb->W);
     if (rc != ADI_OK) return rc;
     HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
-    return ADI_OK;
+    return health_status(pb);
 }
 
 int adi_sync(adi_problem* pb) {
@@ -1085,6 +1187,38 @@ int adi_sync(adi_problem* pb) {
     if (!pb) return fail(ADI_EINVAL, "problem is NULL");
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
     HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    return pb->bound ? health_status(pb) : ADI_OK;
+}
+
+int adi_set_check(adi_problem* pb, int64_t every, double max_abs) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!pb->bound) return fail(ADI_ENOTREADY, "problem has no bound arrays");
+    if (every < 0) return fail(ADI_EINVAL, "every must be >= 0");
+    if (!(max_abs >= 0.0)) return fail(ADI_EINVAL, "max_abs must be >= 0");
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    // clear the running state (queued after earlier work on the stream)
+    const Layout L = layout(*pb);
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, pb->st, (uint4*)(pb->ws + L.chk_off), (L.total - L.chk_off) / 16);
+    HIP_TRY(hipGetLastError(), "health check reset");
+    pb->chk_every = every;
+    pb->chk_max = max_abs;
+    return ADI_OK;
+}
+
+int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite) {
+    g_err.clear();
+    if (!pb || !max_abs || !nonfinite) return fail(ADI_EINVAL, "NULL argument");
+    *max_abs = 0.0;
+    *nonfinite = 0;
+    if (!pb->bound) return fail(ADI_ENOTREADY, "problem has no bound arrays");
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    double st[4];
+    HIP_TRY(hipMemcpy(st, (double*)(pb->ws + layout(*pb).chk_off) + kChkState, sizeof(st), hipMemcpyDeviceToHost),
+            "health check state");
+    *max_abs = st[1];
+    *nonfinite = st[0] > 0.0 ? 1 : 0;
     return ADI_OK;
 }
 

@@ -92,6 +92,10 @@ struct adi_problem {
     double eps = 0.0;
     int eps_kmin = 0;
     void* eps_buf = nullptr;
+    // health check (adi_set_check): every chk_every steps, largest pressure
+    // magnitude allowed (0: non-finite values only); state in the workspace
+    int64_t chk_every = 0;
+    double chk_max = 0.0;
     // factor store of the direct solves (sweeps 0) and the constant
     // materials {a kappa0, a rinv0} they read when K or R is absent, both
     // part of the workspace

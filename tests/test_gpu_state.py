@@ -178,3 +178,37 @@ def test_held_requests_fetched_once():
     for a, b in zip(copy, plain):
         assert np.array_equal(a, b)
     srv.close()
+
+
+def test_health_check_flags_growth_and_nonfinite_values():
+    """adi_set_check: a healthy run passes and reports its largest pressure
+    magnitude; the compact scheme's growing boundary modes on the layered
+    workload (1024^2 FP32, 1500 steps: the field grows to about 1e8) trip a
+    magnitude bound; a non-finite value in the initial state trips the check
+    at the first step.  No host synchronisation happens between checks."""
+    pr = inputs.seismic_problem(adi.CFD, 1024, seed=0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float32)
+    U, V, W, K = t(pr["U"]), t(pr["V"]), t(pr["W"]), t(pr["K"])
+    p = adi.make_params(adi.CFD, adi.FP32, 1024, 1024, pr["h"], pr["dt"], pr["cmax"], src=pr["src"])
+    log("case health check: healthy 100 steps, then 1400 more with a bound of 1e3")
+    pb = adi.Problem(p).bind(U, V, W, K).set_check(10, 1e3)
+    pb.run(100)
+    pb.get_state()
+    m, nf = pb.check_stats()
+    assert 0.0 < m < 1.0 and not nf, (m, nf)
+    pb.run(1400)
+    with pytest.raises(adi.AdiError, match="above the bound") as ei:
+        pb.sync()
+    assert ei.value.code == -6
+    m, nf = pb.check_stats()
+    assert m > 1e3 and not nf, (m, nf)
+    pb.close()
+    log("case health check: NaN in the initial pressure")
+    U0 = t(pr["U"])
+    U0[512, 512] = float("nan")
+    pb = adi.Problem(p).bind(U0, t(pr["V"]), t(pr["W"]), K).set_check(1)
+    pb.run(3)
+    with pytest.raises(adi.AdiError, match="non-finite values in the state at step 1"):
+        pb.get_state()
+    assert pb.check_stats()[1]
+    pb.close()
