@@ -94,6 +94,16 @@ typedef struct adi_params {
 
 typedef struct adi_problem adi_problem;
 
+/* A time signal s(t): ADI_SIGNAL_RICKER amp (1 - 2 x^2) exp(-x^2) with
+ * x = pi f0 (t - t0); ADI_SIGNAL_COS amp cos(2 pi f0 (t - t0)) (f0 = 0: the
+ * constant amp). */
+enum { ADI_SIGNAL_RICKER = 1, ADI_SIGNAL_COS = 2 };
+typedef struct adi_signal {
+    int32_t kind;
+    int32_t reserved0;
+    double f0, t0, amp;
+} adi_signal;
+
 /* Human-readable name of a status code (static storage). */
 const char* adi_status_string(int status);
 
@@ -116,6 +126,36 @@ const char* adi_last_error(void);
  * slot.  Scope: ADI_FP32 and ADI_FP64, single problems; adi_create rejects
  * ADI_FP32C and step sizes whose margin exceeds 4096 slots, and batches,
  * servers and adi_set_tolerance refuse such problems (ADI_EINVAL). */
+
+/* Distributed forcing and Dirichlet data that vary in time (the
+ * heterogeneous tests of Section 4, eq. harmonic_hetero, which need both).
+ * Call after adi_create and before adi_bind; both are read at adi_bind.
+ *
+ * adi_set_forcing: f(x, y, t) = F(x, y) s(t) at every interior pressure
+ * point, in addition to the point source: F^m enters the first stage of a
+ * step and F^{m+1} the second, as in eqs. ecua2:PR and ecua3:PR2.  F is a
+ * device array shaped like U (leading dimension ldF, 0 = dense), read by
+ * adi_bind; NULL removes the forcing.  Costs one more array read per pass.
+ *
+ * adi_set_boundary: the pressure on the walls is u = Ub(x, y) s(t), Ub the
+ * wall entries of the U bound by adi_bind (so at t = 0, s(0) = 1 gives back
+ * the initial data); s = NULL restores homogeneous walls.  The paper does
+ * not say which wall values the intermediate level of the split carries;
+ * this library uses the pressure component of the split's own identity
+ * U* = (I + a A2) U^m / 2 + (I - a A2) U^{m+1} / 2 + a (F^m - F^{m+1}) / 2
+ * on the wall data, i.e. (u_b^m + u_b^{m+1}) / 2 - a^2 c^2 d_ll u_b(t^m +
+ * dt/2) + a (f^m - f^{m+1}) / 2 with d_ll the second difference along the
+ * wall and c^2 = kappa / rho at the wall point; the other stages see the
+ * walls at t^m and t^{m+1}.  This keeps the time error second order (the
+ * mid-step wall value alone converges at first order).
+ *
+ * Scope: fixed sweep counts (ADI_EINVAL with sweeps 0), single problems
+ * (batches refuse them).  Settings take effect at the next adi_bind; the
+ * workspace then holds the forcing field in both line layouts and six
+ * values per line, beyond what adi_workspace_size reports (pass no
+ * workspace to adi_bind, or a larger one: adi_bind names the size it needs). */
+int adi_set_forcing(adi_problem* pb, const void* F, int64_t ldF, const adi_signal* s);
+int adi_set_boundary(adi_problem* pb, const adi_signal* s);
 
 /* Fill *p with defaults: CFD, FP32, order 0, 6 sweeps, no source,
  * kappa0 = rinv0 = 1, struct_size set.  Sizes, h, dt, c_max left zero. */

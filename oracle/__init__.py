@@ -73,6 +73,10 @@ def _load():
         lib.oracle_run_eps.restype = ctypes.c_int
         lib.oracle_run_direct.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64]
         lib.oracle_run_direct.restype = ctypes.c_int
+        sp = ctypes.POINTER(_Signal)
+        lib.oracle_run_forced.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64, dp, sp,
+                                          sp]
+        lib.oracle_run_forced.restype = ctypes.c_int
         lib.oracle_source.argtypes = [ctypes.POINTER(_Params), ctypes.c_double]
         lib.oracle_source.restype = ctypes.c_double
         for name in ("oracle_cfd_d", "oracle_cfd_dbar", "oracle_mfd_g", "oracle_mfd_d"):
@@ -194,6 +198,47 @@ def run_direct(method, U, V, W, *, h, dt, nsteps, K=None, Rv=None, Rw=None, orde
                                    _ptr(K), _ptr(Rv), _ptr(Rw), int(nsteps))
     if rc != 0:
         raise ValueError("oracle_run_direct rejected its arguments")
+    return U, V, W
+
+
+class _Signal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32), ("f0", ctypes.c_double),
+                ("t0", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+SIGNAL_RICKER, SIGNAL_COS = 1, 2
+
+
+def _signal(g):
+    if g is None:
+        return None
+    s = _Signal()
+    s.kind, s.f0, s.t0, s.amp = int(g["kind"]), float(g["f0"]), float(g.get("t0", 0.0)), float(g.get("amp", 1.0))
+    return ctypes.byref(s)
+
+
+def run_forced(method, U, V, W, *, h, dt, nsteps, sweeps=6, K=None, Rv=None, Rw=None, order=0, src=None,
+               t0=0.0, kappa0=1.0, rinv0=1.0, threads=0, F=None, fsig=None, bsig=None):
+    """As :func:`run` (or :func:`run_direct` with sweeps=0) with a
+    distributed forcing f = F(x, y) s_F(t) (F pressure-shaped, fsig the
+    signal dict: kind 1 Ricker / 2 cosine amp cos(2 pi f0 (t - t0)), f0, t0,
+    amp) and, when bsig is given, Dirichlet wall values equal to U's entries
+    on the walls times s_b(t)."""
+    ny = U.shape[0] - (1 if method == CFD else 2)
+    nx = U.shape[1] - (1 if method == CFD else 2)
+    sh = shapes(method, nx, ny)
+    U = _f64(U, sh["U"], "U").copy()
+    V = _f64(V, sh["V"], "V").copy()
+    W = _f64(W, sh["W"], "W").copy()
+    K = None if K is None else _f64(K, sh["K"], "K")
+    Rv = None if Rv is None else _f64(Rv, sh["Rv"], "Rv")
+    Rw = None if Rw is None else _f64(Rw, sh["Rw"], "Rw")
+    F = None if F is None else _f64(F, sh["U"], "F")
+    p = make_params(method, nx, ny, h, dt, sweeps, order, src, t0, kappa0, rinv0, threads)
+    rc = _load().oracle_run_forced(ctypes.byref(p), _ptr(U), _ptr(V), _ptr(W), _ptr(K), _ptr(Rv), _ptr(Rw),
+                                   int(nsteps), _ptr(F), _signal(fsig), _signal(bsig))
+    if rc != 0:
+        raise ValueError("oracle_run_forced rejected its arguments")
     return U, V, W
 
 

@@ -59,7 +59,25 @@
  *   - direct mode (oracle_run_direct): each stage's line systems solved
  *     exactly, the limit of infinitely many sweeps, which is the
  *     Peaceman-Rachford step itself (eqs. ecua2:PR, ecua3:PR2) with no
- *     fixed-point error and no step-size limit from the iteration.
+ *     fixed-point error and no step-size limit from the iteration;
+ *   - time-dependent Dirichlet data and a distributed forcing
+ *     (oracle_run_forced; the heterogeneous tests of Section 4, eq.
+ *     harmonic_hetero): u = Ub(x, y) s_b(t) on the walls, f = F(x, y) s_F(t)
+ *     in the interior.  The paper does not say which wall values the
+ *     intermediate level U* carries.  Reading taken: the explicit part of the
+ *     first stage reads the walls along its lines at t^m, the implicit part
+ *     of the second stage at t^{m+1}; the walls across the first stage's
+ *     lines (x = 0, 1 in order 0) carry the pressure component of the
+ *     split's own identity for the intermediate level,
+ *       U* = (1/2)(I + a A2) U^m + (1/2)(I - a A2) U^{m+1} + (a/2)(F^m - F^{m+1}),
+ *     evaluated on the wall data: with rho w_t = -u_y the A2 terms become
+ *     -a^2 c^2 d_yy u_b at t^m + dt/2 (d_yy the second difference along the
+ *     wall, c^2 = kappa / rho at the wall point), so
+ *       U*_wall = (u_b^m + u_b^{m+1}) / 2 - a^2 c^2 d_yy u_b(t^m + dt/2)
+ *                 + (a/2)(f^m - f^{m+1}).
+ *     Without the last two terms the wall values are off by O(dt^2) each
+ *     step and the error converges at first order only.  F^m enters the
+ *     first stage and F^{m+1} the second, as the point source does.
  *
  * Built with -O2 -ffp-contract=off and no fast-math so every operation is
  * rounded as written.
@@ -75,6 +93,13 @@
 
 #define ORC_CFD 0
 #define ORC_MFD 1
+
+/* A time signal: kind 1 Ricker amp (1 - 2 x^2) exp(-x^2), x = pi f0 (t - t0);
+ * kind 2 cosine amp cos(2 pi f0 (t - t0)); kind 0 zero. */
+typedef struct {
+    int32_t kind, pad;
+    double f0, t0, amp;
+} oracle_signal;
 
 typedef struct {
     int32_t method;   /* 0 = CFD, 1 = MFD */
@@ -330,8 +355,8 @@ typedef struct {
 static void implicit_eps(problem* pb, int d, int sweeps, int nthreads, double eps, int min_sweeps, int32_t* used);
 static void implicit_direct(problem* pb, int d, int nthreads);
 
-static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads, double eps, int min_sweeps,
-                  int32_t* used) {
+static void stage(problem* pb, int d, double Fsrc, const double* Ffield, double Fscale, int sweeps,
+                  int nthreads, double eps, int min_sweeps, int32_t* used) {
     const int e = 1 - d;
     const int method = pb->method;
     const double a = pb->a;
@@ -366,6 +391,7 @@ static void stage(problem* pb, int d, double Fsrc, int sweeps, int nthreads, dou
                 double kap = mat(&pb->K, e, l, k, pb->kappa0);
                 int j = e == 0 ? l : k, i = e == 0 ? k : l;
                 double f = (i == pb->src_i && j == pb->src_j) ? Fsrc : 0.0;
+                if (Ffield) f += Fscale * Ffield[(size_t)j * pb->U.cols + i];
                 RU_AT(j - 1, i - 1) = *at(&pb->U, e, l, k) - a * (kap * tmp[k - 1] - f);
             }
             /* vel_e <- vel_e - a R_e .* G_e(U) (full pressure line) */
@@ -622,9 +648,66 @@ static int check_params(const oracle_params* p) {
     return 0;
 }
 
+static double signal(const oracle_signal* g, double t) {
+    const double pi = 3.14159265358979323846;
+    if (!g || g->kind == 0) return 0.0;
+    if (g->kind == 1) return ricker(t, g->f0, g->t0, g->amp);
+    return g->amp * cos(2.0 * pi * g->f0 * (t - g->t0));
+}
+
+/* Wall values of U: the walls across the lines of direction d (the two
+ * ends of every interior line along d) set to Ub times the boundary signal
+ * at time t. */
+static void set_walls(problem* pb, int d, const double* Ub, const oracle_signal* bs, double t) {
+    const double sc = signal(bs, t);
+    const int nd = d == 0 ? pb->nx : pb->ny, ne = d == 0 ? pb->ny : pb->nx;
+    const int last = n_ufull(pb->method, nd) - 1;
+    for (int l = 1; l <= n_uint(pb->method, ne); ++l) {
+        double* a = at(&pb->U, d, l, 0);
+        double* b = at(&pb->U, d, l, last);
+        *a = sc * Ub[a - pb->U.p];
+        *b = sc * Ub[b - pb->U.p];
+    }
+}
+
+/* Coordinate of pressure index k along a direction of n cells. */
+static double pcoord(int method, int n, double h, int k) {
+    if (method == ORC_CFD) return k * h;
+    return k == 0 ? 0.0 : (k == n + 1 ? n * h : (k - 0.5) * h);
+}
+
+/* The intermediate level's wall values across the lines of direction d (the
+ * reading in the header): for each interior line l along d and each of its
+ * two wall points, (u_b^m + u_b^{m+1})/2 - a^2 c^2 d_ll u_b(t_half) +
+ * (a/2)(f^m - f^{m+1}), d_ll the three-point second difference along the
+ * wall (across the lines), c^2 = kappa * (1/rho of the velocity along d at
+ * that point). */
+static void set_walls_half(problem* pb, int d, const double* Ub, const double* F, const oracle_signal* bs,
+                           const oracle_signal* fs, double tm, double dt) {
+    const int m = pb->method;
+    const int nd = d == 0 ? pb->nx : pb->ny, ne = d == 0 ? pb->ny : pb->nx;
+    const int last = n_ufull(m, nd) - 1;
+    const double a = pb->a;
+    const double sav = 0.5 * (signal(bs, tm) + signal(bs, tm + dt)), shalf = signal(bs, tm + 0.5 * dt);
+    const double fdif = F ? 0.5 * a * (signal(fs, tm) - signal(fs, tm + dt)) : 0.0;
+    const field* R = d == 0 ? &pb->Rv : &pb->Rw;
+    for (int l = 1; l <= n_uint(m, ne); ++l) {
+        const double ym = pcoord(m, ne, pb->h, l - 1), y0 = pcoord(m, ne, pb->h, l), yp = pcoord(m, ne, pb->h, l + 1);
+        for (int e = 0; e < 2; ++e) {
+            const int k = e ? last : 0;
+            double* u = at(&pb->U, d, l, k);
+            const size_t o = (size_t)(u - pb->U.p);
+            const double um = Ub[at(&pb->U, d, l - 1, k) - pb->U.p], u0 = Ub[o], up = Ub[at(&pb->U, d, l + 1, k) - pb->U.p];
+            const double dll = 2.0 * ((up - u0) / (yp - y0) - (u0 - um) / (y0 - ym)) / (yp - ym);
+            const double c2 = mat(&pb->K, d, l, k, pb->kappa0) * mat(R, d, l, (e && m == ORC_MFD) ? k - 1 : k, pb->rinv0);
+            *u = sav * u0 - a * a * c2 * dll * shalf + (F ? fdif * F[o] : 0.0);
+        }
+    }
+}
+
 static int run_impl(const oracle_params* p, double* U, double* V, double* W, const double* K,
                     const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
-                    int32_t* used) {
+                    int32_t* used, const double* F, const oracle_signal* fs, const oracle_signal* bs) {
     if (check_params(p) || !U || !V || !W || nsteps < 0) return -1;
     problem pb;
     memset(&pb, 0, sizeof(pb));
@@ -655,20 +738,30 @@ static int run_impl(const oracle_params* p, double* U, double* V, double* W, con
 #endif
     const double h2 = p->h * p->h;
     const int has_src = p->src_i >= 0 && p->src_j >= 0;
+    /* wall values at t = 0 scale the boundary signal */
+    double* Ub = NULL;
+    if (bs) {
+        const size_t nu = (size_t)pb.U.rows * pb.U.cols;
+        Ub = malloc(nu * sizeof(double));
+        memcpy(Ub, U, nu * sizeof(double));
+    }
+    const int d1 = p->order == 0 ? 0 : 1, d2 = 1 - d1;   /* implicit directions of the two stages */
     for (int64_t s = 0; s < nsteps; ++s) {
         double tm = p->t0 + (double)s * p->dt, tm1 = p->t0 + (double)(s + 1) * p->dt;
         double Fm = has_src ? ricker(tm, p->src_f0, p->src_t0, p->src_amp) / h2 : 0.0;
         double Fm1 = has_src ? ricker(tm1, p->src_f0, p->src_t0, p->src_amp) / h2 : 0.0;
         int32_t* u0 = used ? used + 2 * s : NULL;
         int32_t* u1 = used ? used + 2 * s + 1 : NULL;
-        if (p->order == 0) {
-            stage(&pb, 0, Fm, p->sweeps, nthreads, eps, min_sweeps, u0);
-            stage(&pb, 1, Fm1, p->sweeps, nthreads, eps, min_sweeps, u1);
-        } else {
-            stage(&pb, 1, Fm, p->sweeps, nthreads, eps, min_sweeps, u0);
-            stage(&pb, 0, Fm1, p->sweeps, nthreads, eps, min_sweeps, u1);
+        if (Ub) {
+            set_walls(&pb, d2, Ub, bs, tm);                    /* read by the first explicit part */
+            set_walls_half(&pb, d1, Ub, F, bs, fs, tm, p->dt); /* the intermediate level */
         }
+        stage(&pb, d1, Fm, F, signal(fs, tm), p->sweeps, nthreads, eps, min_sweeps, u0);
+        if (Ub) set_walls(&pb, d2, Ub, bs, tm1);
+        stage(&pb, d2, Fm1, F, signal(fs, tm1), p->sweeps, nthreads, eps, min_sweeps, u1);
+        if (Ub) set_walls(&pb, d1, Ub, bs, tm1);               /* U^{m+1} whole */
     }
+    free(Ub);
     free(pb.RU);
     line_ops_free(&pb.ox);
     line_ops_free(&pb.oy);
@@ -681,7 +774,20 @@ static int run_impl(const oracle_params* p, double* U, double* V, double* W, con
 int oracle_run(const oracle_params* p, double* U, double* V, double* W,
                const double* K, const double* Rv, const double* Rw, int64_t nsteps) {
     if (!p || p->sweeps < 1) return -1;
-    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL);
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL);
+}
+
+/* As oracle_run (sweeps >= 1) or oracle_run_direct (sweeps 0), with a
+ * distributed forcing F (pressure-shaped; NULL = none) times the signal fs,
+ * and, when bs is given, Dirichlet wall values equal to the entries of U on
+ * the walls at the call times the signal bs (see the reading in the
+ * header).  Returns 0 or -1. */
+int oracle_run_forced(const oracle_params* p, double* U, double* V, double* W, const double* K,
+                      const double* Rv, const double* Rw, int64_t nsteps, const double* F,
+                      const oracle_signal* fs, const oracle_signal* bs) {
+    if (!p || p->sweeps < 0) return -1;
+    if (F && !fs) return -1;
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, F, fs, bs);
 }
 
 /* As oracle_run, with the tolerance test: eps > 0, min_sweeps even in
@@ -691,7 +797,7 @@ int oracle_run_eps(const oracle_params* p, double* U, double* V, double* W, cons
                    const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
                    int32_t* used) {
     if (!(eps > 0.0) || min_sweeps < 2 || (min_sweeps & 1) || !p || min_sweeps > p->sweeps) return -1;
-    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used);
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used, NULL, NULL, NULL);
 }
 
 /* As oracle_run with every stage's line systems solved exactly (the limit
@@ -701,7 +807,7 @@ int oracle_run_direct(const oracle_params* p, double* U, double* V, double* W, c
     if (!p) return -1;
     oracle_params q = *p;
     q.sweeps = 0;
-    return run_impl(&q, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL);
+    return run_impl(&q, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL);
 }
 
 /* Ricker source value F(t) = s(t) / h^2 as the oracle applies it. */

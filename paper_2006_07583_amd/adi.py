@@ -21,6 +21,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
            "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_check", "adi_check_stats",
+           "adi_set_forcing", "adi_set_boundary",
            "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
@@ -41,6 +42,20 @@ class AdiParams(ctypes.Structure):
         ("c_max", ctypes.c_double), ("kappa0", ctypes.c_double), ("rinv0", ctypes.c_double),
         ("src_f0", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_amp", ctypes.c_double),
     ]
+
+
+class AdiSignal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("f0", ctypes.c_double),
+                ("t0", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+SIGNAL_RICKER, SIGNAL_COS = 1, 2
+
+
+def _signal(g):
+    s = AdiSignal()
+    s.kind, s.f0, s.t0, s.amp = int(g["kind"]), float(g["f0"]), float(g.get("t0", 0.0)), float(g.get("amp", 1.0))
+    return s
 
 
 class AdiServerParams(ctypes.Structure):
@@ -93,6 +108,8 @@ def lib():
         L.adi_sync.argtypes = [vp]
         L.adi_get_state.argtypes = [vp, vp, vp, vp]
         L.adi_set_check.argtypes = [vp, i64, ctypes.c_double]
+        L.adi_set_forcing.argtypes = [vp, vp, i64, ctypes.POINTER(AdiSignal)]
+        L.adi_set_boundary.argtypes = [vp, ctypes.POINTER(AdiSignal)]
         L.adi_check_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
@@ -186,6 +203,28 @@ class Problem:
         _check(lib().adi_create(ctypes.byref(params), ctypes.c_void_p(stream.cuda_stream),
                                 ctypes.byref(self._h)))
         self._keep = ()
+
+    def set_forcing(self, F, signal) -> "Problem":
+        """adi_set_forcing (before bind): f = F(x, y) s(t), F a device tensor
+        shaped like U, signal a dict (kind 1 Ricker / 2 cosine, f0, t0, amp);
+        F None removes it."""
+        if F is None:
+            _check(lib().adi_set_forcing(self._h, None, 0, None))
+            self._force = None
+            return self
+        if F.dim() != 2 or F.stride(1) != 1:
+            raise ValueError("F must be 2-D with contiguous rows")
+        s = _signal(signal)
+        _check(lib().adi_set_forcing(self._h, _dptr(F), F.stride(0), ctypes.byref(s)))
+        self._force = F
+        return self
+
+    def set_boundary(self, signal) -> "Problem":
+        """adi_set_boundary (before bind): wall pressure = (U's wall entries
+        at bind) x s(t); None restores homogeneous walls."""
+        s = None if signal is None else _signal(signal)
+        _check(lib().adi_set_boundary(self._h, None if s is None else ctypes.byref(s)))
+        return self
 
     def bind(self, U, V, W, K=None, Rv=None, Rw=None, workspace=None):
         arrs = (U, V, W, K, Rv, Rw)

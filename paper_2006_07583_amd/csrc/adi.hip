@@ -156,14 +156,23 @@ double ricker(const adi_params& p, double t) {
     return p.src_amp * (1.0 - 2.0 * x2) * std::exp(-x2);
 }
 
+double signal_at(const adi_signal& g, double t) {
+    if (g.kind == ADI_SIGNAL_RICKER) {
+        const double x = kPi * g.f0 * (t - g.t0);
+        return g.amp * (1.0 - 2.0 * x * x) * std::exp(-x * x);
+    }
+    if (g.kind == ADI_SIGNAL_COS) return g.amp * std::cos(2.0 * kPi * g.f0 * (t - g.t0));
+    return 0.0;
+}
+
 }  // namespace
 
 namespace {
 
 // Workspace regions of one direction: P, V0, V1, K, R, Plo, V0lo, V1lo, coef,
-// Vs, Vslo.
+// Vs, Vslo, FF (forcing field), BND (wall coefficients).
 struct Layout {
-    size_t off[2][11];
+    size_t off[2][13];
     size_t fs_off;    // factor store of the direct solves (shared by both directions)
     size_t dc_off;    // their constant materials
     size_t red_off;   // per-block partial maxima of the material check at bind
@@ -192,10 +201,11 @@ Layout layout(const adi_problem& pb) {
         // the final re-run of adi_get_state writes its velocity here unless it
         // can go straight into the target (slot-major column passes)
         const bool spare = d == last_dir(p) && (d == 0 || D.lm);
-        const size_t sizes[11] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
+        const size_t sizes[13] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
                                   comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : 0,
-                                  spare ? ve : 0, spare && comp ? ve : 0};
-        for (int i = 0; i < 11; ++i) {
+                                  spare ? ve : 0, spare && comp ? ve : 0, pb.fsig.kind ? pe : 0,
+                                  pb.bsig.kind ? (size_t)6 * (pl.nlines + 64) : 0};
+        for (int i = 0; i < 13; ++i) {
             L.off[d][i] = cur;
             cur += (sizes[i] * pb.esz + 255) / 256 * 256;
         }
@@ -413,9 +423,36 @@ hipError_t zero_lo(const adi_problem* pb, int d, T* lo, bool ptype, hipStream_t 
 
 // Pass along x (dir 0: lines = interior rows) or along y (dir 1: lines =
 // interior columns); the materials come from the direction's arrays.
+// Per-pass scalars of the wall values and the distributed forcing for step
+// m: level 0 (walls at t^m, forcing F^m: the explicit pass of step m and the
+// final form of the pass that ended step m - 1), 1 (the intermediate walls
+// of step m -> m + 1, forcing F^{m+1}: the first pass of step m), 2 (walls
+// at t^{m+1}, forcing F^{m+1}: the second pass).
+struct PassScalars {
+    double bsc[3] = {0.0, 0.0, 0.0};
+    double aFf = 0.0;
+};
+PassScalars pass_scalars(const adi_problem& pb, int64_t m, int level) {
+    PassScalars r;
+    const auto& p = pb.p;
+    const double tm = p.t0 + (double)m * p.dt, tm1 = tm + p.dt;
+    if (pb.fsig.kind) r.aFf = pb.a * signal_at(pb.fsig, level == 0 ? tm : tm1);
+    if (pb.bsig.kind) {
+        if (level == 1) {
+            r.bsc[0] = 0.5 * (signal_at(pb.bsig, tm) + signal_at(pb.bsig, tm1));
+            r.bsc[1] = -pb.a * pb.a * signal_at(pb.bsig, tm + 0.5 * p.dt);
+            r.bsc[2] = pb.fsig.kind ? 0.5 * pb.a * (signal_at(pb.fsig, tm) - signal_at(pb.fsig, tm1)) : 0.0;
+        } else {
+            r.bsc[0] = signal_at(pb.bsig, level == 0 ? tm : tm1);
+        }
+    }
+    return r;
+}
+
 template <typename T>
 adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, const Buf<T>& vin,
-                           const Buf<T>& vout, const Buf<T>& uout, int utrans, T f, const T* aFtab, int mode) {
+                           const Buf<T>& vout, const Buf<T>& uout, int utrans, T f, const T* aFtab, int mode,
+                           const PassScalars& ps = PassScalars()) {
     const auto& p = pb->p;
     const Plan& pl = dir == 0 ? pb->px : pb->py;
     const auto& D = pb->d[dir];
@@ -429,6 +466,11 @@ adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, co
     a.vout = vout.hi; a.vout_lo = vout.lo; a.vout_ld = vout.ld;
     a.uout = uout.hi; a.uout_lo = uout.lo; a.uout_ld = uout.ld;
     a.utrans = utrans;
+    a.bnd = (const T*)D.BND;
+    for (int i = 0; i < 3; ++i) a.bsc[i] = (T)ps.bsc[i];
+    a.ff = (const T*)D.FF;
+    a.ff_ld = D.ld;
+    a.aFf = (T)ps.aFf;
     // the wave-per-line kernel writes the natural-layout pressure at
     // (s - 1) * ld + (q + 1): its base is one element lower
     if (pl.ver == 3 && utrans == 0) {
@@ -475,6 +517,7 @@ int run_begin(adi_problem* pb, hipStream_t st) {
     T* V = (T*)pb->V;
     T* W = (T*)pb->W;
     const T f0 = (T)source_term(*pb, pb->step);
+    const PassScalars ps = pass_scalars(*pb, pb->step, 0);
     int ut;
     // V -> velocity arrays of the x passes; low words start at zero
     HIP_TRY(vel_to_dir<T>(pb, 0, (T*)pb->d[0].V[pb->vcur], V, pb->ldV, T(1), st), "V in");
@@ -486,13 +529,13 @@ int run_begin(adi_problem* pb, hipStream_t st) {
             HIP_TRY(vel_to_dir<T>(pb, 1, (T*)pb->d[1].V[pb->wcur], W, pb->ldW, T(1), st), "W in");
             const Buf<T> out = pres_out<T>(pb, 1, ut);
             auto d = make_pass<T>(pb, 1, nolo(pres<T>(pb, 1)), nolo(vel<T>(pb, 1, pb->wcur)), vel<T>(pb, 1, 1 - pb->wcur),
-                                  out, ut, f0, nullptr, LINE_EXPLICIT);
+                                  out, ut, f0, nullptr, LINE_EXPLICIT, ps);
             HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
             pb->wcur ^= 1;
         } else {
             const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
             const Buf<T> out = pres_out<T>(pb, 1, ut);
-            auto d = make_pass<T>(pb, 1, Uu, Wu, vel<T>(pb, 1, pb->wcur), out, ut, f0, nullptr, LINE_EXPLICIT);
+            auto d = make_pass<T>(pb, 1, Uu, Wu, vel<T>(pb, 1, pb->wcur), out, ut, f0, nullptr, LINE_EXPLICIT, ps);
             HIP_TRY(launch_pass<T>(d, st), "explicit column pass");
         }
     } else {
@@ -503,7 +546,7 @@ int run_begin(adi_problem* pb, hipStream_t st) {
         if (comp) HIP_TRY(zero_lo<T>(pb, 1, (T*)pb->d[1].Vlo[pb->wcur], false, st), "zero W low words");
         const Buf<T> out = pres_out<T>(pb, 0, ut);
         auto d = make_pass<T>(pb, 0, nolo(pres<T>(pb, 0)), nolo(vel<T>(pb, 0, pb->vcur)), vel<T>(pb, 0, 1 - pb->vcur),
-                              out, ut, f0, nullptr, LINE_EXPLICIT);
+                              out, ut, f0, nullptr, LINE_EXPLICIT, ps);
         HIP_TRY(launch_pass<T>(d, st), "explicit row pass");
         pb->vcur ^= 1;
     }
@@ -515,6 +558,7 @@ template <typename T>
 PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, bool final_pass, const T* aFtab) {
     const bool last = final_pass;
     const T f1 = (T)source_term(*pb, pb->step + s + 1);
+    const PassScalars ps = pass_scalars(*pb, pb->step + s, half == 0 ? 1 : 2);
     T* U = (T*)pb->U;
     T* W = (T*)pb->W;
     int ut;
@@ -530,21 +574,21 @@ PassDesc<T> run_pass(adi_problem* pb, int64_t s, int half, bool final_pass, cons
         if (dir == 1) {
             const Buf<T> Uu{U + pb->ldU + 1, nullptr, pb->ldU}, Wu{W + 1, nullptr, pb->ldW};
             if (pb->d[1].lm) {
-                d = make_pass<T>(pb, 1, uin, vin, vout, Uu, 0, T(0), nullptr, LINE_FINAL);
+                d = make_pass<T>(pb, 1, uin, vin, vout, Uu, 0, T(0), nullptr, LINE_FINAL, ps);
                 cur ^= 1;
             } else {
-                d = make_pass<T>(pb, 1, uin, vin, Wu, Uu, 0, T(0), nullptr, LINE_FINAL);
+                d = make_pass<T>(pb, 1, uin, vin, Wu, Uu, 0, T(0), nullptr, LINE_FINAL, ps);
             }
         } else {
             const Buf<T> Ux{U + pb->ldU + 1, nullptr, pb->ldU};
-            d = make_pass<T>(pb, 0, uin, vin, vout, Ux, 1, T(0), nullptr, LINE_FINAL);
+            d = make_pass<T>(pb, 0, uin, vin, vout, Ux, 1, T(0), nullptr, LINE_FINAL, ps);
             cur ^= 1;
         }
         return d;
     }
     // sweeps of this stage, then the explicit part of the next stage
     const Buf<T> out = pres_out<T>(pb, dir, ut);
-    d = make_pass<T>(pb, dir, uin, vin, vout, out, ut, f1, aFtab, LINE_SWEEP);
+    d = make_pass<T>(pb, dir, uin, vin, vout, out, ut, f1, aFtab, LINE_SWEEP, ps);
     cur ^= 1;
     return d;
 }
@@ -796,7 +840,8 @@ int materialize_ready(adi_problem* pb, T* U, T* V, T* W) {
     const Buf<T> spare{(T*)D.Vs, (T*)D.Vslo, D.ld};
     const bool straight = dl == 1 && !D.lm;
     const Buf<T> vout = straight ? Buf<T>{W + 1, nullptr, pb->ldW} : spare;
-    const auto d = make_pass<T>(pb, dl, uin, vin, vout, Uu, dl == 0 ? 1 : 0, T(0), nullptr, adi::LINE_FINAL);
+    const auto d = make_pass<T>(pb, dl, uin, vin, vout, Uu, dl == 0 ? 1 : 0, T(0), nullptr, adi::LINE_FINAL,
+                                pass_scalars(*pb, pb->step, 0));
     if (pb->p.sweeps == 0)
         HIP_TRY(launch_direct_pass<T>(pb, d), "final direct pass");
     else
@@ -913,6 +958,81 @@ __global__ void __launch_bounds__(256) block_max_kernel(const T* __restrict__ x,
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// Pressure coordinate of index k along a direction of n cells.
+double pcoord(int method, int n, double h, int k) {
+    if (method == ADI_CFD) return k * h;
+    return k == 0 ? 0.0 : (k == n + 1 ? n * h : (k - 0.5) * h);
+}
+
+// Wall coefficients of the time-dependent Dirichlet data (adi_set_boundary),
+// per direction d and line q (interior index l = q + 1 across the lines),
+// at both ends: the wall value Ub, c^2 times its three-point second
+// difference along the wall (across the lines), and the forcing field's
+// value there.  Read from the bound U, the materials and the forcing field
+// (wall rows and columns only), computed in FP64, stored in the direction's
+// BND region.
+template <typename T>
+int wall_coefficients(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_t ldK, int64_t ldRv,
+                      int64_t ldRw) {
+    const auto& p = pb->p;
+    hipStream_t st = pb->st;
+    HIP_TRY(hipStreamSynchronize(st), "wall data");
+    const int m = p.method;
+    const int ru = m == ADI_CFD ? p.ny + 1 : p.ny + 2, cu = m == ADI_CFD ? p.nx + 1 : p.nx + 2;
+    // column c (all rows) / row r (all columns) of a device array
+    auto col = [&](const T* a, int64_t ld, int rows, int c, std::vector<double>& out) -> hipError_t {
+        std::vector<T> tmp(rows);
+        out.assign(rows, 0.0);
+        const hipError_t e = hipMemcpy2D(tmp.data(), sizeof(T), a + c, ld * sizeof(T), sizeof(T), rows,
+                                         hipMemcpyDeviceToHost);
+        for (int i = 0; i < rows; ++i) out[i] = (double)tmp[i];
+        return e;
+    };
+    auto row = [&](const T* a, int64_t ld, int cols, int r, std::vector<double>& out) -> hipError_t {
+        std::vector<T> tmp(cols);
+        out.assign(cols, 0.0);
+        const hipError_t e = hipMemcpy(tmp.data(), a + (int64_t)r * ld, cols * sizeof(T), hipMemcpyDeviceToHost);
+        for (int i = 0; i < cols; ++i) out[i] = (double)tmp[i];
+        return e;
+    };
+    const T* U = (const T*)pb->U;
+    const T* F = (const T*)pb->fF;
+    for (int d = 0; d < 2; ++d) {
+        const int nl = d == 0 ? pb->niy : pb->nix;           // lines
+        const int na = d == 0 ? p.ny : p.nx;                 // cells across the lines (along the walls)
+        const int ends[2] = {0, d == 0 ? cu - 1 : ru - 1};   // wall index along the lines
+        std::vector<double> coef((size_t)6 * nl, 0.0);
+        for (int e = 0; e < 2; ++e) {
+            std::vector<double> ub, kb, rb, fb;
+            const int w = ends[e];
+            const int wv = (e && m == ADI_MFD) ? w - 1 : w;  // the velocity point at the wall
+            if (d == 0) {
+                HIP_TRY(col(U, pb->ldU, ru, w, ub), "wall data");
+                if (K) HIP_TRY(col(K, ldK, ru, w, kb), "wall data");
+                if (Rv) HIP_TRY(col(Rv, ldRv, ru, wv, rb), "wall data");
+                if (F) HIP_TRY(col(F, pb->fF_ld, ru, w, fb), "wall data");
+            } else {
+                HIP_TRY(row(U, pb->ldU, cu, w, ub), "wall data");
+                if (K) HIP_TRY(row(K, ldK, cu, w, kb), "wall data");
+                if (Rw) HIP_TRY(row(Rw, ldRw, cu, wv, rb), "wall data");
+                if (F) HIP_TRY(row(F, pb->fF_ld, cu, w, fb), "wall data");
+            }
+            for (int q = 0; q < nl; ++q) {
+                const int l = q + 1;
+                const double ym = pcoord(m, na, p.h, l - 1), y0 = pcoord(m, na, p.h, l), yp = pcoord(m, na, p.h, l + 1);
+                const double dll = 2.0 * ((ub[l + 1] - ub[l]) / (yp - y0) - (ub[l] - ub[l - 1]) / (y0 - ym)) / (yp - ym);
+                const double c2 = (K ? kb[l] : p.kappa0) * (rb.empty() ? p.rinv0 : rb[l]);
+                coef[(size_t)6 * q + 3 * e] = ub[l];
+                coef[(size_t)6 * q + 3 * e + 1] = c2 * dll;
+                coef[(size_t)6 * q + 3 * e + 2] = F ? fb[l] : 0.0;
+            }
+        }
+        std::vector<T> ct(coef.begin(), coef.end());
+        HIP_TRY(hipMemcpy(pb->d[d].BND, ct.data(), ct.size() * sizeof(T), hipMemcpyHostToDevice), "wall coefficients");
+    }
+    return ADI_OK;
+}
+
 template <typename T>
 int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_t ldK, int64_t ldRv, int64_t ldRw) {
     const auto& p = pb->p;
@@ -935,6 +1055,14 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
         const int cnt = 6 * adi::line_ws(pl.cfg);
         for (int i = 0; i < cnt; ++i) tab[d][i] = (T)t64[i];
         HIP_TRY(hipMemcpyAsync(pb->d[d].coef, tab[d], cnt * sizeof(T), hipMemcpyHostToDevice, st), "factor tables");
+    }
+    // distributed forcing in both directions' layouts
+    if (pb->fsig.kind)
+        for (int d = 0; d < 2; ++d)
+            HIP_TRY(pres_to_dir<T>(pb, d, (T*)pb->d[d].FF, (const T*)pb->fF, pb->fF_ld, T(1), st), "forcing field");
+    if (pb->bsig.kind) {
+        const int rc = wall_coefficients<T>(pb, K, Rv, Rw, ldK, ldRv, ldRw);
+        if (rc != ADI_OK) return rc;
     }
     const T dconst[2] = {(T)(pb->a * p.kappa0), (T)(pb->a * p.rinv0)};
     if (pb->dconst)
@@ -1012,6 +1140,8 @@ void place(adi_problem* pb, const Layout& L, char* w) {
         D.coef = w + L.off[d][8];
         D.Vs = L.off[d][9] != L.off[d][10] ? w + L.off[d][9] : nullptr;
         D.Vslo = comp && D.Vs ? w + L.off[d][10] : nullptr;
+        D.FF = pb->fsig.kind ? w + L.off[d][11] : nullptr;
+        D.BND = pb->bsig.kind ? w + L.off[d][12] : nullptr;
     }
     pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
     pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
@@ -1056,6 +1186,43 @@ const char* adi_status_string(int status) {
 }
 
 const char* adi_last_error(void) { return g_err.c_str(); }
+
+int adi_set_forcing(adi_problem* pb, const void* F, int64_t ldF, const adi_signal* s) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!F) {
+        pb->set_fF = nullptr;
+        pb->set_fsig = adi_signal{};
+        return ADI_OK;
+    }
+    if (pb->p.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) take no distributed forcing");
+    if (!s || (s->kind != ADI_SIGNAL_RICKER && s->kind != ADI_SIGNAL_COS))
+        return fail(ADI_EINVAL, "forcing needs a Ricker or cosine signal");
+    if (!std::isfinite(s->f0) || !std::isfinite(s->t0) || !std::isfinite(s->amp))
+        return fail(ADI_EINVAL, "signal parameters must be finite");
+    const int64_t cu = pb->p.method == ADI_CFD ? pb->p.nx + 1 : pb->p.nx + 2;
+    if (ldF != 0 && ldF < cu) return fail(ADI_EINVAL, "ldF below the row length %lld", (long long)cu);
+    pb->set_fF = F;
+    pb->set_fF_ld = ldF ? ldF : cu;
+    pb->set_fsig = *s;
+    return ADI_OK;
+}
+
+int adi_set_boundary(adi_problem* pb, const adi_signal* s) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!s) {
+        pb->set_bsig = adi_signal{};
+        return ADI_OK;
+    }
+    if (pb->p.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) take homogeneous walls only");
+    if (s->kind != ADI_SIGNAL_RICKER && s->kind != ADI_SIGNAL_COS)
+        return fail(ADI_EINVAL, "wall data need a Ricker or cosine signal");
+    if (!std::isfinite(s->f0) || !std::isfinite(s->t0) || !std::isfinite(s->amp))
+        return fail(ADI_EINVAL, "signal parameters must be finite");
+    pb->set_bsig = *s;
+    return ADI_OK;
+}
 
 int adi_params_init(adi_params* p) {
     if (!p) return fail(ADI_EINVAL, "params is NULL");
@@ -1123,6 +1290,10 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->own_ws = false;
     }
     pb->bound = false;
+    pb->fF = pb->set_fF;
+    pb->fF_ld = pb->set_fF_ld;
+    pb->fsig = pb->set_fsig;
+    pb->bsig = pb->set_bsig;
     pb->hasK = K != nullptr;
     pb->hasRv = Rv != nullptr;
     pb->hasRw = Rw != nullptr;

@@ -322,6 +322,8 @@ int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, 
             return fail(ADI_EINVAL, "problem %d uses tolerance-tested stages, which batches do not run", i);
         if (pb->p.sweeps == 0)
             return fail(ADI_EINVAL, "problem %d uses direct solves (sweeps 0), which batches do not run", i);
+        if (pb->fsig.kind || pb->bsig.kind)
+            return fail(ADI_EINVAL, "problem %d has a forcing field or wall data, which batches do not run", i);
         for (int j = 0; j < i; ++j)
             if (problems[j] == pb) return fail(ADI_EINVAL, "problem %d appears twice", i);
     }

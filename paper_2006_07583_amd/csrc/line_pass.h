@@ -44,6 +44,16 @@ struct LinePassArgs {
     // |v_K - v_{K-1}|^2}, over the slots it writes at eps_part[q nlg nwin + tile]
     double* eps_part;
     const int* eps_go;
+    // Dirichlet wall values (NULL: zero walls).  For line q the value at its
+    // first pressure slot (0) is bnd[6q] bsc[0] + bnd[6q+1] bsc[1] +
+    // bnd[6q+2] bsc[2], at its last (n for CFD, n + 1 for MFD) the same with
+    // bnd[6q+3..6q+5].  Distributed forcing (NULL: none): aFf * ff at every
+    // interior pressure slot, added to the pressure output (ff laid out like
+    // ak).
+    const T* bnd;
+    T bsc[3];
+    const T* ff; int64_t ff_ld;
+    T aFf;
 };
 
 // A grouped launch: the passes items[0..nitems) (any problems, any

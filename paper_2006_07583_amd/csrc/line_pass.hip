@@ -361,12 +361,18 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
     }
 
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
+    // Dirichlet wall values at the first and last pressure slots of the line
+    T wl = T(0), wr = T(0);
+    if (a.bnd && qok) {
+        wl = a.bsc[0] * a.bnd[6 * q] + a.bsc[1] * a.bnd[6 * q + 1] + a.bsc[2] * a.bnd[6 * q + 2];
+        wr = a.bsc[0] * a.bnd[6 * q + 3] + a.bsc[1] * a.bnd[6 * q + 4] + a.bsc[2] * a.bnd[6 * q + 5];
+    }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int s = s0 + k;
         const bool uv = qok && s >= ulo && s <= uhi;
         const bool vv = qok && s <= vhi;
-        A[k] = uv ? a.uin[(int64_t)(s - 1) * a.uin_ld + q] : T(0);
+        A[k] = uv ? a.uin[(int64_t)(s - 1) * a.uin_ld + q] : (s == 0 ? wl : (s == uhi + 1 ? wr : T(0)));
         KK[k] = uv ? (a.ak ? a.ak[(int64_t)(s - 1) * a.ak_ld + q] : a.ak0) : T(0);
         B[k] = vv ? a.vin[(int64_t)s * a.vin_ld + q] : T(0);
         RR[k] = vv ? (a.ar ? a.ar[(int64_t)s * a.ar_ld + q] : a.ar0) : T(0);
@@ -425,6 +431,14 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
         }
     }
 
+    if (MODE != LINE_FINAL && a.ff) {
+        // distributed forcing on the interior pressure slots
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int s = s0 + k;
+            if (qok && s >= ulo && s <= uhi) U[k] = fma(a.aFf, a.ff[(int64_t)(s - 1) * a.ff_ld + q], U[k]);
+        }
+    }
     pass_outputs<T, R, LW, C::NT, P::TILEP, COMP>(a, smem, Tt, U, s0, q, qok, lq, lg, c0, c1, uhi, vhi,
                                                   tid, MODE != LINE_FINAL);
 }

@@ -491,6 +491,15 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         if (a.ak) stage_spread(ck, ek, KK);
         if (a.ar) stage_spread(cr, er, RR);
     }
+    // Dirichlet wall values: the first slot of the line (lane 0 of the first
+    // window, position 0) and its last (last lane of the last window,
+    // position R - 1); the material arrays are zero there, so the sweeps keep
+    // them
+    if (a.bnd && qok) {
+        if (L.bl) A[0] = a.bsc[0] * a.bnd[6 * q] + a.bsc[1] * a.bnd[6 * q + 1] + a.bsc[2] * a.bnd[6 * q + 2];
+        if (L.br)
+            A[R - 1] = a.bsc[0] * a.bnd[6 * q + 3] + a.bsc[1] * a.bnd[6 * q + 4] + a.bsc[2] * a.bnd[6 * q + 5];
+    }
     // scale folded into the material values (compact: 3 alpha / h; mimetic: 9 / (8 h))
     const T sc = METHOD == LINE_CFD ? T(3.0 * kAlpha) * a.inv_h : T(9.0 / 8.0) * a.inv_h;
     // The material arrays hold zeros outside the interior of the lines (slot
@@ -853,6 +862,15 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 #pragma unroll
             for (int k = 0; k < R; ++k)
                 if (k == ks) U[k] += a.aF;
+        }
+        if (a.ff) {
+            // distributed forcing (zero outside the interior, like the
+            // materials); KK is free after the last derivative
+            VT cf[CPT], ef{};
+            stage_in(a.ff, a.ff_ld, cf, ef);
+            stage_spread(cf, ef, KK);
+#pragma unroll
+            for (int k = 0; k < R; ++k) U[k] = fma(a.aFf, KK[k], U[k]);
         }
     }
     // velocity into the line-major output (central slots only)

@@ -83,6 +83,9 @@ struct adi_problem {
         // spare velocity buffer (and its low words) of the direction whose
         // pass ends a step: adi_get_state re-runs that pass into it
         void *Vs = nullptr, *Vslo = nullptr;
+        // forcing field in this direction's pressure layout; wall
+        // coefficients per line, {value, c^2 d_ll value, forcing} at each end
+        void *FF = nullptr, *BND = nullptr;
     } d[2];
     int vcur = 0, wcur = 0;
     adi::Plan px, py;
@@ -96,6 +99,17 @@ struct adi_problem {
     // magnitude allowed (0: non-finite values only); state in the workspace
     int64_t chk_every = 0;
     double chk_max = 0.0;
+    // distributed forcing F(x, y) s_F(t) and wall data Ub(x, y) s_b(t)
+    // (adi_set_forcing / adi_set_boundary); kind 0 = none.  The set_ values
+    // take effect at the next adi_bind.
+    const void* fF = nullptr;
+    int64_t fF_ld = 0;
+    adi_signal fsig{};
+    adi_signal bsig{};
+    const void* set_fF = nullptr;
+    int64_t set_fF_ld = 0;
+    adi_signal set_fsig{};
+    adi_signal set_bsig{};
     // factor store of the direct solves (sweeps 0) and the constant
     // materials {a kappa0, a rinv0} they read when K or R is absent, both
     // part of the workspace

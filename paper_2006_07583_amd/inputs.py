@@ -178,3 +178,66 @@ def serve_mix(seed: int = 0, count: int = 2000, rate: float = 200.0, lo: int = 1
                     "fp64": bool(rng.integers(0, 2)), "src_i": int(rng.integers(8, nx - 8 + 1)),
                     "src_j": int(rng.integers(8, ny - 8 + 1))})
     return out
+
+
+def hetero_solution(method: int, nx: int, ny: int, h: float, gamma: float, k: int, t: float,
+                    lam: float = 0.25, period: float = 1.0 / math.sqrt(2.0), rho: float = 1.0) -> dict:
+    """The exact solution of the heterogeneous test of Section 4 (eq.
+    harmonic_hetero) at time t, with c = 1 (kappa = rho):
+        u = phi(x, y) cos(w t),
+        phi = gamma (x^k - (1 - x)^k + y^k - (1 - y)^k) + sin(2 pi x / lam) sin(2 pi y / lam),
+    w = 2 pi / period, and the velocities that make it a solution of
+    rho v_t = -u_x, rho w_t = -u_y from zero at t = 0:
+        v = -phi_x sin(w t) / (rho w),  w_vel = -phi_y sin(w t) / (rho w),
+    at the method's pressure and velocity points.  gamma = 0 leaves the
+    sinusoid, which vanishes on the walls (homogeneous Dirichlet data)."""
+    om = 2.0 * math.pi / period
+    al = 2.0 * math.pi / lam
+    xp, yp = pressure_coords(method, nx, h), pressure_coords(method, ny, h)
+    xn, yn = node_coords(nx, h), node_coords(ny, h)
+
+    def poly(x):
+        return x ** k - (1.0 - x) ** k
+
+    def dpoly(x):
+        return k * (x ** (k - 1) + (1.0 - x) ** (k - 1))
+
+    phi = gamma * (poly(xp)[None, :] + poly(yp)[:, None]) + np.outer(np.sin(al * yp), np.sin(al * xp))
+    # V at (x nodes, y pressure rows), W at (x pressure columns, y nodes)
+    phix = gamma * dpoly(xn)[None, :] + al * np.outer(np.sin(al * yp), np.cos(al * xn))
+    phiy = gamma * dpoly(yn)[:, None] + al * np.outer(np.cos(al * yn), np.sin(al * xp))
+    phix = np.broadcast_to(phix, (yp.size, xn.size))
+    phiy = np.broadcast_to(phiy, (yn.size, xp.size))
+    s = math.sin(om * t) / (rho * om)
+    return {"U": phi * math.cos(om * t), "V": -phix * s, "W": -phiy * s}
+
+
+def hetero_problem(method: int, n: int, gamma: float, k: int, cfl: float, periods: float = 5.0,
+                   lam: float = 0.25, period: float = 1.0 / math.sqrt(2.0)) -> dict:
+    """The heterogeneous test of Section 4 on the unit square with n x n
+    cells: initial fields (the exact solution at t = 0), the forcing that
+    makes eq. harmonic_hetero a solution of eq. 1 with c = rho = kappa = 1,
+        f = -sin(w t) (w phi + lap(phi) / w) = g(x, y) cos(w (t + period / 4)),
+    as a field g with a cosine signal, the wall signal cos(w t) that scales
+    the walls' initial values, and the step: the largest dt <= cfl h that
+    divides the simulated time (periods x period) into whole steps."""
+    h = 1.0 / n
+    om = 2.0 * math.pi / period
+    al = 2.0 * math.pi / lam
+    x, y = pressure_coords(method, n, h), pressure_coords(method, n, h)
+
+    def poly(z, kk):
+        return z ** kk - (1.0 - z) ** kk
+
+    phi = gamma * (poly(x, k)[None, :] + poly(y, k)[:, None]) + np.outer(np.sin(al * y), np.sin(al * x))
+    lap = (gamma * k * (k - 1) * (poly(x, k - 2)[None, :] + poly(y, k - 2)[:, None]) if k >= 2 else 0.0) \
+        - 2.0 * al * al * np.outer(np.sin(al * y), np.sin(al * x))
+    g = om * phi + lap / om
+    T = periods * period
+    nsteps = int(math.ceil(T / (cfl * h) - 1e-9))
+    f0 = hetero_solution(method, n, n, h, gamma, k, 0.0, lam, period)
+    return {"method": method, "n": n, "h": h, "dt": T / nsteps, "nsteps": nsteps, "T": T,
+            "U": f0["U"], "V": f0["V"], "W": f0["W"], "F": g,
+            "fsig": {"kind": 2, "f0": 1.0 / period, "t0": -period / 4.0, "amp": 1.0},
+            "bsig": {"kind": 2, "f0": 1.0 / period, "t0": 0.0, "amp": 1.0},
+            "gamma": gamma, "k": k, "lam": lam, "period": period}

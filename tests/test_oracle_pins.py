@@ -603,3 +603,60 @@ def test_direct_beyond_fixed_point_limit_matches_closed_form(method, mode, tol, 
     assert np.abs(U - g * f["U"]).max() < tol
     Us, _, _ = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, sweeps=6)
     assert not np.abs(Us - g * f["U"]).max() < 1.0
+
+
+# ------------------------------------------------- heterogeneous test (Section 4)
+
+def _hetero_rates(method, gamma, k, ns, cfl, sweeps):
+    errs = []
+    for N in ns:
+        pr = inputs.hetero_problem(method, N, gamma, k, cfl)
+        U, V, W = O.run_forced(method, pr["U"], pr["V"], pr["W"], h=pr["h"], dt=pr["dt"], nsteps=pr["nsteps"],
+                               sweeps=sweeps, F=pr["F"], fsig=pr["fsig"], bsig=pr["bsig"])
+        ex = inputs.hetero_solution(method, N, N, pr["h"], gamma, k, pr["T"])
+        errs.append(np.abs(U - ex["U"]).max())
+    return errs, _rate(errs, ns)
+
+
+@pytest.mark.parametrize("gamma", [2, 9])
+def test_hetero_mimetic_converges_at_second_order(gamma):
+    """Section 4's test with non-homogeneous walls (eq. harmonic_hetero, Gamma
+    = k, lambda = 1/4, T = 1/sqrt 2, five periods): the max error converges at
+    order 2 as in Table 5's Gamma = k columns (averages 1.99 and 1.88), the
+    Crank-Nicolson time error dominating.  Run at cfl 0.4 with 16 sweeps, so
+    that the stages are converged (contraction 0.24 per sweep) and the rate
+    measures the scheme; the rate pins the intermediate level's wall values:
+    the mid-step wall value alone converges at first order."""
+    errs, rates = _hetero_rates(O.MFD, gamma, gamma, [48, 64, 96, 128], 0.4, 16)
+    assert all(1.8 < r < 2.6 for r in rates[-2:]), (errs, rates)
+    assert errs[-1] < 1.5e-3, errs
+
+
+def test_hetero_homogeneous_limit():
+    """Gamma = 0: the walls carry sin(8 pi x) sin(8 pi y) = 0, so the
+    time-dependent wall data change nothing, and with the forcing alone the
+    error converges at high order (Table 5's Gamma = 0 column averages 3.87)."""
+    pr = inputs.hetero_problem(O.MFD, 48, 0, 2, 0.81)
+    kw = dict(h=pr["h"], dt=pr["dt"], nsteps=pr["nsteps"], sweeps=6, F=pr["F"], fsig=pr["fsig"])
+    a = O.run_forced(O.MFD, pr["U"], pr["V"], pr["W"], bsig=pr["bsig"], **kw)
+    b = O.run_forced(O.MFD, pr["U"], pr["V"], pr["W"], **kw)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1.0)
+    errs, rates = _hetero_rates(O.MFD, 0, 2, [64, 96, 128], 0.4, 16)
+    assert min(rates) > 3.8, (errs, rates)
+
+
+def test_hetero_forcing_enters_like_the_point_source():
+    """A forcing field that is zero except at one interior point, h^-2 there,
+    with a Ricker signal, is the point source: same fields."""
+    n = 24
+    h = 1.0 / n
+    f = inputs.random_fields(O.MFD, n, n, 5)
+    src = {"i": 7, "j": 11, "f0": 3.0, "t0": 0.2, "amp": 1.3}
+    F = np.zeros(O.shapes(O.MFD, n, n)["U"])
+    F[11, 7] = 1.0 / (h * h)
+    a = O.run(O.MFD, f["U"], f["V"], f["W"], h=h, dt=0.5 * h, nsteps=5, src=src)
+    b = O.run_forced(O.MFD, f["U"], f["V"], f["W"], h=h, dt=0.5 * h, nsteps=5, F=F,
+                     fsig={"kind": O.SIGNAL_RICKER, "f0": 3.0, "t0": 0.2, "amp": 1.3})
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-14 * np.abs(x).max()
