@@ -157,6 +157,25 @@ const char* adi_last_error(void);
 int adi_set_forcing(adi_problem* pb, const void* F, int64_t ldF, const adi_signal* s);
 int adi_set_boundary(adi_problem* pb, const adi_signal* s);
 
+/* Absorbing layers: the damped system, a reformulation the paper points to
+ * for absorbing boundaries (Section 2.1, closing remarks),
+ *   u_t = -kappa div v - (d_x + d_y) u + f,
+ *   rho v_t = -u_x - rho d_x v,   rho w_t = -u_y - rho d_y w,
+ * with d_x (d_y) the rate of the layers along the x (y) walls.  The split
+ * keeps each rate with its direction (A1 gets -d_x on u and v, A2 -d_y on u
+ * and w), so every implicit line system divides by 1 + a d and every
+ * explicit part multiplies by 1 - a d: the line passes compute the factors
+ * per slot, with no extra memory traffic.  Profile: d = d0 (1 - dist /
+ * width)^2 within `width` cells of each wall whose bit is set (ADI_WALL_*),
+ * 0 beyond; width 0 = the uniform rate d0 in each direction with a wall bit
+ * set.  A free surface (the top of the layered workloads) keeps its bit
+ * clear.  d0 = 0 or walls = 0 switches the layers off (the default).
+ * Takes effect at the next pass.  Scope: FP32 and FP64 with fixed sweep
+ * counts, single problems and batches; ADI_EINVAL for the compensated mode,
+ * direct solves and tolerance-tested stages. */
+enum { ADI_WALL_X0 = 1, ADI_WALL_X1 = 2, ADI_WALL_Y0 = 4, ADI_WALL_Y1 = 8 };
+int adi_set_damping(adi_problem* pb, double d0, double width, int walls);
+
 /* Fill *p with defaults: CFD, FP32, order 0, 6 sweeps, no source,
  * kappa0 = rinv0 = 1, struct_size set.  Sizes, h, dt, c_max left zero. */
 int adi_params_init(adi_params* p);

@@ -77,6 +77,8 @@ def _load():
         lib.oracle_run_forced.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64, dp, sp,
                                           sp]
         lib.oracle_run_forced.restype = ctypes.c_int
+        lib.oracle_run_damped.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp, dp, ctypes.c_int64, dp]
+        lib.oracle_run_damped.restype = ctypes.c_int
         lib.oracle_source.argtypes = [ctypes.POINTER(_Params), ctypes.c_double]
         lib.oracle_source.restype = ctypes.c_double
         for name in ("oracle_cfd_d", "oracle_cfd_dbar", "oracle_mfd_g", "oracle_mfd_d"):
@@ -239,6 +241,29 @@ def run_forced(method, U, V, W, *, h, dt, nsteps, sweeps=6, K=None, Rv=None, Rw=
                                    int(nsteps), _ptr(F), _signal(fsig), _signal(bsig))
     if rc != 0:
         raise ValueError("oracle_run_forced rejected its arguments")
+    return U, V, W
+
+
+def run_damped(method, U, V, W, *, h, dt, nsteps, d0, width, walls, sweeps=6, K=None, Rv=None, Rw=None,
+               order=0, src=None, t0=0.0, kappa0=1.0, rinv0=1.0, threads=0):
+    """As :func:`run` with damping layers: rate d0 (1 - dist/width)^2 within
+    `width` cells of the walls in the mask (1: x = 0, 2: x = 1, 4: y = 0,
+    8: y = 1; width 0 = uniform d0)."""
+    ny = U.shape[0] - (1 if method == CFD else 2)
+    nx = U.shape[1] - (1 if method == CFD else 2)
+    sh = shapes(method, nx, ny)
+    U = _f64(U, sh["U"], "U").copy()
+    V = _f64(V, sh["V"], "V").copy()
+    W = _f64(W, sh["W"], "W").copy()
+    K = None if K is None else _f64(K, sh["K"], "K")
+    Rv = None if Rv is None else _f64(Rv, sh["Rv"], "Rv")
+    Rw = None if Rw is None else _f64(Rw, sh["Rw"], "Rw")
+    p = make_params(method, nx, ny, h, dt, sweeps, order, src, t0, kappa0, rinv0, threads)
+    damp = np.array([d0, width, walls], dtype=np.float64)
+    rc = _load().oracle_run_damped(ctypes.byref(p), _ptr(U), _ptr(V), _ptr(W), _ptr(K), _ptr(Rv), _ptr(Rw),
+                                   int(nsteps), _ptr(damp))
+    if rc != 0:
+        raise ValueError("oracle_run_damped rejected its arguments")
     return U, V, W
 
 

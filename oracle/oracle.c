@@ -346,7 +346,30 @@ typedef struct {
     double* RU;                /* interior pressure right-hand side */
     int src_i, src_j;
     double h;
+    /* damping layers (oracle_run_damped): rate d0 (1 - dist / width)^2 within
+     * `width` cells of each wall whose bit is set in dmask (1: x = 0, 2: x = 1,
+     * 4: y = 0, 8: y = 1); width 0: the uniform rate d0 in every direction
+     * with a bit set */
+    double d0, dwidth;
+    int dmask;
 } problem;
+
+/* Damping rate at index k along direction dir: pressure points (vel = 0)
+ * or velocity points (vel = 1), from the distances to the two walls. */
+static double damp_rate(const problem* pb, int dir, int vel, int k) {
+    const int bits = (pb->dmask >> (2 * dir)) & 3;
+    if (!bits || pb->d0 == 0.0) return 0.0;
+    if (pb->dwidth <= 0.0) return pb->d0;
+    const int n = dir == 0 ? pb->nx : pb->ny;
+    double lo;
+    if (vel || pb->method == ORC_CFD) lo = k;
+    else lo = k == 0 ? 0.0 : (k == n + 1 ? (double)n : k - 0.5);
+    const double hi = n - lo;
+    double r = 0.0;
+    if (bits & 1) { const double x = 1.0 - lo / pb->dwidth; if (x > 0.0) r += pb->d0 * x * x; }
+    if (bits & 2) { const double x = 1.0 - hi / pb->dwidth; if (x > 0.0) r += pb->d0 * x * x; }
+    return r;
+}
 
 /* One stage of the Peaceman-Rachford split with the implicit direction d
  * and explicit direction e = 1-d, forcing value F at the source point.
@@ -392,14 +415,15 @@ static void stage(problem* pb, int d, double Fsrc, const double* Ffield, double 
                 int j = e == 0 ? l : k, i = e == 0 ? k : l;
                 double f = (i == pb->src_i && j == pb->src_j) ? Fsrc : 0.0;
                 if (Ffield) f += Fscale * Ffield[(size_t)j * pb->U.cols + i];
-                RU_AT(j - 1, i - 1) = *at(&pb->U, e, l, k) - a * (kap * tmp[k - 1] - f);
+                const double g = 1.0 - a * damp_rate(pb, e, 0, k);   /* damping along e */
+                RU_AT(j - 1, i - 1) = g * *at(&pb->U, e, l, k) - a * (kap * tmp[k - 1] - f);
             }
             /* vel_e <- vel_e - a R_e .* G_e(U) (full pressure line) */
             gather(&pb->U, e, l, 0, nfu_e, ubuf);
             deriv_G(oe, ubuf, tmp);
             for (int k = 0; k <= ne; ++k) {
                 double r = mat(R_e, e, l, k, pb->rinv0);
-                *at(vel_e, e, l, k) = vbuf[k] - a * r * tmp[k];
+                *at(vel_e, e, l, k) = (1.0 - a * damp_rate(pb, e, 1, k)) * vbuf[k] - a * r * tmp[k];
             }
         }
         free(ubuf); free(vbuf); free(tmp);
@@ -438,13 +462,13 @@ static void stage(problem* pb, int d, double Fsrc, const double* Ffield, double 
                 deriv_D(od, vk, tmp);
                 for (int k = 1; k <= niu_d; ++k) {
                     double kap = mat(&pb->K, d, l, k, pb->kappa0);
-                    ubuf[k] = rhs[k] - a * kap * tmp[k - 1];
+                    ubuf[k] = (rhs[k] - a * kap * tmp[k - 1]) / (1.0 + a * damp_rate(pb, d, 0, k));
                 }
                 /* vel_k = vel_d - a R_d .* G_d(U_k) */
                 deriv_G(od, ubuf, tmp);
                 for (int k = 0; k <= nd; ++k) {
                     double r = mat(R_d, d, l, k, pb->rinv0);
-                    vk[k] = vold[k] - a * r * tmp[k];
+                    vk[k] = (vold[k] - a * r * tmp[k]) / (1.0 + a * damp_rate(pb, d, 1, k));
                 }
             }
             scatter(&pb->U, d, l, 1, niu_d, ubuf + 1);
@@ -707,7 +731,8 @@ static void set_walls_half(problem* pb, int d, const double* Ub, const double* F
 
 static int run_impl(const oracle_params* p, double* U, double* V, double* W, const double* K,
                     const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
-                    int32_t* used, const double* F, const oracle_signal* fs, const oracle_signal* bs) {
+                    int32_t* used, const double* F, const oracle_signal* fs, const oracle_signal* bs,
+                    const double* damp) {
     if (check_params(p) || !U || !V || !W || nsteps < 0) return -1;
     problem pb;
     memset(&pb, 0, sizeof(pb));
@@ -727,6 +752,11 @@ static int run_impl(const oracle_params* p, double* U, double* V, double* W, con
         pb.W.cols = pb.Rw.cols = nx + 1;
     }
     pb.src_i = p->src_i; pb.src_j = p->src_j;
+    if (damp) {
+        pb.d0 = damp[0];
+        pb.dwidth = damp[1];
+        pb.dmask = (int)damp[2];
+    }
     line_ops_init(&pb.ox, m, nx, p->h);
     line_ops_init(&pb.oy, m, ny, p->h);
     pb.RU = calloc((size_t)n_uint(m, nx) * (size_t)n_uint(m, ny), sizeof(double));
@@ -774,7 +804,7 @@ static int run_impl(const oracle_params* p, double* U, double* V, double* W, con
 int oracle_run(const oracle_params* p, double* U, double* V, double* W,
                const double* K, const double* Rv, const double* Rw, int64_t nsteps) {
     if (!p || p->sweeps < 1) return -1;
-    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL);
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL, NULL);
 }
 
 /* As oracle_run (sweeps >= 1) or oracle_run_direct (sweeps 0), with a
@@ -787,7 +817,7 @@ int oracle_run_forced(const oracle_params* p, double* U, double* V, double* W, c
                       const oracle_signal* fs, const oracle_signal* bs) {
     if (!p || p->sweeps < 0) return -1;
     if (F && !fs) return -1;
-    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, F, fs, bs);
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, F, fs, bs, NULL);
 }
 
 /* As oracle_run, with the tolerance test: eps > 0, min_sweeps even in
@@ -797,7 +827,21 @@ int oracle_run_eps(const oracle_params* p, double* U, double* V, double* W, cons
                    const double* Rv, const double* Rw, int64_t nsteps, double eps, int min_sweeps,
                    int32_t* used) {
     if (!(eps > 0.0) || min_sweeps < 2 || (min_sweeps & 1) || !p || min_sweeps > p->sweeps) return -1;
-    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used, NULL, NULL, NULL);
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, eps, min_sweeps, used, NULL, NULL, NULL, NULL);
+}
+
+/* As oracle_run with damping layers (the damped system, a reformulation the
+ * paper points to for absorbing boundaries, Section 2.1): u_t = -kappa div v
+ * - (d_x + d_y) u + f, v_t = -(1/rho) u_x - d_x v, w_t = -(1/rho) u_y - d_y w,
+ * with d_x (d_y) the rate of the x (y) walls' layers.  The split keeps
+ * each rate with its direction: A1 gets -d_x on u and v, A2 gets -d_y on u
+ * and w, so a stage's implicit line systems divide by 1 + a d and its
+ * explicit part multiplies by 1 - a d.  damp = {d0, width in cells, wall
+ * mask}, the profile of damp_rate.  Fixed sweep counts only. */
+int oracle_run_damped(const oracle_params* p, double* U, double* V, double* W, const double* K,
+                      const double* Rv, const double* Rw, int64_t nsteps, const double* damp) {
+    if (!p || p->sweeps < 1 || !damp) return -1;
+    return run_impl(p, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL, damp);
 }
 
 /* As oracle_run with every stage's line systems solved exactly (the limit
@@ -807,7 +851,7 @@ int oracle_run_direct(const oracle_params* p, double* U, double* V, double* W, c
     if (!p) return -1;
     oracle_params q = *p;
     q.sweeps = 0;
-    return run_impl(&q, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL);
+    return run_impl(&q, U, V, W, K, Rv, Rw, nsteps, 0.0, 0, NULL, NULL, NULL, NULL, NULL);
 }
 
 /* Ricker source value F(t) = s(t) / h^2 as the oracle applies it. */

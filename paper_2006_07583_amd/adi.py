@@ -21,7 +21,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
            "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_check", "adi_check_stats",
-           "adi_set_forcing", "adi_set_boundary",
+           "adi_set_forcing", "adi_set_boundary", "adi_set_damping",
            "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
@@ -29,6 +29,7 @@ EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create
            "adi_request_times", "adi_server_get_stats", "adi_server_destroy")
 
 BATCH_GRAPH = 1
+WALL_X0, WALL_X1, WALL_Y0, WALL_Y1 = 1, 2, 4, 8
 REQUEST_HOLD = 1
 
 
@@ -110,6 +111,7 @@ def lib():
         L.adi_set_check.argtypes = [vp, i64, ctypes.c_double]
         L.adi_set_forcing.argtypes = [vp, vp, i64, ctypes.POINTER(AdiSignal)]
         L.adi_set_boundary.argtypes = [vp, ctypes.POINTER(AdiSignal)]
+        L.adi_set_damping.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.adi_check_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
@@ -217,6 +219,12 @@ class Problem:
         s = _signal(signal)
         _check(lib().adi_set_forcing(self._h, _dptr(F), F.stride(0), ctypes.byref(s)))
         self._force = F
+        return self
+
+    def set_damping(self, d0: float, width: float, walls: int) -> "Problem":
+        """adi_set_damping: absorbing layers of rate d0 (1 - dist/width)^2
+        along the walls in the mask (WALL_*); d0 = 0 switches them off."""
+        _check(lib().adi_set_damping(self._h, float(d0), float(width), int(walls)))
         return self
 
     def set_boundary(self, signal) -> "Problem":

@@ -471,6 +471,10 @@ adi::PassDesc<T> make_pass(const adi_problem* pb, int dir, const Buf<T>& uin, co
     a.ff = (const T*)D.FF;
     a.ff_ld = D.ld;
     a.aFf = (T)ps.aFf;
+    a.ah = (T)pb->a;
+    a.dmpm = pb->dmp0 != 0.0 ? (pb->dmpwalls >> (2 * dir)) & 3 : 0;
+    a.dmp0 = (T)pb->dmp0;
+    a.dmpiw = pb->dmpw > 0.0 ? (T)(1.0 / pb->dmpw) : T(0);
     // the wave-per-line kernel writes the natural-layout pressure at
     // (s - 1) * ld + (q + 1): its base is one element lower
     if (pl.ver == 3 && utrans == 0) {
@@ -504,9 +508,9 @@ double source_term(const adi_problem& pb, int64_t m) {
 
 template <typename T>
 hipError_t launch_pass(const PassDesc<T>& d, hipStream_t st) {
-    if (d.ver == 1) return launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg);
+    if (d.ver == 1) return launch_line_pass<T>(d.a, d.method, d.mode, st, d.comp, d.cfg, (d.full() && !d.comp));
     if (d.ver == 2) return launch_line_pass2<T>(d.a, d.method, d.mode, st, d.comp);
-    return launch_line_pass3<T>(d.a, d.method, d.mode, st, d.comp);
+    return launch_line_pass3<T>(d.a, d.method, d.mode, st, d.comp, (d.full() && !d.comp));
 }
 
 template <typename T>
@@ -609,9 +613,9 @@ int run_end(adi_problem* pb, hipStream_t st, int64_t nsteps) {
 
 template <typename T>
 hipError_t launch_grouped(const PassDesc<T>& d, const GroupArgs<T>& ga, hipStream_t st) {
-    if (d.ver == 1) return launch_line_group<T>(ga, d.cfg, d.method, d.mode, st, d.comp);
+    if (d.ver == 1) return launch_line_group<T>(ga, d.cfg, d.method, d.mode, st, d.comp, (d.full() && !d.comp));
     if (d.ver == 2) return launch_line_group2<T>(ga, d.method, d.mode, st, d.comp);
-    return launch_line_group3<T>(ga, d.method, d.mode, st, d.comp);
+    return launch_line_group3<T>(ga, d.method, d.mode, st, d.comp, (d.full() && !d.comp));
 }
 
 template hipError_t launch_grouped<float>(const PassDesc<float>&, const GroupArgs<float>&, hipStream_t);
@@ -1208,6 +1212,23 @@ int adi_set_forcing(adi_problem* pb, const void* F, int64_t ldF, const adi_signa
     return ADI_OK;
 }
 
+int adi_set_damping(adi_problem* pb, double d0, double width, int walls) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!(d0 >= 0.0) || !std::isfinite(d0)) return fail(ADI_EINVAL, "the damping rate must be finite and >= 0");
+    if (!(width >= 0.0) || !std::isfinite(width)) return fail(ADI_EINVAL, "the layer width must be finite and >= 0");
+    if (walls & ~15) return fail(ADI_EINVAL, "unknown wall bits 0x%x", walls);
+    if (d0 > 0.0 && walls) {
+        if (pb->p.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) run without damping layers");
+        if (pb->eps > 0.0) return fail(ADI_EINVAL, "tolerance-tested stages run without damping layers");
+        if (pb->p.dtype == ADI_FP32C) return fail(ADI_EINVAL, "damping layers run in FP32 or FP64, not the compensated mode");
+    }
+    pb->dmp0 = walls ? d0 : 0.0;
+    pb->dmpw = width;
+    pb->dmpwalls = walls;
+    return ADI_OK;
+}
+
 int adi_set_boundary(adi_problem* pb, const adi_signal* s) {
     g_err.clear();
     if (!pb) return fail(ADI_EINVAL, "problem is NULL");
@@ -1289,6 +1310,8 @@ int adi_bind(adi_problem* pb, void* U, void* V, void* W, const void* K, const vo
         pb->ws = nullptr;
         pb->own_ws = false;
     }
+    if (pb->eps > 0.0 && (pb->set_fsig.kind || pb->set_bsig.kind))
+        return fail(ADI_EINVAL, "tolerance-tested stages run without wall data or a forcing field");
     pb->bound = false;
     pb->fF = pb->set_fF;
     pb->fF_ld = pb->set_fF_ld;
@@ -1469,6 +1492,9 @@ int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
         return fail(ADI_EINVAL, "min_sweeps must be even and in [2, sweeps] (got %d, sweeps %d)", min_sweeps,
                     pb->p.sweeps);
     if (pb->p.dtype == ADI_FP32C) return fail(ADI_EINVAL, "tolerance-tested stages: FP32 or FP64 only");
+    if (pb->dmp0 != 0.0) return fail(ADI_EINVAL, "tolerance-tested stages run without damping layers");
+    if (pb->fsig.kind || pb->bsig.kind)
+        return fail(ADI_EINVAL, "tolerance-tested stages run without wall data or a forcing field");
     if (pb->px.ver != 3 || pb->py.ver != 3)
         return fail(ADI_EINVAL,
                     "tolerance-tested stages need lines longer than %d slots in both directions "

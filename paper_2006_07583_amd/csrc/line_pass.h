@@ -54,6 +54,12 @@ struct LinePassArgs {
     T bsc[3];
     const T* ff; int64_t ff_ld;
     T aFf;
+    // Damping layers along this direction (dmpm: bit 0 the line's first
+    // wall, bit 1 its last; 0 = none): rate dmp0 (1 - dist * dmpiw)^2 at a
+    // point dist cells from a wall with its bit set, dmp0 everywhere when
+    // dmpiw = 0.  ah = dt / 2.
+    T dmp0, dmpiw, ah;
+    int dmpm;
 };
 
 // A grouped launch: the passes items[0..nitems) (any problems, any
@@ -69,9 +75,11 @@ struct GroupArgs {
 
 // Single-window kernel (line_pass.hip), tile shape cfg (window line_ws(cfg)).
 template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg);
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg,
+                            bool full = false);
 template <typename T>
-hipError_t launch_line_group(const GroupArgs<T>& g, int cfg, int method, int mode, hipStream_t st, bool comp);
+hipError_t launch_line_group(const GroupArgs<T>& g, int cfg, int method, int mode, hipStream_t st, bool comp,
+                             bool full = false);
 
 // dst[r*dld + c] = scale * (src[r*srs + c*scs] + src2[same])   (src2 may be NULL)
 template <typename T>
@@ -97,10 +105,14 @@ int line2_seg(int dtype);
 
 // Multi-window variant with one line per half wave (line_pass3.hip; FP32,
 // FP64 and the compensated FP32 mode): lines per workgroup.
+// full: the variant with the optional features (damping layers, wall data,
+// distributed forcing)
 template <typename T>
-hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false);
+hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp = false,
+                             bool full = false);
 template <typename T>
-hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp = false);
+hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp = false,
+                              bool full = false);
 int line3_lanes(int dtype);
 
 // Tolerance-tested stages (LinePassArgs::eps_part): a pass is `attempts`

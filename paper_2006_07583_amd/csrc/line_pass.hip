@@ -330,7 +330,9 @@ template <typename T, int CF, int METHOD> struct Pass {
 };
 
 // One workgroup's share of a pass: line group `tile` (one window per line).
-template <typename T, int CF, int METHOD, int MODE, bool COMP>
+// FULL: the variant with the optional features (damping layers, wall data,
+// distributed forcing); the plain variant has none of their code.
+template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL = false>
 __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* smem) {
     using P = Pass<T, CF, METHOD>;
     using C = K<T, CF>;
@@ -363,7 +365,7 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
     T A[R], B[R], KK[R], RR[R], U[R], Tt[R];
     // Dirichlet wall values at the first and last pressure slots of the line
     T wl = T(0), wr = T(0);
-    if (a.bnd && qok) {
+    if ((FULL || COMP) && a.bnd && qok) {
         wl = a.bsc[0] * a.bnd[6 * q] + a.bsc[1] * a.bnd[6 * q + 1] + a.bsc[2] * a.bnd[6 * q + 2];
         wr = a.bsc[0] * a.bnd[6 * q + 3] + a.bsc[1] * a.bnd[6 * q + 4] + a.bsc[2] * a.bnd[6 * q + 5];
     }
@@ -379,15 +381,33 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
     }
     if (METHOD == LINE_CFD) __syncthreads();   // tables visible
 
+    // Damping layers (the damped system): implicit rows divided by 1 + a d,
+    // explicit parts multiplied by 1 - a d; the pressure rows are divided
+    // here, the velocity rows after the first half sweep
+    const bool damp = FULL && !COMP && a.dmpm != 0;
+    auto dpres = [&](int s) { return damp_at(a, pres_pos<METHOD, T>(s, n)); };
+    auto dvel = [&](int s) { return damp_at(a, T(s)); };
+    if (MODE != LINE_EXPLICIT && damp) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T e = T(1) / fma(a.ah, dpres(s0 + k), T(1));
+            A[k] *= e;
+            KK[k] *= e;
+        }
+    }
+
     if (MODE == LINE_EXPLICIT || COMP) {
         p.template deriv<0>(A, Tt);                 // G(A)
         p.template deriv<1>(B, U);                  // D(B)
         if (MODE == LINE_EXPLICIT) {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                // W* = B - aR G(A), A_out = A - aK D(B)   (increments when compensated)
-                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
-                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
+                // W* = B - aR G(A), A_out = A - aK D(B)   (increments when compensated;
+                // B, A times 1 - a d with damping)
+                const T bb = damp ? B[k] * fma(-a.ah, dvel(s0 + k), T(1)) : B[k];
+                const T aa = damp ? A[k] * fma(-a.ah, dpres(s0 + k), T(1)) : A[k];
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], bb);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], aa);
             }
         } else {
             // compensated: iterate on the increments, A' = -aK D(B), B' = -aR G(A)
@@ -404,6 +424,14 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
             p.template deriv<1>(B, U);
 #pragma unroll
             for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+        }
+        if (damp) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T e = T(1) / fma(a.ah, dvel(s0 + k), T(1));
+                B[k] *= e;
+                RR[k] *= e;
+            }
         }
         for (int it = 1; it < a.sweeps; ++it) {
             p.template deriv<0>(U, Tt);
@@ -422,16 +450,26 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
                 for (int k = 0; k < R; ++k) U[k] += A[k];
             }
             p.template deriv<1>(Tt, A);                                   // D(v_K)
+            if (damp) {
+                // B and aK restored from their divided forms
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const T vk = Tt[k];
-                Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);                 // 2 v_K - B
-                U[k] = fma(-KK[k], A[k], U[k]);                            // u_K - aK D(v_K)
+                for (int k = 0; k < R; ++k) {
+                    const T dp = a.ah * dpres(s0 + k), vk = Tt[k];
+                    Tt[k] = vk + (vk - B[k] * fma(a.ah, dvel(s0 + k), T(1)));
+                    U[k] = fma(-KK[k] * (T(1) + dp), A[k], U[k] * (T(1) - dp));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T vk = Tt[k];
+                    Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);             // 2 v_K - B
+                    U[k] = fma(-KK[k], A[k], U[k]);                        // u_K - aK D(v_K)
+                }
             }
         }
     }
 
-    if (MODE != LINE_FINAL && a.ff) {
+    if ((FULL || COMP) && MODE != LINE_FINAL && a.ff) {
         // distributed forcing on the interior pressure slots
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -443,15 +481,15 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
                                                   tid, MODE != LINE_FINAL);
 }
 
-template <typename T, int CF, int METHOD, int MODE, bool COMP>
+template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL>
 __global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_kernel(const LinePassArgs<T> a) {
     __shared__ T smem[Pass<T, CF, METHOD>::SMEM];
-    lp_body<T, CF, METHOD, MODE, COMP>(a, (int)blockIdx.x, smem);
+    lp_body<T, CF, METHOD, MODE, COMP, FULL>(a, (int)blockIdx.x, smem);
 }
 
 // Several passes (of several problems) in one launch: each workgroup finds
 // its pass in the prefix sums of the block counts.
-template <typename T, int CF, int METHOD, int MODE, bool COMP>
+template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL>
 __global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_group_kernel(const GroupArgs<T> ga) {
     __shared__ T smem[Pass<T, CF, METHOD>::SMEM];
     int tile;
@@ -459,7 +497,7 @@ __global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_group_kernel(const G
     if (it < 0) return;
     LinePassArgs<T> a = ga.items[it];
     if (a.aFtab) a.aF = a.aFtab[*ga.tick];
-    lp_body<T, CF, METHOD, MODE, COMP>(a, tile, smem);
+    lp_body<T, CF, METHOD, MODE, COMP, FULL>(a, tile, smem);
 }
 
 // ------------------------------------------------------------------------
@@ -502,7 +540,7 @@ __global__ void __launch_bounds__(256) scaled_copy_kernel(T* __restrict__ dst, i
     }
 }
 
-template <typename T, int CF, bool COMP>
+template <typename T, int CF, bool COMP, bool FULL>
 hipError_t launch_lp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st) {
     const unsigned nb = a ? (unsigned)(a->nlg * a->nwin) : (unsigned)(((ga->total + 7) / 8) * 8);
     if (nb == 0) return hipSuccess;
@@ -510,9 +548,9 @@ hipError_t launch_lp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int metho
 #define LP_CASE(M, MD)                                                                                  \
     if (method == M && mode == MD) {                                                                    \
         if (a)                                                                                          \
-            hipLaunchKernelGGL((line_pass_kernel<T, CF, M, MD, COMP>), grid, block, 0, st, *a);        \
-        else                                                                                            \
-            hipLaunchKernelGGL((line_pass_group_kernel<T, CF, M, MD, COMP>), grid, block, 0, st, *ga); \
+            hipLaunchKernelGGL((line_pass_kernel<T, CF, M, MD, COMP, FULL>), grid, block, 0, st, *a);        \
+        else                                                                                                  \
+            hipLaunchKernelGGL((line_pass_group_kernel<T, CF, M, MD, COMP, FULL>), grid, block, 0, st, *ga); \
         return hipGetLastError();                                                                       \
     }
     LP_CASE(LINE_CFD, LINE_SWEEP)
@@ -525,30 +563,40 @@ hipError_t launch_lp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int metho
     return hipErrorInvalidValue;
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, bool FULL>
 hipError_t launch_lp_cfg(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int cfg, int method, int mode,
                          hipStream_t st) {
     switch (cfg) {
-        case 0: return launch_lp<T, 0, COMP>(a, ga, method, mode, st);
-        case 1: return launch_lp<T, 1, COMP>(a, ga, method, mode, st);
-        case 2: return launch_lp<T, 2, COMP>(a, ga, method, mode, st);
+        case 0: return launch_lp<T, 0, COMP, FULL>(a, ga, method, mode, st);
+        case 1: return launch_lp<T, 1, COMP, FULL>(a, ga, method, mode, st);
+        case 2: return launch_lp<T, 2, COMP, FULL>(a, ga, method, mode, st);
         default: return hipErrorInvalidValue;
     }
 }
 
+// variants: plain, compensated (FP32; wall data and forcing included), with
+// the optional features (damping layers, wall data, forcing; not compensated)
 template <typename T>
-hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg) {
-    if (!comp) return launch_lp_cfg<T, false>(&a, nullptr, cfg, method, mode, st);
-    if constexpr (std::is_same<T, float>::value) return launch_lp_cfg<T, true>(&a, nullptr, cfg, method, mode, st);
+hipError_t launch_lp_any(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int cfg, int method, int mode,
+                         hipStream_t st, bool comp, bool full) {
+    if (comp && full) return hipErrorInvalidValue;
+    if (full) return launch_lp_cfg<T, false, true>(a, ga, cfg, method, mode, st);
+    if (!comp) return launch_lp_cfg<T, false, false>(a, ga, cfg, method, mode, st);
+    if constexpr (std::is_same<T, float>::value) return launch_lp_cfg<T, true, false>(a, ga, cfg, method, mode, st);
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_line_group(const GroupArgs<T>& ga, int cfg, int method, int mode, hipStream_t st, bool comp) {
+hipError_t launch_line_pass(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, int cfg,
+                            bool full) {
+    return launch_lp_any<T>(&a, nullptr, cfg, method, mode, st, comp, full);
+}
+
+template <typename T>
+hipError_t launch_line_group(const GroupArgs<T>& ga, int cfg, int method, int mode, hipStream_t st, bool comp,
+                             bool full) {
     if (ga.total <= 0) return hipSuccess;
-    if (!comp) return launch_lp_cfg<T, false>(nullptr, &ga, cfg, method, mode, st);
-    if constexpr (std::is_same<T, float>::value) return launch_lp_cfg<T, true>(nullptr, &ga, cfg, method, mode, st);
-    return hipErrorInvalidValue;
+    return launch_lp_any<T>(nullptr, &ga, cfg, method, mode, st, comp, full);
 }
 
 template <typename T>
@@ -604,10 +652,10 @@ int line_halo(int dtype, int method, int sweeps, double cfl) {
     return cfl <= 0.85 ? 36 + 2 * sweeps : 40 + 3 * sweeps;
 }
 
-template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, int);
-template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool, int);
-template hipError_t launch_line_group<float>(const GroupArgs<float>&, int, int, int, hipStream_t, bool);
-template hipError_t launch_line_group<double>(const GroupArgs<double>&, int, int, int, hipStream_t, bool);
+template hipError_t launch_line_pass<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, int, bool);
+template hipError_t launch_line_pass<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool, int, bool);
+template hipError_t launch_line_group<float>(const GroupArgs<float>&, int, int, int, hipStream_t, bool, bool);
+template hipError_t launch_line_group<double>(const GroupArgs<double>&, int, int, int, hipStream_t, bool, bool);
 template hipError_t launch_scaled_copy<float>(float*, int64_t, const float*, int64_t, int64_t, int, int, float,
                                              hipStream_t, const float*);
 template hipError_t launch_scaled_copy<double>(double*, int64_t, const double*, int64_t, int64_t, int, int, double,

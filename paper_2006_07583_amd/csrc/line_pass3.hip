@@ -336,7 +336,9 @@ template <typename T, int METHOD> struct Line3 {
 // EPS: the tolerance-tested form (LinePassArgs::eps_part).  It keeps the
 // previous iterates by solving into a spare array, and stores the squared
 // changes of the last two sweeps over the slots the window writes.
-template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false>
+// FULL: the variant with the optional features (damping layers, wall data,
+// distributed forcing); the plain variant has none of their code.
+template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false, bool FULL = false>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
     static_assert(!(EPS && COMP), "the tolerance-tested form runs without compensation");
     if (EPS && *a.eps_go == 0) return;   // uniform: an earlier attempt converged
@@ -495,7 +497,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     // window, position 0) and its last (last lane of the last window,
     // position R - 1); the material arrays are zero there, so the sweeps keep
     // them
-    if (a.bnd && qok) {
+    if ((FULL || COMP) && a.bnd && qok) {
         if (L.bl) A[0] = a.bsc[0] * a.bnd[6 * q] + a.bsc[1] * a.bnd[6 * q + 1] + a.bsc[2] * a.bnd[6 * q + 2];
         if (L.br)
             A[R - 1] = a.bsc[0] * a.bnd[6 * q + 3] + a.bsc[1] * a.bnd[6 * q + 4] + a.bsc[2] * a.bnd[6 * q + 5];
@@ -521,6 +523,26 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 #pragma unroll
         for (int k = 0; k < R; ++k) RR[k] = qok && s0 + k <= n ? v : T(0);
     }
+    // Damping layers (the damped system: each implicit line system divides
+    // by 1 + a d, each explicit part multiplies by 1 - a d).  The implicit
+    // pressure rows are divided here (A and a kappa); the velocity rows after
+    // the first half sweep, which still reads the undivided B.
+    const bool damp = FULL && !COMP && a.dmpm != 0;   // uniform
+    auto dpres = [&](int s) { return damp_at(a, pres_pos<METHOD, T>(s, n)); };
+    auto dvel = [&](int s) { return damp_at(a, T(s)); };
+    if (MODE != LINE_EXPLICIT && damp) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T e = T(1) / fma(a.ah, dpres(s0 + k), T(1));
+            A[k] *= e;
+            KK[k] *= e;
+        }
+    }
+    auto damp_vel = [&](T& x, T& r, int s) {
+        const T e = T(1) / fma(a.ah, dvel(s), T(1));
+        x *= e;
+        r *= e;
+    };
 
     // Tolerance test: squared changes of the last two sweeps over the slots
     // this window writes (pressure: interior slots; velocity: slots 0..n).
@@ -546,7 +568,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
         T Al = L.prev(A[R - 1]), Ar = L.next(A[0]);
         const T Kl = L.prev(KK[R - 1]), Kr = L.next(KK[0]);
         T Bl = L.prev(B[R - 1]), Br = L.next(B[0]);
-        const T Rl = L.prev(RR[R - 1]), Rr = L.next(RR[0]);
+        T Rl = L.prev(RR[R - 1]), Rr = L.next(RR[0]);
         T xl, xr;
         if (MODE == LINE_EXPLICIT) {
             L.rhs(0, A, Al, Ar, Tt);
@@ -555,9 +577,12 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             L.solve(1, U, xl, xr);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                // W* = B - aR G(A), A - aK D(B) (the increments when compensated)
-                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
-                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
+                // W* = B - aR G(A), A - aK D(B) (the increments when compensated;
+                // B, A times 1 - a d with damping)
+                const T bb = damp ? B[k] * fma(-a.ah, dvel(s0 + k), T(1)) : B[k];
+                const T aa = damp ? A[k] * fma(-a.ah, dpres(s0 + k), T(1)) : A[k];
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], bb);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], aa);
             }
         } else {
             T Ul, Ur;
@@ -589,6 +614,12 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
                 Ul = fma(-Kl, xl, Al);
                 Ur = fma(-Kr, xr, Ar);
+            }
+            if (damp) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) damp_vel(B[k], RR[k], s0 + k);
+                damp_vel(Bl, Rl, s0 - 1);
+                damp_vel(Br, Rr, s0 + R);
             }
             T Tl, Tr;
             if constexpr (EPS) {
@@ -660,18 +691,29 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 }
                 L.rhs(1, Tt, Tl, Tr, A);
                 L.solve(1, A, xl, xr);
+                if (damp) {
+                    // 2 v_K - B and u_K (1 - a d) - aK D(v_K), with B and aK
+                    // restored from their divided forms
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const T vk = Tt[k];
-                    Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);                  // 2 v_K - B
-                    U[k] = fma(-KK[k], A[k], U[k]);                             // u_K - aK D(v_K)
+                    for (int k = 0; k < R; ++k) {
+                        const T dp = a.ah * dpres(s0 + k), vk = Tt[k];
+                        Tt[k] = vk + (vk - B[k] * fma(a.ah, dvel(s0 + k), T(1)));
+                        U[k] = fma(-KK[k] * (T(1) + dp), A[k], U[k] * (T(1) - dp));
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T vk = Tt[k];
+                        Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);              // 2 v_K - B
+                        U[k] = fma(-KK[k], A[k], U[k]);                         // u_K - aK D(v_K)
+                    }
                 }
             }
         }
     } else {
         // ---- mimetic ----
         T Bm2 = L.prev(B[R - 2]), Bm1 = L.prev(B[R - 1]), Bp = L.next(B[0]);
-        const T Rm2 = L.prev(RR[R - 2]), Rm1 = L.prev(RR[R - 1]), Rp = L.next(RR[0]);
+        T Rm2 = L.prev(RR[R - 2]), Rm1 = L.prev(RR[R - 1]), Rp = L.next(RR[0]);
         const T ih8 = T(8.0 / 9.0);   // boundary rows are divided by the folded 9/8
         const T d0c[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
                           T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
@@ -754,8 +796,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             applyD(B, Bm2, Bm1, Bp, U);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], B[k]);
-                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], A[k]);
+                const T bb = damp ? B[k] * fma(-a.ah, dvel(s0 + k), T(1)) : B[k];
+                const T aa = damp ? A[k] * fma(-a.ah, dpres(s0 + k), T(1)) : A[k];
+                Tt[k] = COMP ? -RR[k] * Tt[k] : fma(-RR[k], Tt[k], bb);
+                U[k] = COMP ? -KK[k] * U[k] : fma(-KK[k], U[k], aa);
             }
         } else {
             T Tm2, Tm1, Tp;
@@ -782,6 +826,13 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 applyD(B, Bm2, Bm1, Bp, U);
 #pragma unroll
                 for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            }
+            if (damp) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) damp_vel(B[k], RR[k], s0 + k);
+                damp_vel(Bm2, Rm2, s0 - 2);
+                damp_vel(Bm1, Rm1, s0 - 1);
+                damp_vel(Bp, Rp, s0 + R);
             }
             if constexpr (EPS) {
                 T X[R];
@@ -827,11 +878,20 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                     for (int k = 0; k < R; ++k) U[k] += A[k];
                 }
                 applyD(Tt, Tm2, Tm1, Tp, A);
+                if (damp) {
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const T vk = Tt[k];
-                    Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);
-                    U[k] = fma(-KK[k], A[k], U[k]);
+                    for (int k = 0; k < R; ++k) {
+                        const T dp = a.ah * dpres(s0 + k), vk = Tt[k];
+                        Tt[k] = vk + (vk - B[k] * fma(a.ah, dvel(s0 + k), T(1)));
+                        U[k] = fma(-KK[k] * (T(1) + dp), A[k], U[k] * (T(1) - dp));
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T vk = Tt[k];
+                        Tt[k] = COMP ? vk + vk : vk + (vk - B[k]);
+                        U[k] = fma(-KK[k], A[k], U[k]);
+                    }
                 }
             }
         }
@@ -863,7 +923,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             for (int k = 0; k < R; ++k)
                 if (k == ks) U[k] += a.aF;
         }
-        if (a.ff) {
+        if ((FULL || COMP) && a.ff) {
             // distributed forcing (zero outside the interior, like the
             // materials); KK is free after the last derivative
             VT cf[CPT], ef{};
@@ -1009,7 +1069,7 @@ constexpr bool kGroupOrder = METHOD == LINE_CFD || sizeof(T) == 4;
 template <typename T, bool EPS>
 constexpr int kWpe = EPS ? (sizeof(T) == 4 ? 2 : 1) : Cfg3<T>::WPE;
 
-template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false>
+template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false, bool FULL = false>
 __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(kWpe<T, EPS>, kWpe<T, EPS>)))
 line_pass3_kernel(const LinePassArgs<T> a) {
@@ -1022,10 +1082,10 @@ line_pass3_kernel(const LinePassArgs<T> a) {
     const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (t >= nb) return;
     const int tile = kGroupOrder<T, METHOD> ? (t % a.nwin) * a.nlg + t / a.nwin : t;
-    lp3_body<T, METHOD, MODE, EPS, COMP>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, EPS, COMP, FULL>(a, tile, smem);
 }
 
-template <typename T, int METHOD, int MODE, bool COMP = false>
+template <typename T, int METHOD, int MODE, bool COMP = false, bool FULL = false>
 __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(Cfg3<T>::WPE, Cfg3<T>::WPE)))
 line_pass3_group_kernel(const GroupArgs<T> ga) {
@@ -1035,7 +1095,7 @@ line_pass3_group_kernel(const GroupArgs<T> ga) {
     if (it < 0) return;
     LinePassArgs<T> a = ga.items[it];
     if (a.aFtab) a.aF = a.aFtab[*ga.tick];
-    lp3_body<T, METHOD, MODE, false, COMP>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, false, COMP, FULL>(a, tile, smem);
 }
 
 // compensated launches exist for FP32 only
@@ -1054,15 +1114,23 @@ hipError_t launch3_comp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, dim3 g
 
 template <typename T>
 hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method, int mode, hipStream_t st,
-                   bool comp) {
+                   bool comp, bool full) {
     const int nb = a ? a->nlg * a->nwin : ga->total;
     if (nb <= 0) return hipSuccess;
     dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
     const bool eps = a && a->eps_part;
-    if (eps && (mode == LINE_EXPLICIT || comp)) return hipErrorInvalidValue;
+    if (eps && (mode == LINE_EXPLICIT || comp || full)) return hipErrorInvalidValue;
+    if (comp && full) return hipErrorInvalidValue;
 #define LP3_CASE(M, MD)                                                                                  \
     if (method == M && mode == MD) {                                                                     \
         if (comp) return launch3_comp<T, M, MD>(a, ga, grid, block, st);                                  \
+        if (full) {                                                                                      \
+            if (a)                                                                                       \
+                hipLaunchKernelGGL((line_pass3_kernel<T, M, MD, false, false, true>), grid, block, 0, st, *a); \
+            else                                                                                         \
+                hipLaunchKernelGGL((line_pass3_group_kernel<T, M, MD, false, true>), grid, block, 0, st, *ga); \
+            return hipGetLastError();                                                                    \
+        }                                                                                                \
         if (eps)                                                                                         \
             hipLaunchKernelGGL((line_pass3_kernel<T, M, MD, MD != LINE_EXPLICIT>), grid, block, 0, st, *a); \
         else if (a)                                                                                      \
@@ -1082,13 +1150,13 @@ hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method,
 }
 
 template <typename T>
-hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp) {
-    return launch3<T>(&a, nullptr, method, mode, st, comp);
+hipError_t launch_line_pass3(const LinePassArgs<T>& a, int method, int mode, hipStream_t st, bool comp, bool full) {
+    return launch3<T>(&a, nullptr, method, mode, st, comp, full);
 }
 
 template <typename T>
-hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipStream_t st, bool comp) {
-    return launch3<T>(nullptr, &ga, method, mode, st, comp);
+hipError_t launch_line_group3(const GroupArgs<T>& ga, int method, int mode, hipStream_t st, bool comp, bool full) {
+    return launch3<T>(nullptr, &ga, method, mode, st, comp, full);
 }
 
 int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW; }
@@ -1143,9 +1211,9 @@ hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int atte
     return hipGetLastError();
 }
 
-template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool);
-template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool);
-template hipError_t launch_line_group3<float>(const GroupArgs<float>&, int, int, hipStream_t, bool);
-template hipError_t launch_line_group3<double>(const GroupArgs<double>&, int, int, hipStream_t, bool);
+template hipError_t launch_line_pass3<float>(const LinePassArgs<float>&, int, int, hipStream_t, bool, bool);
+template hipError_t launch_line_pass3<double>(const LinePassArgs<double>&, int, int, hipStream_t, bool, bool);
+template hipError_t launch_line_group3<float>(const GroupArgs<float>&, int, int, hipStream_t, bool, bool);
+template hipError_t launch_line_group3<double>(const GroupArgs<double>&, int, int, hipStream_t, bool, bool);
 
 }  // namespace adi

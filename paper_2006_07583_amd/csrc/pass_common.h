@@ -23,6 +23,30 @@ __device__ __forceinline__ int group_item(const GroupArgs<T>& g, int& tile) {
     return lo;
 }
 
+// Damping rate at a point `lo` cells from the line's first wall (the line
+// has n cells), from the layer parameters of LinePassArgs.
+template <typename T>
+__device__ __forceinline__ T damp_at(const LinePassArgs<T>& a, T lo) {
+    if (a.dmpiw == T(0)) return a.dmp0;
+    T r = T(0);
+    if (a.dmpm & 1) {
+        const T x = T(1) - lo * a.dmpiw;
+        r += x > T(0) ? a.dmp0 * x * x : T(0);
+    }
+    if (a.dmpm & 2) {
+        const T x = T(1) - (T(a.n) - lo) * a.dmpiw;
+        r += x > T(0) ? a.dmp0 * x * x : T(0);
+    }
+    return r;
+}
+// Position (cells from the first wall) of pressure slot s: nodes (compact)
+// or the faces and cell centres (mimetic).
+template <int METHOD, typename T>
+__device__ __forceinline__ T pres_pos(int s, int n) {
+    if (METHOD == 0) return T(s);
+    return s <= 0 ? T(0) : (s >= n + 1 ? T(n) : T(s) - T(0.5));
+}
+
 // hi + lo + inc as a new (hi, lo) pair: TwoSum of hi and the increment, its
 // rounding error folded into the low word, then renormalised.
 template <typename T>

@@ -30,9 +30,11 @@ struct PassDesc {
     int ver, cfg, method, mode;
     bool comp;
     int dir;
+    // the kernel variant with damping layers, wall data or a forcing field
+    bool full() const { return a.dmpm != 0 || a.bnd != nullptr || a.ff != nullptr; }
     int tiles() const { return a.nlg * a.nwin; }
     // kernel variant: passes with equal keys can share a grouped launch
-    int key() const { return ((ver * 4 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0); }
+    int key() const { return (((ver * 4 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0)) * 2 + (full() ? 1 : 0); }
 };
 
 int fail(int code, const char* fmt, ...);
@@ -110,6 +112,10 @@ struct adi_problem {
     int64_t set_fF_ld = 0;
     adi_signal set_fsig{};
     adi_signal set_bsig{};
+    // damping layers (adi_set_damping): rate, width in cells (0: uniform),
+    // walls (bit 0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1)
+    double dmp0 = 0.0, dmpw = 0.0;
+    int dmpwalls = 0;
     // factor store of the direct solves (sweeps 0) and the constant
     // materials {a kappa0, a rinv0} they read when K or R is absent, both
     // part of the workspace

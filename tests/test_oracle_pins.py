@@ -660,3 +660,85 @@ def test_hetero_forcing_enters_like_the_point_source():
                      fsig={"kind": O.SIGNAL_RICKER, "f0": 3.0, "t0": 0.2, "amp": 1.3})
     for x, y in zip(a, b):
         assert np.abs(x - y).max() <= 1e-14 * np.abs(x).max()
+
+
+# ---------------------------------------------------------- damping layers (f4)
+
+def pr_mode_state_damped(alpha, beta, a, nsteps, d):
+    """pr_mode_state with kappa = rho = 1 and the uniform damping rate d in
+    both directions: A1 gets -d on pressure and x-velocity, A2 -d on
+    pressure and y-velocity."""
+    A1 = np.array([[-d, alpha, 0], [-alpha, -d, 0], [0, 0, 0.0]])
+    A2 = np.array([[-d, 0, beta], [0, 0, 0], [-beta, 0, -d]])
+    I = np.eye(3)
+    M = np.linalg.solve(I - a * A2, I + a * A1) @ np.linalg.solve(I - a * A1, I + a * A2)
+    return np.linalg.matrix_power(M, nsteps)[:, 0]
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_damping_zero_rate_is_the_undamped_step(method):
+    n = 30
+    f = inputs.random_fields(method, n, n, 4)
+    a = O.run(method, f["U"], f["V"], f["W"], h=1 / n, dt=0.5 / n, nsteps=4)
+    b = O.run_damped(method, f["U"], f["V"], f["W"], h=1 / n, dt=0.5 / n, nsteps=4, d0=0.0, width=8, walls=15)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_uniform_damping_follows_closed_form(method):
+    """A uniform rate d = 3 in both directions (width 0, all walls): the
+    standing mode (1, 2) follows the closed-form amplification of the damped
+    split, pressure and both velocities, at fourth order in h; damping the
+    pressure once instead of with both directions' rates fails."""
+    d = 3.0
+    errs = {}
+    for N in (64, 128):
+        h = 1.0 / N
+        f = inputs.standing_mode(method, N, N, h, 1, 2)
+        dt, nsteps = 0.5 * h, 40
+        xp, xn = inputs.pressure_coords(method, N, h), inputs.node_coords(N, h)
+        al, be = math.pi, 2 * math.pi
+        u, v, w = pr_mode_state_damped(al, be, dt / 2, nsteps, d)
+        Ue = u * np.outer(np.sin(be * xp), np.sin(al * xp))
+        Ve = v * np.outer(np.sin(be * xp), np.cos(al * xn))
+        We = w * np.outer(np.cos(be * xn), np.sin(al * xp))
+        U, V, W = O.run_damped(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, d0=d, width=0, walls=15,
+                               sweeps=16)
+        errs[N] = (np.abs(U - Ue)[1:-1, 1:-1].max(), np.abs(V - Ve)[1:-1, :].max(), np.abs(W - We)[:, 1:-1].max())
+    assert max(errs[64]) < 1e-6 and max(errs[128]) < 1e-7, errs
+    assert all(a / b > 6 for a, b in zip(errs[64], errs[128])), errs
+    u1, _, _ = pr_mode_state_damped(math.pi, 2 * math.pi, 0.25 / 64, 40, d / 2)
+    u2, _, _ = pr_mode_state_damped(math.pi, 2 * math.pi, 0.25 / 64, 40, d)
+    assert abs(u1 - u2) > 100 * max(errs[64])
+
+
+def _pulse_energy(method, U, V, W, h):
+    return float((U[1:-1, 1:-1] ** 2).sum() + (V[1:-1, :] ** 2).sum() + (W[:, 1:-1] ** 2).sum()) * h * h
+
+
+@pytest.mark.parametrize("method", [O.CFD, O.MFD])
+def test_damping_layers_absorb_an_outgoing_pulse(method):
+    """A Gaussian pulse in a 128^2 box with 24-cell layers on all four walls:
+    the energy never grows, and once the wave has reached the walls the
+    energy left is a few per cent of what the reflecting box keeps."""
+    N = 128
+    h = 1.0 / N
+    x = inputs.pressure_coords(method, N, h)
+    U = np.exp(-((x[None, :] - 0.5) ** 2 + (x[:, None] - 0.5) ** 2) / (2 * 0.03 ** 2))
+    U[0, :] = U[-1, :] = U[:, 0] = U[:, -1] = 0.0
+    sh = O.shapes(method, N, N)
+    V, W = np.zeros(sh["V"]), np.zeros(sh["W"])
+    dt = 0.4 * h
+    kw = dict(h=h, dt=dt, nsteps=100, sweeps=8)
+    e0 = _pulse_energy(method, U, V, W, h)
+    free = (U, V, W)
+    damped = (U, V, W)
+    ed = [e0]
+    for _ in range(6):                       # 600 steps: t = 1.875, the front well past the walls
+        free = O.run(method, *free, **kw)
+        damped = O.run_damped(method, *damped, d0=60.0, width=24, walls=15, **kw)
+        ed.append(_pulse_energy(method, *damped, h))
+    ef = _pulse_energy(method, *free, h)
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(ed, ed[1:])), ed
+    assert ed[-1] < 0.03 * ef, (ed[-1], ef)
