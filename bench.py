@@ -244,12 +244,27 @@ def batch_case(steps, count):
     for pb in probs:
         pb.run(1)
     t_alone = timed(lambda: [pb.run(steps) for pb in probs])
+    # the same batch after adi_autotune on every problem (outside the timed
+    # region: it times each problem's own passes)
+    def choice(pl):
+        return pl["tile_shape"] if pl["kernel"] == adi.KERNEL_SINGLE else pl["tile_order"]
+    before = [[choice(pb.plan(d)) for d in (0, 1)] for pb in probs]
+    t0 = time.perf_counter()
+    for pb in probs:
+        pb.autotune(reps=5)
+    t_tune = time.perf_counter() - t0
+    changed = sum(choice(pb.plan(d)) != before[i][d] for i, pb in enumerate(probs) for d in (0, 1))
+    b = adi.Batch(probs, st, graph=True)
+    b.run(2)
+    t_tuned = timed(lambda: b.run(steps))
+    b.close()
     for pb in probs:
         pb.close()
     return {"problems": count, "cells": cells, "steps": steps,
             "batched_pt_steps_s": cells * steps / t_batch, "alone_pt_steps_s": cells * steps / t_alone,
-            "speedup": t_alone / t_batch, "batched_s": t_batch, "alone_s": t_alone,
-            "grouped_launches": launches}
+            "batched_tuned_pt_steps_s": cells * steps / t_tuned,
+            "speedup": t_alone / t_batch, "batched_s": t_batch, "alone_s": t_alone, "tuned_s": t_tuned,
+            "tuning_s": t_tune, "choices_changed": changed, "grouped_launches": launches}
 
 
 class PinnedPool:
@@ -509,7 +524,9 @@ def main():
     if args.batch_steps > 0:
         bc = batch_case(args.batch_steps, args.batch_count)
         print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "
-              f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched, {bc['alone_pt_steps_s']:.4g} one at a time "
+              f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched, {bc['batched_tuned_pt_steps_s']:.4g} after "
+              f"autotuning ({bc['choices_changed']} of {2 * bc['problems']} choices changed, "
+              f"{bc['tuning_s']:.3g} s of tuning), {bc['alone_pt_steps_s']:.4g} one at a time "
               f"({bc['speedup']:.2f}x), {bc['grouped_launches']} grouped launches", file=sys.stderr, flush=True)
         out["batched"] = bc
     if args.serve_requests > 0:

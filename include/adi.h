@@ -245,6 +245,63 @@ int adi_set_check(adi_problem* pb, int64_t every, double max_abs);
  * whether a non-finite value was seen (waits for the problem's work). */
 int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite);
 
+/* Launch autotuner.  The line passes (Section 3: one implicit sweep stage
+ * and the next stage's explicit part per launch) have launch choices that
+ * change their speed but not what they compute: the single-window kernel's
+ * tile shape (window of 512, 256 or 128 slots with 32/64 lines per
+ * workgroup in FP32, 16/32/64 in FP64; every shape whose window holds the
+ * line is a candidate) and the wave-per-line kernel's order of tiles across
+ * the eight XCDs (0: each XCD takes whole line groups, 1: whole windows, 2:
+ * no XCD mapping).  adi_autotune times each candidate of each direction's
+ * sweep pass on the bound problem's own data (reps passes per timing, 0 =
+ * 10; three rounds, best kept), keeps the fastest (the default stays unless
+ * another is more than 1% faster), and stores the choice in a process-wide
+ * cache keyed by (device architecture, method, dtype, slots per line,
+ * lines, window margin, kernel).  Problems created later with the same key
+ * (adi_create, batches, servers, adi_run_noalloc) start with the cached
+ * choice.  With the environment variable ADI_TUNE_CACHE naming a file, the
+ * cache is read from it at first use and rewritten after each tuning
+ * (ADI_EINVAL if it cannot be written; the choice is kept in memory).
+ * pass_us (optional, 2 values) receives the chosen pass time per direction
+ * in microseconds (0 where a direction has no choice).  The current state
+ * goes to the bound arrays first; the next run starts from them.  Tile
+ * order changes nothing in the results; a tile shape may change FP rounding
+ * of the single-window compact solves.  Direct solves (sweeps 0) have no
+ * choices: the call returns at once.  Waits for the problem's stream; call
+ * it before creating batches that hold the problem.  ADI_ENOTREADY before
+ * adi_bind. */
+int adi_autotune(adi_problem* pb, int reps, double* pass_us);
+
+enum { ADI_KERNEL_SINGLE = 1, ADI_KERNEL_WAVE = 3, ADI_KERNEL_DIRECT = 4 };
+
+/* The launch plan of one direction (dir 0: the x lines, along which i
+ * runs; 1: the y lines). */
+typedef struct adi_plan_info {
+    int kernel;          /* ADI_KERNEL_SINGLE (one window per line), ADI_KERNEL_WAVE
+                            (wave per line, windows of 512 slots) or ADI_KERNEL_DIRECT */
+    int lines;           /* lines of the direction */
+    int slots;           /* velocity slots per line */
+    int windows;         /* windows per line */
+    int window;          /* slots per window (direct solves: output slots per inner window) */
+    int margin;          /* overlap margin of the multi-window plans (slots per side) */
+    int lines_per_group; /* lines per workgroup */
+    int workgroups;      /* workgroups of one pass */
+    int tile_shape;      /* single-window tile shape 0, 1, 2 (windows 512, 256, 128); -1 otherwise */
+    int tile_order;      /* wave-per-line tile order 0, 1, 2; -1 otherwise */
+    int tuned;           /* 1 when the choice came from adi_autotune or its cache */
+    int reserved[5];
+} adi_plan_info;
+
+int adi_get_plan(const adi_problem* pb, int dir, adi_plan_info* info);
+
+/* Pin one direction's launch choice by hand: the tile shape (0, 1, 2) of a
+ * single-window plan, whose window must hold the line, or the tile order
+ * (0, 1, 2) of a wave-per-line plan; ADI_EINVAL for any other value and for
+ * direct solves.  Allowed before or after adi_bind and between runs (the
+ * resident state is kept; the call waits for the problem's stream).  The
+ * cache is not changed; adi_get_plan then reports tuned = 0. */
+int adi_set_plan(adi_problem* pb, int dir, int choice);
+
 /* Write the state of the current time level m into the device arrays U, V,
  * W (shapes and leading dimensions of the bound arrays; NULL = the bound
  * array itself) and wait for it.  Only the entries the method updates are

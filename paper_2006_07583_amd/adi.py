@@ -21,6 +21,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
            "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_check", "adi_check_stats",
+           "adi_autotune", "adi_get_plan", "adi_set_plan",
            "adi_set_forcing", "adi_set_boundary", "adi_set_damping",
            "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
@@ -51,6 +52,14 @@ class AdiSignal(ctypes.Structure):
 
 
 SIGNAL_RICKER, SIGNAL_COS = 1, 2
+
+KERNEL_SINGLE, KERNEL_WAVE, KERNEL_DIRECT = 1, 3, 4
+
+
+class AdiPlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("kernel", "lines", "slots", "windows", "window", "margin",
+                                              "lines_per_group", "workgroups", "tile_shape", "tile_order",
+                                              "tuned")] + [("reserved", ctypes.c_int32 * 5)]
 
 
 def _signal(g):
@@ -113,6 +122,9 @@ def lib():
         L.adi_set_boundary.argtypes = [vp, ctypes.POINTER(AdiSignal)]
         L.adi_set_damping.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.adi_check_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.adi_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.adi_get_plan.argtypes = [vp, ctypes.c_int, ctypes.POINTER(AdiPlanInfo)]
+        L.adi_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
@@ -287,6 +299,25 @@ class Problem:
         m, nf = ctypes.c_double(), ctypes.c_int()
         _check(lib().adi_check_stats(self._h, ctypes.byref(m), ctypes.byref(nf)))
         return m.value, bool(nf.value)
+
+    def autotune(self, reps: int = 0):
+        """Time the launch choices of both directions' line passes and keep
+        the fastest (adi_autotune); returns the chosen pass times (us) of
+        the x and y passes."""
+        us = (ctypes.c_double * 2)()
+        _check(lib().adi_autotune(self._h, int(reps), us))
+        return us[0], us[1]
+
+    def plan(self, direction: int) -> dict:
+        """The launch plan of the x (0) or y (1) lines (adi_get_plan)."""
+        info = AdiPlanInfo()
+        _check(lib().adi_get_plan(self._h, int(direction), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in AdiPlanInfo._fields_ if k != "reserved"}
+
+    def set_plan(self, direction: int, choice: int) -> "Problem":
+        """Pin the tile shape / tile order of one direction (adi_set_plan)."""
+        _check(lib().adi_set_plan(self._h, int(direction), int(choice)))
+        return self
 
     def set_tolerance(self, eps: float, min_sweeps: int = 2) -> "Problem":
         """Tolerance-tested stages (adi_set_tolerance); eps = 0 restores the

@@ -22,7 +22,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -99,7 +103,119 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps, double cfl)
                               : (p.ver == 2 ? adi::line2_lanes(dtype) : adi::line3_lanes(dtype));
     // the wave-per-line kernel indexes its rows r = q + 1 (row 0 all zeros)
     p.nlg = (nlines + (p.ver == 3 ? 1 : 0) + lw - 1) / lw;
+    p.torder = adi::line3_torder(dtype, method);
     return p;
+}
+
+// Single-window tile shape cfg for a plan (lines per workgroup follow it).
+void set_cfg(Plan& p, int dtype, int cfg) {
+    p.cfg = cfg;
+    const int lw = adi::line_lanes(dtype, cfg);
+    p.nlg = (p.nlines + lw - 1) / lw;
+}
+
+// ---- tuned plans ----
+//
+// The launch choices the autotuner times: the tile shape of the
+// single-window kernel (every shape whose window holds the line) and the
+// tile order of the wave-per-line kernel.  The other kernels have none.
+int plan_choices(const Plan& p, int* c) {
+    int k = 0;
+    if (p.ver == 1) {
+        for (int cfg = 0; cfg < adi::LINE_NCFG; ++cfg)
+            if (p.ns <= adi::line_ws(cfg)) c[k++] = cfg;
+    } else if (p.ver == 3) {
+        for (int o = 0; o < 3; ++o) c[k++] = o;
+    }
+    return k;
+}
+
+int plan_choice(const Plan& p) { return p.ver == 1 ? p.cfg : p.torder; }
+
+void apply_choice(Plan& p, int dtype, int ch) {
+    if (p.ver == 1)
+        set_cfg(p, dtype, ch);
+    else
+        p.torder = ch;
+}
+
+// Process-wide cache of tuned choices: (device architecture, method, dtype,
+// slots per line, lines, margin, kernel) -> choice.  With the environment
+// variable ADI_TUNE_CACHE naming a file, the cache reads it when a plan is
+// first made with that name set (entries of the file replace those held)
+// and writes itself back to it after each tuning.
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+std::string g_tune_path;   // the file last read
+std::string g_arch[64];
+
+std::string device_arch() {   // caller holds g_tune_mu
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return "unknown";
+    if (g_arch[dev].empty()) {
+        hipDeviceProp_t pr;
+        g_arch[dev] = hipGetDeviceProperties(&pr, dev) == hipSuccess ? std::string(pr.gcnArchName) : "unknown";
+        for (char& ch : g_arch[dev])
+            if (ch == ' ') ch = '_';
+    }
+    return g_arch[dev];
+}
+
+TuneKey tune_key(const std::string& arch, int method, int dtype, const Plan& p) {
+    return TuneKey(arch, method, dtype, p.ns, p.nlines, p.H, p.ver);
+}
+
+// Cache file lines: "adi-tune arch method dtype ns nlines H ver choice".
+void tune_load() {   // caller holds g_tune_mu
+    const char* path = std::getenv("ADI_TUNE_CACHE");
+    if (!path || !*path || g_tune_path == path) return;
+    g_tune_path = path;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string tag, arch;
+        int v[7];
+        if (!(in >> tag >> arch) || tag != "adi-tune") continue;
+        bool ok = true;
+        for (int& x : v) ok = ok && (bool)(in >> x);
+        if (ok) g_tune[TuneKey(arch, v[0], v[1], v[2], v[3], v[4], v[5])] = v[6];
+    }
+}
+
+int tune_save() {   // caller holds g_tune_mu
+    const char* path = std::getenv("ADI_TUNE_CACHE");
+    if (!path || !*path) return ADI_OK;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        for (const auto& kv : g_tune) {
+            const auto& k = kv.first;
+            f << "adi-tune " << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
+              << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k) << ' '
+              << kv.second << '\n';
+        }
+        if (!f) return fail(ADI_EINVAL, "cannot write the tuning cache %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return fail(ADI_EINVAL, "cannot replace the tuning cache %s", path);
+    return ADI_OK;
+}
+
+// A cached choice for the plan, if any (valid for the plan's kernel).
+void apply_tuned(Plan& p, int method, int dtype) {
+    int c[8];
+    const int nc = plan_choices(p, c);
+    if (nc == 0) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    const auto it = g_tune.find(tune_key(device_arch(), method, dtype, p));
+    if (it == g_tune.end()) return;
+    for (int i = 0; i < nc; ++i)
+        if (c[i] == it->second) {
+            apply_choice(p, dtype, it->second);
+            p.tuned = true;
+        }
 }
 
 
@@ -202,7 +318,7 @@ Layout layout(const adi_problem& pb) {
         // can go straight into the target (slot-major column passes)
         const bool spare = d == last_dir(p) && (d == 0 || D.lm);
         const size_t sizes[13] = {pe, ve, ve, pb.hasK ? pe : 0, hasR ? ve : 0, comp ? pe : 0, comp ? ve : 0,
-                                  comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::line_ws(pl.cfg) : 0,
+                                  comp ? ve : 0, cfd && pl.ver == 1 ? (size_t)6 * adi::LINE_WS : 0,
                                   spare ? ve : 0, spare && comp ? ve : 0, pb.fsig.kind ? pe : 0,
                                   pb.bsig.kind ? (size_t)6 * (pl.nlines + 64) : 0};
         for (int i = 0; i < 13; ++i) {
@@ -307,6 +423,9 @@ void derive(adi_problem* pb) {
     if (p.sweeps == 0) {
         direct_plan(pb->px, p);
         direct_plan(pb->py, p);
+    } else {
+        apply_tuned(pb->px, p.method, p.dtype);
+        apply_tuned(pb->py, p.method, p.dtype);
     }
     for (int d = 0; d < 2; ++d) {
         const Plan& pl = d == 0 ? pb->px : pb->py;
@@ -345,6 +464,7 @@ adi::LinePassArgs<T> base_args(const adi_problem& pb, const Plan& pl, const void
     a.gbase = 0;
     a.gstride = 1;
     a.gcount = pl.nwin;
+    a.torder = pl.torder;
     return a;
 }
 
@@ -643,8 +763,16 @@ struct EpsLayout {
     int* go;
     long long* stats;
 };
+// (the most tiles any tile shape of the plan's kernel launches: the
+// autotuner may change the shape after the buffer exists)
+int max_tiles(const Plan& p, int dtype) {
+    if (p.ver != 1) return p.nlg * p.nwin;
+    int lw = adi::line_lanes(dtype, 0);
+    for (int c = 1; c < adi::LINE_NCFG; ++c) lw = std::min(lw, adi::line_lanes(dtype, c));
+    return (p.nlines + lw - 1) / lw;
+}
 size_t eps_tiles(const adi_problem* pb) {
-    return (size_t)std::max(pb->px.nlg * pb->px.nwin, pb->py.nlg * pb->py.nwin);
+    return (size_t)std::max(max_tiles(pb->px, pb->p.dtype), max_tiles(pb->py, pb->p.dtype));
 }
 size_t eps_bytes(const adi_problem* pb) { return 4 * eps_tiles(pb) * sizeof(double) + 64 + 2 * sizeof(long long); }
 EpsLayout eps_layout(const adi_problem* pb) {
@@ -900,6 +1028,106 @@ int run_impl(adi_problem* pb, int64_t nsteps) {
     return ADI_OK;
 }
 
+// Factor tables of a direction's single-window compact plan into its coef
+// region (nothing for other plans); host (6 LINE_WS values) must live until
+// the copy has run.
+template <typename T>
+int upload_tables(adi_problem* pb, int d, T* host, hipStream_t st) {
+    const Plan& pl = d == 0 ? pb->px : pb->py;
+    if (pb->p.method != ADI_CFD || pl.ver != 1) return ADI_OK;
+    double t64[6 * adi::LINE_WS];
+    build_tables(pl, t64);
+    const int cnt = 6 * adi::line_ws(pl.cfg);
+    for (int i = 0; i < cnt; ++i) host[i] = (T)t64[i];
+    HIP_TRY(hipMemcpyAsync(pb->d[d].coef, host, cnt * sizeof(T), hipMemcpyHostToDevice, st), "factor tables");
+    return ADI_OK;
+}
+
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~EventPair() {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// Times every launch choice of each direction's sweep pass on the problem's
+// own data and keeps the fastest (adi_autotune).  The state goes to the
+// bound arrays first; the timed passes advance a copy of it in the
+// workspace, and the next run starts again from the bound arrays.
+template <typename T>
+int autotune_impl(adi_problem* pb, int reps, double* pass_us) {
+    const auto& p = pb->p;
+    hipStream_t st = pb->st;
+    if (pb->ready) {
+        const int rc = materialize_ready<T>(pb, (T*)pb->U, (T*)pb->V, (T*)pb->W);
+        if (rc != ADI_OK) return rc;
+        pb->ready = false;
+    }
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.e[0]), "tuning events");
+    HIP_TRY(hipEventCreate(&ev.e[1]), "tuning events");
+    int rc = adi::run_begin<T>(pb, st);
+    if (rc != ADI_OK) return rc;
+    static thread_local T host[6 * adi::LINE_WS];
+    std::string arch;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        arch = device_arch();
+    }
+    for (int d = 0; d < 2; ++d) {
+        Plan& pl = d == 0 ? pb->px : pb->py;
+        pass_us[d] = 0.0;
+        int c[8];
+        const int nc = plan_choices(pl, c);
+        if (nc == 0) continue;
+        const int half = p.order == 0 ? d : 1 - d;
+        auto pass = [&]() -> int {
+            const auto desc = adi::run_pass<T>(pb, 0, half, false, nullptr);
+            HIP_TRY(adi::launch_pass<T>(desc, st), "tuning pass");
+            return ADI_OK;
+        };
+        const Plan dflt = make_plan(p.method, p.dtype, pl.n, pl.nlines, p.sweeps, p.dt * p.c_max / p.h);
+        double t[8];
+        for (int i = 0; i < nc; ++i) t[i] = 1e300;
+        // three rounds over the choices, the best time of each kept
+        for (int round = 0; round < 3; ++round)
+            for (int i = 0; i < nc; ++i) {
+                apply_choice(pl, p.dtype, c[i]);
+                if ((rc = upload_tables<T>(pb, d, host, st)) != ADI_OK) return rc;
+                HIP_TRY(hipStreamSynchronize(st), "factor tables");   // host is reused
+                for (int w = 0; w < 2; ++w)
+                    if ((rc = pass()) != ADI_OK) return rc;
+                HIP_TRY(hipEventRecord(ev.e[0], st), "tuning events");
+                for (int r = 0; r < reps; ++r)
+                    if ((rc = pass()) != ADI_OK) return rc;
+                HIP_TRY(hipEventRecord(ev.e[1], st), "tuning events");
+                HIP_TRY(hipEventSynchronize(ev.e[1]), "tuning events");
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]), "tuning events");
+                t[i] = std::min(t[i], 1e3 * ms / reps);
+            }
+        // the default choice stays unless another is more than 1% faster
+        int best = 0;
+        for (int i = 0; i < nc; ++i)
+            if (c[i] == plan_choice(dflt)) best = i;
+        for (int i = 0; i < nc; ++i)
+            if (t[i] < 0.99 * t[best]) best = i;
+        apply_choice(pl, p.dtype, c[best]);
+        pl.tuned = true;
+        if ((rc = upload_tables<T>(pb, d, host, st)) != ADI_OK) return rc;
+        HIP_TRY(hipStreamSynchronize(st), "tuning");
+        pass_us[d] = t[best];
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        g_tune[tune_key(arch, p.method, p.dtype, pl)] = c[best];
+    }
+    HIP_TRY(hipStreamSynchronize(st), "tuning");
+    pb->ready = false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return tune_save();
+}
+
 // ADI_ENUMERIC when the health check has seen a non-finite value or a
 // magnitude above its bound (after the problem's stream has drained).
 int health_status(adi_problem* pb) {
@@ -1051,14 +1279,9 @@ int bind_materials(adi_problem* pb, const T* K, const T* Rv, const T* Rw, int64_
     // kernel uses compile-time constants); the host copies live until the
     // synchronisation below
     T tab[2][6 * adi::LINE_WS];
-    for (int d = 0; d < 2 && p.method == ADI_CFD; ++d) {
-        const Plan& pl = d == 0 ? pb->px : pb->py;
-        if (pl.ver != 1) continue;
-        double t64[6 * adi::LINE_WS];
-        build_tables(pl, t64);
-        const int cnt = 6 * adi::line_ws(pl.cfg);
-        for (int i = 0; i < cnt; ++i) tab[d][i] = (T)t64[i];
-        HIP_TRY(hipMemcpyAsync(pb->d[d].coef, tab[d], cnt * sizeof(T), hipMemcpyHostToDevice, st), "factor tables");
+    for (int d = 0; d < 2; ++d) {
+        const int rc = upload_tables<T>(pb, d, tab[d], st);
+        if (rc != ADI_OK) return rc;
     }
     // distributed forcing in both directions' layouts
     if (pb->fsig.kind)
@@ -1397,6 +1620,79 @@ int adi_set_check(adi_problem* pb, int64_t every, double max_abs) {
     HIP_TRY(hipGetLastError(), "health check reset");
     pb->chk_every = every;
     pb->chk_max = max_abs;
+    return ADI_OK;
+}
+
+int adi_autotune(adi_problem* pb, int reps, double* pass_us) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (!pb->bound) return fail(ADI_ENOTREADY, "problem has no bound arrays");
+    if (reps < 0 || reps > 1000) return fail(ADI_EINVAL, "reps must be in [0, 1000]");
+    double us[2] = {0.0, 0.0};
+    if (pb->p.sweeps == 0) {
+        if (pass_us) pass_us[0] = pass_us[1] = 0.0;
+        return ADI_OK;   // the direct solves have no launch choices
+    }
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    const int r = reps ? reps : 10;
+    const int rc = pb->p.dtype == ADI_FP64 ? autotune_impl<double>(pb, r, us) : autotune_impl<float>(pb, r, us);
+    if (pass_us) {
+        pass_us[0] = us[0];
+        pass_us[1] = us[1];
+    }
+    return rc;
+}
+
+int adi_set_plan(adi_problem* pb, int dir, int choice) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (x lines) or 1 (y lines)");
+    Plan& pl = dir == 0 ? pb->px : pb->py;
+    int c[8];
+    const int nc = pb->p.sweeps == 0 ? 0 : plan_choices(pl, c);
+    bool ok = false;
+    for (int i = 0; i < nc; ++i) ok = ok || c[i] == choice;
+    if (!ok) return fail(ADI_EINVAL, "choice %d is not a launch choice of this plan (%d choices)", choice, nc);
+    apply_choice(pl, pb->p.dtype, choice);
+    pl.tuned = false;
+    if (!pb->bound) return ADI_OK;
+    // the tables of the new tile shape, after the queued passes that read
+    // the old ones
+    HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    double host64[6 * adi::LINE_WS];
+    float host32[6 * adi::LINE_WS];
+    const int rc = pb->p.dtype == ADI_FP64 ? upload_tables<double>(pb, dir, host64, pb->st)
+                                           : upload_tables<float>(pb, dir, host32, pb->st);
+    if (rc != ADI_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(pb->st), "factor tables");
+    return ADI_OK;
+}
+
+int adi_get_plan(const adi_problem* pb, int dir, adi_plan_info* info) {
+    g_err.clear();
+    if (!pb || !info) return fail(ADI_EINVAL, "NULL argument");
+    if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (x lines) or 1 (y lines)");
+    const Plan& pl = dir == 0 ? pb->px : pb->py;
+    std::memset(info, 0, sizeof(*info));
+    info->kernel = pb->p.sweeps == 0 ? ADI_KERNEL_DIRECT
+                                     : (pl.ver == 1 ? ADI_KERNEL_SINGLE : (pl.ver == 3 ? ADI_KERNEL_WAVE : 0));
+    info->lines = pl.nlines;
+    info->slots = pl.ns;
+    if (pb->p.sweeps == 0) {
+        info->windows = pl.dnwin;
+        info->window = pl.dS;
+        info->margin = pl.dH;
+        return ADI_OK;
+    }
+    info->windows = pl.nwin;
+    info->window = pl.ver == 1 ? adi::line_ws(pl.cfg) : adi::LINE_WS;
+    info->margin = pl.ver == 1 ? 0 : pl.H;
+    info->lines_per_group = pl.ver == 1 ? adi::line_lanes(pb->p.dtype, pl.cfg) : adi::line3_lanes(pb->p.dtype);
+    info->workgroups = pl.nlg * pl.nwin;
+    info->tile_shape = pl.ver == 1 ? pl.cfg : -1;
+    info->tile_order = pl.ver == 3 ? pl.torder : -1;
+    info->tuned = pl.tuned ? 1 : 0;
     return ADI_OK;
 }
 

@@ -60,6 +60,9 @@ struct LinePassArgs {
     // dmpiw = 0.  ah = dt / 2.
     T dmp0, dmpiw, ah;
     int dmpm;
+    // wave-per-line kernel: order of the tiles across the XCDs (0: line
+    // group by line group, 1: window by window, 2: launch order)
+    int torder;
 };
 
 // A grouped launch: the passes items[0..nitems) (any problems, any
@@ -114,6 +117,7 @@ template <typename T>
 hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp = false,
                               bool full = false);
 int line3_lanes(int dtype);
+int line3_torder(int dtype, int method);
 
 // Tolerance-tested stages (LinePassArgs::eps_part): a pass is `attempts`
 // launches, attempt j with K = kmin + 2 j sweeps running while go[j] != 0

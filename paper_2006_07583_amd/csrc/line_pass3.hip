@@ -1060,8 +1060,9 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     }
 }
 
-template <typename T, int METHOD>
-constexpr bool kGroupOrder = METHOD == LINE_CFD || sizeof(T) == 4;
+// Default tile order across the XCDs (LinePassArgs::torder), the faster of
+// the two as measured: line group by line group, except for mimetic FP64.
+int line3_torder(int dtype, int method) { return method == LINE_CFD || dtype != 1 ? 0 : 1; }
 
 // The tolerance-tested form holds a spare array and the change sums: it
 // runs at a lower occupancy (2 waves per SIMD in FP32, 1 in FP64) rather
@@ -1074,14 +1075,16 @@ __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(kWpe<T, EPS>, kWpe<T, EPS>)))
 line_pass3_kernel(const LinePassArgs<T> a) {
     __shared__ __align__(16) T smem[K3<T>::TILE];
-    // Each XCD takes a contiguous range of the ordered tiles: line group by
-    // line group (all windows of a group in turn) or window by window,
-    // whichever measured faster for the variant.
+    // Workgroups go round-robin to the eight XCDs; with torder 0 and 1 each
+    // XCD takes a contiguous range of the ordered tiles, line group by line
+    // group (all windows of a group in turn) or window by window; torder 2
+    // keeps the launch order (torder: a default per variant, or the
+    // autotuner's choice).
     const int nb = a.nlg * a.nwin;
     const int per = (nb + 7) / 8;
-    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    const int t = a.torder == 2 ? (int)blockIdx.x : (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (t >= nb) return;
-    const int tile = kGroupOrder<T, METHOD> ? (t % a.nwin) * a.nlg + t / a.nwin : t;
+    const int tile = a.torder == 0 ? (t % a.nwin) * a.nlg + t / a.nwin : t;
     lp3_body<T, METHOD, MODE, EPS, COMP, FULL>(a, tile, smem);
 }
 

@@ -15,6 +15,8 @@ struct Plan {
     int ver = 1;   // 1: single-window kernel (line_pass.hip); multi-window: 2 (line_pass2.hip,
                    // compensated mode) or 3 (line_pass3.hip)
     int cfg = 0;   // tile shape of the single-window kernel
+    int torder = 0;   // tile order of the wave-per-line kernel (LinePassArgs::torder)
+    bool tuned = false;   // cfg / torder from the autotuner (adi_autotune)
     int seg = 0;   // slots per lane segment of the multi-window kernel
     // direct (exact) line solves: output slots per window (and of the two
     // end windows), margin, windows,

@@ -1,0 +1,217 @@
+"""The launch autotuner (adi_autotune) and the plan query (adi_get_plan)
+through the C ABI.
+
+The wave-per-line kernel's tile order only changes which workgroup takes
+which tile: every order gives the same run bit for bit.  The
+single-window kernel's tile shape may change the rounding of the compact
+solves: every shape, and the tuned choice, match the oracle at the parity bar (FP64 max-rel 1e-12,
+FP32 relative L2 1e-4).  Problems created after a tuning with the same key
+start with the tuned choice, a batch of them equals their solo runs bit for
+bit, and the file ADI_TUNE_CACHE names keeps the choices."""
+import math
+
+import torch
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_07583_amd import adi, inputs
+from tests.gpu_util import log, max_rel, rel_l2, written_parts
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-4
+
+
+def setup(method, nx, ny, seed):
+    h = 1.0 / max(nx, ny)
+    f = inputs.random_fields(method, nx, ny, seed)
+    med = inputs.random_medium(method, nx, ny, seed + 1)
+    cmax = math.sqrt(med["K"].max() * max(med["Rv"].max(), med["Rw"].max()))
+    src = {"i": max(1, nx // 3), "j": max(1, ny // 2), "f0": 4.0, "t0": 0.1, "amp": 1.0}
+    return h, f, med, cmax, 0.6 * h / cmax, src
+
+
+def problem(method, dtype, nx, ny, h, f, med, cmax, dt, src):
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", tdt)
+    x = [t(f[k]) for k in "UVW"]
+    p = adi.make_params(method, dtype, nx, ny, h, dt, cmax, src=src)
+    return adi.Problem(p).bind(*x, t(med["K"]), t(med["Rv"]), t(med["Rw"])), x
+
+
+def np3(ts):
+    return tuple(t.double().cpu().numpy() for t in ts)
+
+
+def check_oracle(method, dtype, got, f, med, h, dt, src, nsteps):
+    ref = O.run(method, f["U"], f["V"], f["W"], h=h, dt=dt, nsteps=nsteps, sweeps=6, K=med["K"], Rv=med["Rv"],
+                Rw=med["Rw"], src=src)
+    for g, r in zip(written_parts(method, *got), written_parts(method, *ref)):
+        err = max_rel(g, r) if dtype == adi.FP64 else rel_l2(g, r)
+        assert err <= (TOL64 if dtype == adi.FP64 else TOL32), err
+
+
+# (method, dtype, nx, ny): wave-per-line both ways, mixed, single-window both
+# ways (every tile shape a candidate along short lines), compensated
+CASES = [
+    (adi.CFD, adi.FP32, 610, 530),
+    (adi.MFD, adi.FP64, 530, 91),
+    (adi.CFD, adi.FP64, 101, 77),
+    (adi.MFD, adi.FP32, 201, 150),
+    (adi.CFD, adi.FP32C, 620, 100),
+]
+
+
+def choices(pl):
+    if pl["kernel"] == adi.KERNEL_WAVE:
+        return [0, 1, 2]
+    return [c for c, w in enumerate((512, 256, 128)) if w >= pl["slots"]]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_every_launch_choice_and_the_tuned_one(case):
+    """Each direction's choices pinned in turn between two runs (the
+    resident state is kept): tile orders give the default run bit for bit,
+    tile shapes match the oracle; then a tuned run matches the oracle."""
+    method, dtype, nx, ny = case
+    h, f, med, cmax, dt, src = setup(method, nx, ny, 17 * nx + ny)
+    log(f"case autotune {case}")
+    a, xa = problem(method, dtype, nx, ny, h, f, med, cmax, dt, src)
+    before = [a.plan(d) for d in (0, 1)]
+    a.run(2)
+    a.run(3)
+    a.get_state()
+    check_oracle(method, dtype, np3(xa), f, med, h, dt, src, 5)
+    for d in (0, 1):
+        for c in choices(before[d]):
+            b, xb = problem(method, dtype, nx, ny, h, f, med, cmax, dt, src)
+            b.run(2)
+            b.set_plan(d, c)
+            pl = b.plan(d)
+            assert pl["tuned"] == 0 and c == (pl["tile_order"] if pl["kernel"] == adi.KERNEL_WAVE else pl["tile_shape"])
+            b.run(3)
+            b.get_state()
+            if pl["kernel"] == adi.KERNEL_WAVE:
+                for u, v in zip(xa, xb):
+                    assert torch.equal(u, v), (d, c)
+            else:
+                assert pl["window"] == (512, 256, 128)[c] and pl["lines_per_group"] > 0
+                check_oracle(method, dtype, np3(xb), f, med, h, dt, src, 5)
+            b.close()
+    b, xb = problem(method, dtype, nx, ny, h, f, med, cmax, dt, src)
+    b.run(2)
+    us = b.autotune(reps=5)
+    after = [b.plan(d) for d in (0, 1)]
+    log(f"  plans before {before}\n  after {after}\n  pass us {us}")
+    for d in (0, 1):
+        pl = after[d]
+        assert pl["tuned"] == 1 and us[d] > 0
+        assert pl["kernel"] == before[d]["kernel"] in (adi.KERNEL_WAVE, adi.KERNEL_SINGLE)
+        if pl["kernel"] == adi.KERNEL_WAVE:
+            assert pl["tile_order"] in (0, 1, 2) and pl["tile_shape"] == -1
+            assert pl["window"] == 512 and pl["windows"] >= 2
+        else:
+            assert pl["tile_shape"] in choices(pl) and pl["tile_order"] == -1
+            assert pl["window"] >= pl["slots"] and pl["windows"] == 1
+        assert pl["lines"] == before[d]["lines"] and pl["slots"] == before[d]["slots"]
+    b.run(3)
+    b.get_state()
+    assert b.step_index == 5
+    check_oracle(method, dtype, np3(xb), f, med, h, dt, src, 5)
+    a.close()
+    b.close()
+
+
+def test_cache_reaches_new_problems_and_batches():
+    """Tune one problem per shape; later problems of those shapes start
+    tuned; a graph-replayed batch of them equals their solo runs bit for bit
+    and matches the oracle."""
+    shapes = [(adi.CFD, adi.FP32, 151, 120), (adi.MFD, adi.FP64, 600, 92), (adi.MFD, adi.FP32, 90, 300)]
+    for k, (m, d, nx, ny) in enumerate(shapes):
+        h, f, med, cmax, dt, src = setup(m, nx, ny, 500 + k)
+        pb, _ = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
+        pb.autotune(reps=3)
+        pb.close()
+    # other data, the same shapes (and cfl 0.6, so the same window margins)
+    runs = [(m, d, nx, ny, *setup(m, nx, ny, 900 + k)) for k, (m, d, nx, ny) in enumerate(shapes * 2)]
+    solo = []
+    for m, d, nx, ny, h, f, med, cmax, dt, src in runs:
+        pb, x = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
+        for dd in (0, 1):
+            assert pb.plan(dd)["tuned"] == 1, (m, d, nx, ny, dd, pb.plan(dd))
+        pb.run(6)
+        pb.get_state()
+        solo.append(np3(x))
+        pb.close()
+    st = torch.cuda.Stream()
+    probs, xs = [], []
+    for m, d, nx, ny, h, f, med, cmax, dt, src in runs:
+        tdt = torch.float64 if d == adi.FP64 else torch.float32
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", tdt)
+        x = [t(f[k]) for k in "UVW"]
+        p = adi.make_params(m, d, nx, ny, h, dt, cmax, src=src)
+        probs.append(adi.Problem(p, st).bind(*x, t(med["K"]), t(med["Rv"]), t(med["Rw"])))
+        xs.append(x)
+    torch.cuda.synchronize()
+    b = adi.Batch(probs, st, graph=True)
+    b.run(6)
+    b.sync()
+    b.close()
+    for i, (pb, x) in enumerate(zip(probs, xs)):
+        pb.get_state()
+        for u, v in zip(np3(x), solo[i]):
+            assert np.array_equal(u, v), (i, runs[i][:4])
+        m, d, nx, ny, h, f, med, cmax, dt, src = runs[i]
+        check_oracle(m, d, np3(x), f, med, h, dt, src, 6)
+        pb.close()
+
+
+def test_cache_file(tmp_path, monkeypatch):
+    """A tuning writes its choices to ADI_TUNE_CACHE; a file named there is
+    read when the next plan is made: a hand-written entry pins tile order 2
+    on a new shape."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("ADI_TUNE_CACHE", str(path))
+    m, d, nx, ny = adi.MFD, adi.FP32, 700, 64
+    h, f, med, cmax, dt, src = setup(m, nx, ny, 77)
+    pb, _ = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
+    pb.autotune(reps=3)
+    pl = pb.plan(0)
+    pb.close()
+    lines = [ln.split() for ln in path.read_text().splitlines()]
+    log(f"  cache file {lines}")
+    assert all(ln[0] == "adi-tune" and len(ln) == 9 for ln in lines)
+    arch = lines[0][1]
+    assert arch.startswith("gfx")
+    assert ["adi-tune", arch, str(m), str(d), str(pl["slots"]), str(pl["lines"]), str(pl["margin"]),
+            str(adi.KERNEL_WAVE), str(pl["tile_order"])] in lines
+    # a new shape, by hand: x lines of 801 cells (803 slots) on 70 lines
+    other = tmp_path / "other.txt"
+    other.write_text(f"adi-tune {arch} {m} {d} 803 70 {pl['margin']} {adi.KERNEL_WAVE} 2\n")
+    monkeypatch.setenv("ADI_TUNE_CACHE", str(other))
+    p = adi.make_params(m, d, 801, 70, h, dt, cmax)
+    pb = adi.Problem(p)
+    got = pb.plan(0)
+    assert got["tuned"] == 1 and got["tile_order"] == 2 and got["slots"] == 803 and got["lines"] == 70, got
+    assert pb.plan(1)["tuned"] == 0
+    pb.close()
+
+
+def test_direct_and_unbound_problems():
+    n = 64
+    p = adi.make_params(adi.MFD, adi.FP64, n, n, 1.0 / n, 0.5 / n, 1.0, sweeps=0)
+    pb = adi.Problem(p)
+    assert pb.plan(0)["kernel"] == adi.KERNEL_DIRECT
+    with pytest.raises(adi.AdiError, match="no bound arrays"):
+        pb.autotune()
+    f = inputs.random_fields(adi.MFD, n, n, 3)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float64)
+    pb.bind(t(f["U"]), t(f["V"]), t(f["W"]))
+    assert pb.autotune() == (0.0, 0.0)
+    with pytest.raises(adi.AdiError, match="launch choice"):
+        pb.set_plan(0, 0)
+    with pytest.raises(adi.AdiError, match="dir"):
+        pb.plan(2)
+    pb.close()
