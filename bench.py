@@ -163,6 +163,33 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
             "sweeps_per_pass": stats[1] / stats[0] if stats[0] else float(sweeps)}
 
 
+def stream_ceiling_case(n, dtype, reps=20):
+    """The project's streaming reference kernel (adi_stream_ceiling: three
+    arrays read, two written, (n + 1)^2 elements each, like a line pass's
+    algorithmic traffic): GB/s over `reps` launches timed with events."""
+    import torch
+    from paper_2006_07583_amd import adi
+    tdt = torch.float64 if dtype == adi.FP64 else torch.float32
+    m = ((n + 1) * (n + 1) + 3) // 4 * 4
+    ts = [torch.rand(m, dtype=tdt, device="cuda:0") for _ in range(3)] + \
+         [torch.empty(m, dtype=tdt, device="cuda:0") for _ in range(2)]
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        adi.stream_ceiling(*ts, stream=st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        adi.stream_ceiling(*ts, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    ok = bool(torch.equal(ts[4], ts[1] - ts[0]))
+    nbytes = 5 * m * ts[0].element_size()
+    del ts
+    return {"us": t * 1e6, "GBs": nbytes / t / 1e9, "bytes": nbytes, "correct": ok}
+
+
 def tolerance_case(n, steps):
     """Cost of the tolerance-tested stages on the compact FP32 pass at n^2:
     min_sweeps 6 and cap 8 against the fixed 6-sweep pass, with every stage
@@ -236,6 +263,10 @@ def batch_case(steps, count):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e-3
 
+    b = adi.Batch(probs, st, graph=True, one_stream=True)
+    b.run(2)
+    t_one = timed(lambda: b.run(steps))
+    b.close()
     b = adi.Batch(probs, st, graph=True)
     b.run(2)
     t_batch = timed(lambda: b.run(steps))
@@ -263,6 +294,7 @@ def batch_case(steps, count):
     return {"problems": count, "cells": cells, "steps": steps,
             "batched_pt_steps_s": cells * steps / t_batch, "alone_pt_steps_s": cells * steps / t_alone,
             "batched_tuned_pt_steps_s": cells * steps / t_tuned,
+            "batched_one_stream_pt_steps_s": cells * steps / t_one,
             "speedup": t_alone / t_batch, "batched_s": t_batch, "alone_s": t_alone, "tuned_s": t_tuned,
             "tuning_s": t_tune, "choices_changed": changed, "grouped_launches": launches}
 
@@ -470,6 +502,11 @@ def main():
                   f"{r['pt_steps_s']:.4g} pt-steps/s, {r['t'] / K * 1e3:.3f} ms/step, "
                   f"pass {r['per_pass'] * 1e6:.1f} us, {r['gbs']:.0f} GB/s alg, finite={r['finite']}{err}",
                   file=sys.stderr, flush=True)
+    ceil = {}
+    for d in sorted({adi.FP64 if d == adi.FP64 else adi.FP32 for d in dtypes}):
+        ceil[d] = stream_ceiling_case(n, d)
+        print(f"# stream ceiling {dname[d]}: 3 reads + 2 writes of {(n + 1)}^2 elements, "
+              f"{ceil[d]['us']:.1f} us, {ceil[d]['GBs']:.0f} GB/s", file=sys.stderr, flush=True)
     head = adi.FP32 if adi.FP32 in dtypes else dtypes[0]
     tt = sum(res[(m, head)]["t"] for m in methods)
     value = n * n * K * len(methods) / tt
@@ -498,6 +535,12 @@ def main():
                      "kernel": (f"line_pass3_kernel<{'float' if head == adi.FP32 else 'double'}, {dom}, SWEEP> "
                                 f"({'compact' if dom == 0 else 'mimetic'} line pass)")},
         "variants": variants,
+        # the project's own streaming kernel with a pass's access pattern:
+        # the rate a line pass could reach, and the pass's share of it
+        "stream_ceiling": {dname[d]: {"GB_s": c["GBs"], "us": c["us"], "bytes": c["bytes"],
+                                      "frac_of_peak": c["GBs"] / HBM_PEAK_GBS}
+                           for d, c in ceil.items()},
+        "roofline_frac_of_ceiling": rd["gbs"] / ceil[adi.FP64 if head == adi.FP64 else adi.FP32]["GBs"],
         # how long the FP32 bar (rel-L2 1e-4 against the FP64 oracle) holds on
         # the layered workload (1024^2, measured; tests/test_gpu_workloads.py
         # test_layered_seismic_long_horizons pins it): the compact scheme's
@@ -524,7 +567,8 @@ def main():
     if args.batch_steps > 0:
         bc = batch_case(args.batch_steps, args.batch_count)
         print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "
-              f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched, {bc['batched_tuned_pt_steps_s']:.4g} after "
+              f"{bc['batched_pt_steps_s']:.4g} pt-steps/s batched ({bc['batched_one_stream_pt_steps_s']:.4g} on "
+              f"one stream), {bc['batched_tuned_pt_steps_s']:.4g} after "
               f"autotuning ({bc['choices_changed']} of {2 * bc['problems']} choices changed, "
               f"{bc['tuning_s']:.3g} s of tuning), {bc['alone_pt_steps_s']:.4g} one at a time "
               f"({bc['speedup']:.2f}x), {bc['grouped_launches']} grouped launches", file=sys.stderr, flush=True)

@@ -382,13 +382,19 @@ typedef struct adi_batch adi_batch;
 
 /* Replay the launches of the steady-state steps from a captured hipGraph. */
 #define ADI_BATCH_GRAPH 1
+/* Issue the grouped launches of a half-step one after the other on the
+ * batch stream.  By default they are spread over the batch stream and three
+ * more streams of the batch (fork and join per half-step, captured as
+ * parallel branches with ADI_BATCH_GRAPH): one variant's grid is often too
+ * small to fill the 256 compute units alone. */
+#define ADI_BATCH_ONE_STREAM 2
 
 /* Group count bound problems (any methods, dtypes, sizes, orders) of the
  * current device.  The batch keeps the pointers, not the problems: they must
  * stay alive and bound while the batch is used.  Work is queued on
  * hip_stream (NULL = null stream; ADI_BATCH_GRAPH needs a created stream),
  * ordered after each problem's own stream and before later work on it.
- * flags: 0 or ADI_BATCH_GRAPH. */
+ * flags: 0 or a combination of ADI_BATCH_GRAPH and ADI_BATCH_ONE_STREAM. */
 int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, int flags,
                      adi_batch** out);
 
@@ -490,6 +496,19 @@ int adi_server_get_stats(adi_server* s, adi_server_stats* st);
 /* Wait for every submitted request, then stop the threads and free the
  * arena, streams and staging buffers. */
 int adi_server_destroy(adi_server* s);
+
+/* ---- Measurement ------------------------------------------------------
+ * The achievable HBM ceiling of a line pass (Section 5 compares kernel
+ * times; the roofline needs the device's reachable rate, not only its
+ * nominal peak).  A pass streams three arrays in and two out, each element
+ * once; this call queues one kernel that does the same with trivial
+ * arithmetic: x = a - c b, y = b - a over n elements of dtype (ADI_FP32 or
+ * ADI_FP64) in 16-byte vectors.  The five device arrays are 16-byte aligned
+ * and n times the element size is a multiple of 16 (else ADI_EINVAL); x and
+ * y must not overlap the inputs.  Queued on hip_stream, no synchronisation:
+ * time it with events on that stream. */
+int adi_stream_ceiling(int dtype, const void* a, const void* b, const void* c, void* x, void* y, int64_t n,
+                       void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -27,9 +27,10 @@ EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
            "adi_batch_destroy",
            "adi_server_params_init", "adi_server_create", "adi_submit", "adi_poll", "adi_wait", "adi_fetch",
-           "adi_request_times", "adi_server_get_stats", "adi_server_destroy")
+           "adi_request_times", "adi_server_get_stats", "adi_server_destroy", "adi_stream_ceiling")
 
 BATCH_GRAPH = 1
+BATCH_ONE_STREAM = 2
 WALL_X0, WALL_X1, WALL_Y0, WALL_Y1 = 1, 2, 4, 8
 REQUEST_HOLD = 1
 
@@ -125,6 +126,7 @@ def lib():
         L.adi_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.adi_get_plan.argtypes = [vp, ctypes.c_int, ctypes.POINTER(AdiPlanInfo)]
         L.adi_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.adi_stream_ceiling.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, i64, vp]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
         L.adi_get_step.argtypes = [vp, ctypes.POINTER(i64)]
@@ -344,11 +346,25 @@ class Problem:
             pass
 
 
+def stream_ceiling(a, b, c, x, y, stream=None):
+    """Queue the streaming reference kernel (adi_stream_ceiling) on torch
+    device tensors of one dtype and length: x = a - c b, y = b - a."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    dt = {torch.float32: FP32, torch.float64: FP64}[a.dtype]
+    ts = (a, b, c, x, y)
+    if any(t.dtype != a.dtype or t.numel() != a.numel() or not t.is_contiguous() for t in ts):
+        raise ValueError("five contiguous tensors of one dtype and length")
+    _check(lib().adi_stream_ceiling(dt, *[ctypes.c_void_p(t.data_ptr()) for t in ts], a.numel(),
+                                    ctypes.c_void_p(stream.cuda_stream)))
+
+
 class Batch:
     """Several bound :class:`Problem` objects advanced together
     (``adi_batch_*``): one grouped launch per kernel variant and half-step."""
 
-    def __init__(self, problems, stream=None, graph=False):
+    def __init__(self, problems, stream=None, graph=False, one_stream=False):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -357,7 +373,8 @@ class Batch:
         arr = (ctypes.c_void_p * len(self._problems))(*[p._h.value for p in self._problems])
         self._h = ctypes.c_void_p()
         _check(lib().adi_batch_create(arr, len(self._problems), ctypes.c_void_p(stream.cuda_stream),
-                                      BATCH_GRAPH if graph else 0, ctypes.byref(self._h)))
+                                      (BATCH_GRAPH if graph else 0) | (BATCH_ONE_STREAM if one_stream else 0),
+                                      ctypes.byref(self._h)))
 
     def run(self, nsteps: int):
         _check(lib().adi_batch_run(self._h, int(nsteps)))

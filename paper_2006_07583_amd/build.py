@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadi.so")
 SOURCES = ["line_pass.hip", "line_pass2.hip", "line_pass3.hip", "line_direct.hip", "adi.hip", "batch.hip",
-           "serve.hip"]
+           "serve.hip", "stream.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from emitting packed FP32 arithmetic

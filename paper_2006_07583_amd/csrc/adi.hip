@@ -785,19 +785,27 @@ static_assert((kMaxAttempts + 1) * sizeof(int) <= 64, "flags");
 // One tolerance-tested pass (Algorithms 3 and 4): attempts with K = kmin,
 // kmin + 2, .. sweeps sweeps, each recomputing the pass from its unchanged
 // inputs and running only while the earlier ones have not converged; the
-// decisions stay on the device.
+// decisions stay on the device.  Each attempt has the windows of its own K
+// (the margin grows with K).
 template <typename T>
 hipError_t launch_tested(adi_problem* pb, adi::PassDesc<T> d) {
-    const int kmin = pb->eps_kmin, kmax = pb->p.sweeps;
+    const auto& p = pb->p;
+    const int kmin = pb->eps_kmin, kmax = p.sweeps;
     const int J = (kmax - kmin) / 2 + 1;
     const EpsLayout L = eps_layout(pb);
-    const int nb = d.a.nlg * d.a.nwin;
+    const Plan& pl = d.dir == 0 ? pb->px : pb->py;
+    const double cfl = p.dt * p.c_max / p.h;
     hipError_t e = hipSuccess;
     for (int j = 0; j < J && e == hipSuccess; ++j) {
         const int K = kmin + 2 * j;
+        const Plan pk = make_plan(p.method, p.dtype, pl.n, pl.nlines, K, cfl);
         d.a.sweeps = K;
+        d.a.H = pk.H;
+        d.a.S = pk.S;
+        d.a.nwin = pk.nwin;
         d.a.eps_part = L.part;
         d.a.eps_go = L.go + j;
+        const int nb = d.a.nlg * d.a.nwin;
         e = adi::launch_pass<T>(d, pb->st);
         if (e == hipSuccess) e = adi::launch_eps_check(L.part, nb, L.go, j, J, pb->eps, K, kmin, kmax, L.stats, pb->st);
     }

@@ -67,6 +67,11 @@ struct adi_batch {
     size_t dmem_bytes = 0;
     int* dtick = nullptr;
     int* dstarts = nullptr;
+    // extra streams of the concurrent grouped launches and the fork / join
+    // events of a half-step
+    static constexpr int kAux = 3;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr, join[kAux] = {};
     hipGraph_t graph = nullptr;   // graph of the last run (kept until the next run)
     hipGraphExec_t exec = nullptr;
     int64_t launches = 0;         // grouped launches in the last run, graph replays included
@@ -164,7 +169,7 @@ void drop_graph(adi_batch* b) {
 }
 
 template <typename T>
-hipError_t launch_group(adi_batch* b, TypedPart<T>& part, int k, int h, size_t gi) {
+hipError_t launch_group(adi_batch* b, TypedPart<T>& part, int k, int h, size_t gi, hipStream_t st) {
     const Group& g = part.groups[k][h][gi];
     adi::GroupArgs<T> ga;
     ga.items = part.ditems + g.first;
@@ -173,15 +178,53 @@ hipError_t launch_group(adi_batch* b, TypedPart<T>& part, int k, int h, size_t g
     ga.nitems = g.count;
     ga.total = g.total;
     ++b->launches;
-    return adi::launch_grouped<T>(part.proto[k][h][gi], ga, b->st);
+    return adi::launch_grouped<T>(part.proto[k][h][gi], ga, st);
+}
+
+// Work of a group, in element-slots: tiles x the slots one tile covers
+// (lines per workgroup x window), for balancing the streams.
+template <typename T>
+double group_work(const TypedPart<T>& part, int k, int h, size_t gi) {
+    const auto& d = part.proto[k][h][gi];
+    const int dt = sizeof(T) == 8 ? 1 : 0;
+    const double per = d.ver == 1 ? (double)adi::line_lanes(dt, d.cfg) * adi::line_ws(d.cfg)
+                                  : (double)adi::line3_lanes(dt) * adi::LINE_WS;
+    return (double)part.groups[k][h][gi].total * per * sizeof(T);
 }
 
 int launch_step(adi_batch* b, int k) {
+    const bool one = (b->flags & ADI_BATCH_ONE_STREAM) != 0;
     for (int h = 0; h < 2; ++h) {
+        // the groups of this half-step, largest first, each to the stream
+        // with the least work so far (the batch stream is stream 0)
+        struct Item { double w; int dt; size_t gi; };
+        std::vector<Item> items;
         for (size_t gi = 0; gi < b->f32.groups[k][h].size(); ++gi)
-            HIP_TRY(launch_group<float>(b, b->f32, k, h, gi), "grouped line pass");
+            items.push_back({group_work(b->f32, k, h, gi), 0, gi});
         for (size_t gi = 0; gi < b->f64.groups[k][h].size(); ++gi)
-            HIP_TRY(launch_group<double>(b, b->f64, k, h, gi), "grouped line pass");
+            items.push_back({group_work(b->f64, k, h, gi), 1, gi});
+        std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.w > y.w; });
+        const int ns = one ? 1 : std::min<int>(1 + adi_batch::kAux, (int)items.size());
+        double load[1 + adi_batch::kAux] = {};
+        if (ns > 1) {
+            HIP_TRY(hipEventRecord(b->fork, b->st), "fork");
+            for (int j = 1; j < ns; ++j) HIP_TRY(hipStreamWaitEvent(b->aux[j - 1], b->fork, 0), "fork");
+        }
+        for (const Item& it : items) {
+            int j = 0;
+            for (int q = 1; q < ns; ++q)
+                if (load[q] < load[j]) j = q;
+            load[j] += it.w;
+            hipStream_t st = j == 0 ? b->st : b->aux[j - 1];
+            if (it.dt == 0)
+                HIP_TRY(launch_group<float>(b, b->f32, k, h, it.gi, st), "grouped line pass");
+            else
+                HIP_TRY(launch_group<double>(b, b->f64, k, h, it.gi, st), "grouped line pass");
+        }
+        for (int j = 1; j < ns; ++j) {
+            HIP_TRY(hipEventRecord(b->join[j - 1], b->aux[j - 1]), "join");
+            HIP_TRY(hipStreamWaitEvent(b->st, b->join[j - 1], 0), "join");
+        }
     }
     hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, b->st, b->dtick, 0, 0);
     HIP_TRY(hipGetLastError(), "step counter");
@@ -296,6 +339,14 @@ void release(adi_batch* b) {
     for (auto e : b->ev)
         if (e) (void)hipEventDestroy(e);
     if (b->done) (void)hipEventDestroy(b->done);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (int j = 0; j < adi_batch::kAux; ++j) {
+        if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+        if (b->aux[j]) {
+            (void)hipStreamSynchronize(b->aux[j]);
+            (void)hipStreamDestroy(b->aux[j]);
+        }
+    }
     if (b->dmem) (void)hipFree(b->dmem);
     delete b;
 }
@@ -308,7 +359,7 @@ int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, 
     if (!out) return fail(ADI_EINVAL, "out is NULL");
     *out = nullptr;
     if (!problems || count <= 0) return fail(ADI_EINVAL, "need at least one problem");
-    if (flags & ~ADI_BATCH_GRAPH) return fail(ADI_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(ADI_BATCH_GRAPH | ADI_BATCH_ONE_STREAM)) return fail(ADI_EINVAL, "unknown flags 0x%x", flags);
     if ((flags & ADI_BATCH_GRAPH) && !hip_stream)
         return fail(ADI_EINVAL, "ADI_BATCH_GRAPH needs a stream other than the null stream");
     int dev = 0;
@@ -342,6 +393,12 @@ int adi_batch_create(adi_problem* const* problems, int count, void* hip_stream, 
         }
     }
     hipError_t e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int j = 0; j < adi_batch::kAux && e == hipSuccess && !(flags & ADI_BATCH_ONE_STREAM); ++j) {
+        e = hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming);
+        // default priority, like every stream of the library
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux[j], hipStreamNonBlocking);
+    }
     if (e != hipSuccess) {
         release(b);
         return hip_fail(e, "hipEventCreate");

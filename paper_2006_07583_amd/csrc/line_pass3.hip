@@ -341,7 +341,6 @@ template <typename T, int METHOD> struct Line3 {
 template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false, bool FULL = false>
 __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* smem) {
     static_assert(!(EPS && COMP), "the tolerance-tested form runs without compensation");
-    if (EPS && *a.eps_go == 0) return;   // uniform: an earlier attempt converged
     using C = K3<T>;
     constexpr int R = C::R, LPL = C::LPL, WS = C::WS, LW = C::LW;
     const int lg = tile % a.nlg, g = tile / a.nlg;
@@ -558,9 +557,18 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
             if (own && s <= n) vmask |= 1 << k;
         }
     }
+    // (on is 0 or 1: a product rather than a select, which would hold one
+    // lane mask per slot in the scalar registers)
     auto chg = [](T x, T y, int on) {
-        const T d = on ? x - y : T(0);
+        const T d = (x - y) * T(on);
         return d * d;
+    };
+    // The masks pass through an empty asm at each use: the per-slot tests
+    // are then not hoisted out of the sweep loop as 2 R lane masks, which
+    // would not fit the scalar registers.
+    auto opaque = [](int m) {
+        asm volatile("" : "+v"(m));
+        return m;
     };
 
     if (METHOD == LINE_CFD) {
@@ -629,12 +637,13 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 // one sweep (v_it, then u_{it+1}); tv: sum the change of v,
                 // q >= 0: sum the change of u into ev[q] (constants at each call)
                 auto sweep = [&](bool tv, int q) {
+                    const int vm = opaque(vmask), um = opaque(umask);
                     L.rhs(0, U, Ul, Ur, X);
                     L.solve(0, X, xl, xr);
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
                         const T vn = fma(-RR[k], X[k], B[k]);
-                        if (tv) ev[1] += chg(vn, Tt[k], (vmask >> k) & 1);
+                        if (tv) ev[1] += chg(vn, Tt[k], (vm >> k) & 1);
                         Tt[k] = vn;
                     }
                     Tl = fma(-Rl, xl, Bl);
@@ -644,7 +653,7 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
                         const T un = fma(-KK[k], X[k], A[k]);
-                        if (q >= 0) ev[q] += chg(un, U[k], (umask >> k) & 1);
+                        if (q >= 0) ev[q] += chg(un, U[k], (um >> k) & 1);
                         U[k] = un;
                     }
                     Ul = fma(-Kl, xl, Al);
@@ -654,12 +663,13 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 for (int it = 1; it < a.sweeps - 2; ++it) sweep(false, -1);
                 if (a.sweeps >= 3) sweep(false, 0);
                 sweep(true, 2);
+                const int vm = opaque(vmask);
                 L.rhs(0, U, Ul, Ur, X);
                 L.solve(0, X, xl, xr);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {                                  // v_K
                     const T vn = fma(-RR[k], X[k], B[k]);
-                    ev[3] += chg(vn, Tt[k], (vmask >> k) & 1);
+                    ev[3] += chg(vn, Tt[k], (vm >> k) & 1);
                     Tt[k] = vn;
                 }
             } else {
@@ -840,27 +850,29 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
                 for (int k = 0; k < R; ++k) Tt[k] = B[k];                     // v_0
                 // one sweep (v_it, then u_{it+1}); tracking as in the compact form
                 auto sweep = [&](bool tv, int q) {
+                    const int vm = opaque(vmask), um = opaque(umask);
                     velocity(U, X, Tm2, Tm1, Tp);
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
-                        if (tv) ev[1] += chg(X[k], Tt[k], (vmask >> k) & 1);
+                        if (tv) ev[1] += chg(X[k], Tt[k], (vm >> k) & 1);
                         Tt[k] = X[k];
                     }
                     applyD(Tt, Tm2, Tm1, Tp, X);
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
                         const T un = fma(-KK[k], X[k], A[k]);
-                        if (q >= 0) ev[q] += chg(un, U[k], (umask >> k) & 1);
+                        if (q >= 0) ev[q] += chg(un, U[k], (um >> k) & 1);
                         U[k] = un;
                     }
                 };
                 for (int it = 1; it < a.sweeps - 2; ++it) sweep(false, -1);
                 if (a.sweeps >= 3) sweep(false, 0);
                 sweep(true, 2);
+                const int vm = opaque(vmask);
                 velocity(U, X, Tm2, Tm1, Tp);                                 // v_K
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
-                    ev[3] += chg(X[k], Tt[k], (vmask >> k) & 1);
+                    ev[3] += chg(X[k], Tt[k], (vm >> k) & 1);
                     Tt[k] = X[k];
                 }
             } else {
@@ -1065,10 +1077,10 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
 int line3_torder(int dtype, int method) { return method == LINE_CFD || dtype != 1 ? 0 : 1; }
 
 // The tolerance-tested form holds a spare array and the change sums: it
-// runs at a lower occupancy (2 waves per SIMD in FP32, 1 in FP64) rather
+// runs at a lower occupancy (3 waves per SIMD in FP32, 1 in FP64) rather
 // than spill.
 template <typename T, bool EPS>
-constexpr int kWpe = EPS ? (sizeof(T) == 4 ? 2 : 1) : Cfg3<T>::WPE;
+constexpr int kWpe = EPS ? (sizeof(T) == 4 ? 3 : 1) : Cfg3<T>::WPE;
 
 template <typename T, int METHOD, int MODE, bool EPS = false, bool COMP = false, bool FULL = false>
 __global__ void __launch_bounds__(K3<T>::NT)
@@ -1082,10 +1094,13 @@ line_pass3_kernel(const LinePassArgs<T> a) {
     // autotuner's choice).
     const int nb = a.nlg * a.nwin;
     const int per = (nb + 7) / 8;
-    const int t = a.torder == 2 ? (int)blockIdx.x : (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    auto order = [&](int b) { return a.torder == 2 ? b : (b % 8) * per + b / 8; };
+    auto tile_of = [&](int t) { return a.torder == 0 ? (t % a.nwin) * a.nlg + t / a.nwin : t; };
+    // uniform: an earlier attempt of a tolerance-tested pass converged
+    if (EPS && *a.eps_go == 0) return;
+    const int t = order((int)blockIdx.x);
     if (t >= nb) return;
-    const int tile = a.torder == 0 ? (t % a.nwin) * a.nlg + t / a.nwin : t;
-    lp3_body<T, METHOD, MODE, EPS, COMP, FULL>(a, tile, smem);
+    lp3_body<T, METHOD, MODE, EPS, COMP, FULL>(a, tile_of(t), smem);
 }
 
 template <typename T, int METHOD, int MODE, bool COMP = false, bool FULL = false>
@@ -1120,8 +1135,8 @@ hipError_t launch3(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int method,
                    bool comp, bool full) {
     const int nb = a ? a->nlg * a->nwin : ga->total;
     if (nb <= 0) return hipSuccess;
-    dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
     const bool eps = a && a->eps_part;
+    dim3 grid((unsigned)(((nb + 7) / 8) * 8)), block(K3<T>::NT);
     if (eps && (mode == LINE_EXPLICIT || comp || full)) return hipErrorInvalidValue;
     if (comp && full) return hipErrorInvalidValue;
 #define LP3_CASE(M, MD)                                                                                  \
@@ -1171,21 +1186,33 @@ int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW;
 // next attempt (K + 2 sweeps) runs only if this one ran and did not converge
 // and K < kmax.  A deciding attempt adds one pass and its K sweeps to stats.
 // The last attempt's check re-arms the flags for the next pass.
-__global__ void __launch_bounds__(256)
+// One workgroup of 1024 threads; each thread sums its share of the four
+// partial arrays with two loads per array in flight.
+__global__ void __launch_bounds__(1024)
 eps_check_kernel(const double* part, int nb, int* go, int j, int attempts, double eps, int K, int kmin, int kmax,
                  long long* stats) {
-    __shared__ double red[4][256];
+    constexpr int NT = 1024;
+    __shared__ double red[4][NT];
     const int t = threadIdx.x;
     const bool ran = go[j] != 0;   // uniform
     if (ran) {
-        for (int q = 0; q < 4; ++q) {
-            double v = 0.0;
-            for (int i = t; i < nb; i += 256) v += part[(int64_t)q * nb + i];
-            red[q][t] = v;
-        }
-        for (int w = 128; w > 0; w >>= 1) {
+        double v[4][2] = {};
+        int i = t;
+        for (; i + NT < nb; i += 2 * NT)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q][0] += part[(int64_t)q * nb + i];
+                v[q][1] += part[(int64_t)q * nb + i + NT];
+            }
+        if (i < nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q][0] += part[(int64_t)q * nb + i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[q][t] = v[q][0] + v[q][1];
+        for (int w = NT / 2; w > 0; w >>= 1) {
             __syncthreads();
             if (t < w)
+#pragma unroll
                 for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + w];
         }
         __syncthreads();
@@ -1209,7 +1236,7 @@ eps_check_kernel(const double* part, int nb, int* go, int j, int attempts, doubl
 
 hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int attempts, double eps, int K,
                             int kmin, int kmax, long long* stats, hipStream_t st) {
-    hipLaunchKernelGGL(eps_check_kernel, dim3(1), dim3(256), 0, st, part, nb, go, j, attempts, eps, K, kmin, kmax,
+    hipLaunchKernelGGL(eps_check_kernel, dim3(1), dim3(1024), 0, st, part, nb, go, j, attempts, eps, K, kmin, kmax,
                        stats);
     return hipGetLastError();
 }

@@ -53,8 +53,8 @@ def build(seed0, stream):
     return [make(*m, seed=seed0 + 3 * i, stream=stream) for i, m in enumerate(MIX)]
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_equals_individual_runs_bitwise(graph):
+@pytest.mark.parametrize("graph,one_stream", [(False, False), (True, False), (True, True)])
+def test_batch_equals_individual_runs_bitwise(graph, one_stream):
     st = torch.cuda.Stream()
     alone = build(100, st)
     batch = build(100, st)
@@ -64,7 +64,7 @@ def test_batch_equals_individual_runs_bitwise(graph):
         for c in chunks:
             pb.run(c)
         pb.get_state()
-    b = adi.Batch([pb for pb, _ in batch], st, graph=graph)
+    b = adi.Batch([pb for pb, _ in batch], st, graph=graph, one_stream=one_stream)
     for c in chunks:
         b.run(c)
     b.sync()
