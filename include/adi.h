@@ -252,7 +252,8 @@ int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite);
  * workgroup in FP32, 16/32/64 in FP64; every shape whose window holds the
  * line is a candidate) and the wave-per-line kernel's order of tiles across
  * the eight XCDs (0: each XCD takes whole line groups, 1: whole windows, 2:
- * no XCD mapping).  adi_autotune times each candidate of each direction's
+ * no XCD mapping, 3 .. 6: whole windows within blocks of 4, 8, 16, 32 line
+ * groups).  adi_autotune times each candidate of each direction's
  * sweep pass on the bound problem's own data (reps passes per timing, 0 =
  * 10; three rounds, best kept), keeps the fastest (the default stays unless
  * another is more than 1% faster), and stores the choice in a process-wide
@@ -287,7 +288,7 @@ typedef struct adi_plan_info {
     int lines_per_group; /* lines per workgroup */
     int workgroups;      /* workgroups of one pass */
     int tile_shape;      /* single-window tile shape 0, 1, 2 (windows 512, 256, 128); -1 otherwise */
-    int tile_order;      /* wave-per-line tile order 0, 1, 2; -1 otherwise */
+    int tile_order;      /* wave-per-line tile order 0 .. 6; -1 otherwise */
     int tuned;           /* 1 when the choice came from adi_autotune or its cache */
     int reserved[5];
 } adi_plan_info;
@@ -296,7 +297,7 @@ int adi_get_plan(const adi_problem* pb, int dir, adi_plan_info* info);
 
 /* Pin one direction's launch choice by hand: the tile shape (0, 1, 2) of a
  * single-window plan, whose window must hold the line, or the tile order
- * (0, 1, 2) of a wave-per-line plan; ADI_EINVAL for any other value and for
+ * (0 .. 6) of a wave-per-line plan; ADI_EINVAL for any other value and for
  * direct solves.  Allowed before or after adi_bind and between runs (the
  * resident state is kept; the call waits for the problem's stream).  The
  * cache is not changed; adi_get_plan then reports tuned = 0. */

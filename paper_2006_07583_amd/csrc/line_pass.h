@@ -61,7 +61,8 @@ struct LinePassArgs {
     T dmp0, dmpiw, ah;
     int dmpm;
     // wave-per-line kernel: order of the tiles across the XCDs (0: line
-    // group by line group, 1: window by window, 2: launch order)
+    // group by line group, 1: window by window, 2: launch order, 3 .. 6:
+    // window by window within blocks of 2^(torder - 1) line groups)
     int torder;
 };
 
@@ -117,7 +118,7 @@ template <typename T>
 hipError_t launch_line_group3(const GroupArgs<T>& g, int method, int mode, hipStream_t st, bool comp = false,
                               bool full = false);
 int line3_lanes(int dtype);
-int line3_torder(int dtype, int method);
+int line3_torder(int dtype, int method, int nlines);
 
 // Tolerance-tested stages (LinePassArgs::eps_part): a pass is `attempts`
 // launches, attempt j with K = kmin + 2 j sweeps running while go[j] != 0

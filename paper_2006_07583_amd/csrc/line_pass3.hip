@@ -1072,9 +1072,14 @@ __device__ __forceinline__ void lp3_body(const LinePassArgs<T>& a, int tile, T* 
     }
 }
 
-// Default tile order across the XCDs (LinePassArgs::torder), the faster of
-// the two as measured: line group by line group, except for mimetic FP64.
-int line3_torder(int dtype, int method) { return method == LINE_CFD || dtype != 1 ? 0 : 1; }
+// Default tile order across the XCDs (LinePassArgs::torder), the fastest as
+// measured: line group by line group, except for mimetic FP64 (window by
+// window); FP32 passes over more than 6144 lines take windows in blocks of
+// 32 line groups (8192^2: 385 against 461 us per pass).
+int line3_torder(int dtype, int method, int nlines) {
+    if (dtype != 1 && nlines > 6144) return 6;
+    return method == LINE_CFD || dtype != 1 ? 0 : 1;
+}
 
 // The tolerance-tested form holds a spare array and the change sums: it
 // runs at a lower occupancy (3 waves per SIMD in FP32, 1 in FP64) rather
@@ -1087,15 +1092,24 @@ __global__ void __launch_bounds__(K3<T>::NT)
 __attribute__((amdgpu_waves_per_eu(kWpe<T, EPS>, kWpe<T, EPS>)))
 line_pass3_kernel(const LinePassArgs<T> a) {
     __shared__ __align__(16) T smem[K3<T>::TILE];
-    // Workgroups go round-robin to the eight XCDs; with torder 0 and 1 each
-    // XCD takes a contiguous range of the ordered tiles, line group by line
-    // group (all windows of a group in turn) or window by window; torder 2
-    // keeps the launch order (torder: a default per variant, or the
-    // autotuner's choice).
+    // Workgroups go round-robin to the eight XCDs; but with torder 2 each
+    // XCD takes a contiguous range of the ordered tiles: line group by line
+    // group (all windows of a group in turn, torder 0), window by window
+    // (torder 1), or window by window within blocks of 2^(torder - 1) line
+    // groups (torder 3 .. 6: the transposed pressure rows of a window then
+    // fill in runs of that many groups); torder 2 keeps the launch order
+    // (torder: a default per variant, or the autotuner's choice).
     const int nb = a.nlg * a.nwin;
     const int per = (nb + 7) / 8;
     auto order = [&](int b) { return a.torder == 2 ? b : (b % 8) * per + b / 8; };
-    auto tile_of = [&](int t) { return a.torder == 0 ? (t % a.nwin) * a.nlg + t / a.nwin : t; };
+    auto tile_of = [&](int t) {
+        if (a.torder == 0) return (t % a.nwin) * a.nlg + t / a.nwin;
+        if (a.torder <= 2) return t;
+        const int gb = 1 << (a.torder - 1);
+        const int sb = t / (gb * a.nwin), r = t - sb * gb * a.nwin;
+        const int base = sb * gb, cnt = min(gb, a.nlg - base);
+        return (r / cnt) * a.nlg + base + r % cnt;
+    };
     // uniform: an earlier attempt of a tolerance-tested pass converged
     if (EPS && *a.eps_go == 0) return;
     const int t = order((int)blockIdx.x);
@@ -1185,7 +1199,9 @@ int line3_lanes(int dtype) { return dtype == 1 ? K3<double>::LW : K3<float>::LW;
 // sweep K - 1 (tested only from kmin on) or of sweep K is at most eps; the
 // next attempt (K + 2 sweeps) runs only if this one ran and did not converge
 // and K < kmax.  A deciding attempt adds one pass and its K sweeps to stats.
-// The last attempt's check re-arms the flags for the next pass.
+// The last attempt (K = kmax) always decides: its check is not launched
+// when an earlier one exists, which counts it when it enables it.  go[0]
+// stays 1; every other flag is written by the check before its attempt.
 // One workgroup of 1024 threads; each thread sums its share of the four
 // partial arrays with two loads per array in flight.
 __global__ void __launch_bounds__(1024)
@@ -1227,11 +1243,12 @@ eps_check_kernel(const double* part, int nb, int* go, int j, int attempts, doubl
         if (stop) {
             stats[0] += 1;
             stats[1] += K;
+        } else if (j + 1 == attempts - 1) {
+            stats[0] += 1;        // the last attempt runs and decides
+            stats[1] += K + 2;
         }
     }
     go[j + 1] = next ? 1 : 0;
-    if (j == attempts - 1)
-        for (int i = 0; i <= attempts; ++i) go[i] = i == 0 ? 1 : 0;
 }
 
 hipError_t launch_eps_check(const double* part, int nb, int* go, int j, int attempts, double eps, int K,
