@@ -158,9 +158,14 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
     per_pass = (t_ev - t_half) / (2.0 * (steps - half)) if steps > half else t_ev / (2.0 * steps)
     finite = bool(torch.isfinite(U).all().item())
     stats = pb.sweep_stats() if tol is not None else (0, 0)
+    # the launch plan of both directions (kernel, windows, tile shape or order)
+    plan = {d: {k: v for k, v in pb.plan(i).items() if k in ("kernel", "windows", "window", "margin",
+                                                                 "lines_per_group", "workgroups", "tile_shape",
+                                                                 "tile_order", "tuned")}
+            for i, d in enumerate(("x", "y"))}
     pb.close()
     return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite,
-            "sweeps_per_pass": stats[1] / stats[0] if stats[0] else float(sweeps)}
+            "sweeps_per_pass": stats[1] / stats[0] if stats[0] else float(sweeps), "plan": plan}
 
 
 def stream_ceiling_case(n, dtype, reps=20):
@@ -518,7 +523,7 @@ def main():
         variants[f"{'cfd' if m == 0 else 'mfd'}_{dname[d]}"] = {
             "pt_steps_s": r["pt_steps_s"], "ms_per_step": r["t"] / K * 1e3,
             "line_pass_us": r["per_pass"] * 1e6, "alg_GBs": r["gbs"], "hbm_frac": r["gbs"] / HBM_PEAK_GBS,
-            "finite": r["finite"], "error_vs_oracle": r.get("error")}
+            "finite": r["finite"], "error_vs_oracle": r.get("error"), "plan": r["plan"]}
     out = {
         "metric": "ADI grid-point-steps/s at 4096^2 FP32 vs FP64 + %HBM peak; p50/p99 solve latency",
         "value": value, "unit": "grid-point-steps/s", "n_gpus": 1, "steps": K, "warmup": W,

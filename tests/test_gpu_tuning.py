@@ -215,3 +215,45 @@ def test_direct_and_unbound_problems():
     with pytest.raises(adi.AdiError, match="dir"):
         pb.plan(2)
     pb.close()
+
+
+def test_cached_shape_reaches_the_server(tmp_path, monkeypatch):
+    """A cache entry (written by hand into the ADI_TUNE_CACHE file) pins the
+    512-slot tile shape on a compact FP32 problem whose lines would take the
+    128-slot one; a problem created alone and a served request of that shape
+    both run with it (bit for bit equal), and both match the oracle."""
+    m, d, nx, ny = adi.CFD, adi.FP32, 100, 90
+    h, f, med, cmax, dt, src = setup(m, nx, ny, 123)
+    pb, _ = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
+    plans = [pb.plan(k) for k in (0, 1)]
+    pb.close()
+    assert all(pl["kernel"] == adi.KERNEL_SINGLE and pl["tile_shape"] == 2 and pl["tuned"] == 0 for pl in plans)
+    arch = None
+    # the architecture string as the library writes it: from a tuning's file
+    monkeypatch.setenv("ADI_TUNE_CACHE", str(tmp_path / "probe.txt"))
+    q, _ = problem(m, d, 80, 70, *setup(m, 80, 70, 5))
+    q.autotune(reps=2)
+    q.close()
+    arch = (tmp_path / "probe.txt").read_text().split()[1]
+    # H = 18 + 2 K = 30 for compact FP32
+    path = tmp_path / "pin.txt"
+    path.write_text(f"adi-tune {arch} {m} {d} {plans[0]['slots']} {plans[0]['lines']} 30 {adi.KERNEL_SINGLE} 0\n"
+                    f"adi-tune {arch} {m} {d} {plans[1]['slots']} {plans[1]['lines']} 30 {adi.KERNEL_SINGLE} 0\n")
+    monkeypatch.setenv("ADI_TUNE_CACHE", str(path))
+    pb, x = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
+    assert [pb.plan(k)["tile_shape"] for k in (0, 1)] == [0, 0]
+    assert all(pb.plan(k)["tuned"] == 1 and pb.plan(k)["window"] == 512 for k in (0, 1))
+    pb.run(5)
+    pb.get_state()
+    solo = np3(x)
+    pb.close()
+    arr = lambda a: np.array(a, dtype=np.float32)
+    srv = adi.Server(hbm_budget_bytes=64 << 20, max_active=2)
+    req = [arr(f[k]) for k in "UVW"]
+    t = srv.submit(adi.make_params(m, d, nx, ny, h, dt, cmax, src=src), *req,
+                   *[arr(med[k]) for k in ("K", "Rv", "Rw")], nsteps=5)
+    srv.wait(t)
+    srv.close()
+    for a, b in zip(req, solo):
+        assert np.array_equal(a.astype(np.float64), b)
+    check_oracle(m, d, solo, f, med, h, dt, src, 5)
