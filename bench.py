@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--cpu-baseline-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle legs (timing and the per-variant errors)")
+    ap.add_argument("--graph-steps", type=int, default=1000,
+                    help="steps of the small-problem leg, launched and graph-replayed (0 = skip)")
+    ap.add_argument("--graph-n", type=int, default=256)
     ap.add_argument("--tolerance-steps", type=int, default=40,
                     help="steps of the tolerance-tested leg (0 = skip)")
     ap.add_argument("--direct-steps", type=int, default=10,
@@ -166,6 +169,37 @@ def gpu_case(method, dtype, n, steps, warmup, sweeps, tol=None):
     pb.close()
     return {"t": t_wall, "t_events": t_ev, "per_pass": per_pass, "finite": finite,
             "sweeps_per_pass": stats[1] / stats[0] if stats[0] else float(sweeps), "plan": plan}
+
+
+def graph_case(n, steps):
+    """Small problems, where launch costs matter (Section 5): the layered
+    n^2 workload (FP32, CFD and MFD) run `steps` steps with one launch per
+    line pass and with graph replay (adi_set_graph), in pt-steps/s."""
+    import torch
+    from paper_2006_07583_amd import adi, inputs
+    out = {}
+    st = torch.cuda.Stream()
+    for method, name in ((adi.CFD, "cfd"), (adi.MFD, "mfd")):
+        pr = inputs.seismic_problem(method, n, seed=0)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float32)
+        res = {}
+        for graph in (False, True):
+            U, V, W, K = t(pr["U"]), t(pr["V"]), t(pr["W"]), t(pr["K"])
+            p = adi.make_params(method, adi.FP32, n, n, pr["h"], pr["dt"], pr["cmax"], src=pr["src"])
+            pb = adi.Problem(p, st).bind(U, V, W, K)
+            pb.set_graph(graph)
+            pb.run(4)
+            pb.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            pb.run(steps)
+            e1.record(st)
+            pb.sync()
+            res["graph" if graph else "launched"] = n * n * steps / (e0.elapsed_time(e1) * 1e-3)
+            pb.close()
+        res["speedup"] = res["graph"] / res["launched"]
+        out[name] = res
+    return {"n": n, "steps": steps, "dtype": "f32", **out}
 
 
 def stream_ceiling_case(n, dtype, reps=20):
@@ -569,6 +603,12 @@ def main():
             if isinstance(v, dict) and "pass_us" in v),
               file=sys.stderr, flush=True)
         out["direct"] = dc
+    if args.graph_steps > 0:
+        gc = graph_case(args.graph_n, args.graph_steps)
+        print(f"# small problem {gc['n']}^2 FP32, {gc['steps']} steps: " + ", ".join(
+            f"{k} {gc[k]['launched']:.4g} launched, {gc[k]['graph']:.4g} graph-replayed ({gc[k]['speedup']:.2f}x)"
+            for k in ("cfd", "mfd")), file=sys.stderr, flush=True)
+        out["small_problem_graph"] = gc
     if args.batch_steps > 0:
         bc = batch_case(args.batch_steps, args.batch_count)
         print(f"# batched {bc['problems']} problems ({bc['cells']} cells), {bc['steps']} steps: "

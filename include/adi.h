@@ -248,9 +248,10 @@ int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite);
 /* Launch autotuner.  The line passes (Section 3: one implicit sweep stage
  * and the next stage's explicit part per launch) have launch choices that
  * change their speed but not what they compute: the single-window kernel's
- * tile shape (window of 512, 256 or 128 slots with 32/64 lines per
- * workgroup in FP32, 16/32/64 in FP64; every shape whose window holds the
- * line is a candidate) and the wave-per-line kernel's order of tiles across
+ * tile shape (0 .. 2: windows of 512, 256 or 128 slots with 32/64/64 lines
+ * per workgroup in FP32, 16/32/64 in FP64; 3 .. 5: the same windows with a
+ * quarter of the lines and of the waves per workgroup; every shape whose
+ * window holds the line is a candidate) and the wave-per-line kernel's order of tiles across
  * the eight XCDs (0: each XCD takes whole line groups, 1: whole windows, 2:
  * no XCD mapping, 3 .. 6: whole windows within blocks of 4, 8, 16, 32 line
  * groups).  adi_autotune times each candidate of each direction's
@@ -273,6 +274,17 @@ int adi_check_stats(adi_problem* pb, double* max_abs, int* nonfinite);
  * adi_bind. */
 int adi_autotune(adi_problem* pb, int reps, double* pass_us);
 
+/* Graph replay for adi_run (on = 1; 0 turns it off).  The paper found
+ * launch costs above the work of small problems (Section 5); with this set,
+ * a run of at least 3 steps goes through a batch of this problem alone
+ * (adi_batch_*, ADI_BATCH_GRAPH): two steps are captured once per run and
+ * replayed, the source term read from a device table.  Results equal the
+ * launched run bit for bit.  Needs the problem's own created stream (not the
+ * null stream); refused for direct solves and for problems with a forcing
+ * field or wall data.  Runs with the health check or the tolerance test on
+ * take the launch path. */
+int adi_set_graph(adi_problem* pb, int on);
+
 enum { ADI_KERNEL_SINGLE = 1, ADI_KERNEL_WAVE = 3, ADI_KERNEL_DIRECT = 4 };
 
 /* The launch plan of one direction (dir 0: the x lines, along which i
@@ -287,7 +299,7 @@ typedef struct adi_plan_info {
     int margin;          /* overlap margin of the multi-window plans (slots per side) */
     int lines_per_group; /* lines per workgroup */
     int workgroups;      /* workgroups of one pass */
-    int tile_shape;      /* single-window tile shape 0, 1, 2 (windows 512, 256, 128); -1 otherwise */
+    int tile_shape;      /* single-window tile shape 0 .. 5 (windows 512, 256, 128, 512, 256, 128); -1 otherwise */
     int tile_order;      /* wave-per-line tile order 0 .. 6; -1 otherwise */
     int tuned;           /* 1 when the choice came from adi_autotune or its cache */
     int reserved[5];
@@ -295,7 +307,7 @@ typedef struct adi_plan_info {
 
 int adi_get_plan(const adi_problem* pb, int dir, adi_plan_info* info);
 
-/* Pin one direction's launch choice by hand: the tile shape (0, 1, 2) of a
+/* Pin one direction's launch choice by hand: the tile shape (0 .. 5) of a
  * single-window plan, whose window must hold the line, or the tile order
  * (0 .. 6) of a wave-per-line plan; ADI_EINVAL for any other value and for
  * direct solves.  Allowed before or after adi_bind and between runs (the

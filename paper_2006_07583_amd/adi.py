@@ -21,7 +21,7 @@ STATUS = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EDEVICE",
 EXPORTS = ("adi_status_string", "adi_last_error", "adi_params_init", "adi_create",
            "adi_workspace_size", "adi_bind", "adi_run", "adi_step", "adi_sync", "adi_get_state",
            "adi_get_step", "adi_set_step", "adi_run_noalloc", "adi_set_check", "adi_check_stats",
-           "adi_autotune", "adi_get_plan", "adi_set_plan",
+           "adi_autotune", "adi_get_plan", "adi_set_plan", "adi_set_graph",
            "adi_set_forcing", "adi_set_boundary", "adi_set_damping",
            "adi_set_tolerance", "adi_sweep_stats", "adi_destroy",
            "adi_batch_create", "adi_batch_run", "adi_batch_sync", "adi_batch_launches",
@@ -126,6 +126,7 @@ def lib():
         L.adi_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.adi_get_plan.argtypes = [vp, ctypes.c_int, ctypes.POINTER(AdiPlanInfo)]
         L.adi_set_plan.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.adi_set_graph.argtypes = [vp, ctypes.c_int]
         L.adi_stream_ceiling.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, i64, vp]
         L.adi_run_noalloc.argtypes = [ctypes.POINTER(AdiParams), vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(i64), i64]
@@ -315,6 +316,11 @@ class Problem:
         info = AdiPlanInfo()
         _check(lib().adi_get_plan(self._h, int(direction), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in AdiPlanInfo._fields_ if k != "reserved"}
+
+    def set_graph(self, on: bool = True) -> "Problem":
+        """Graph replay of :meth:`run` (adi_set_graph)."""
+        _check(lib().adi_set_graph(self._h, 1 if on else 0))
+        return self
 
     def set_plan(self, direction: int, choice: int) -> "Problem":
         """Pin the tile shape / tile order of one direction (adi_set_plan)."""

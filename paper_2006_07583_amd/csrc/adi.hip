@@ -77,11 +77,16 @@ Plan make_plan(int method, int dtype, int n, int nlines, int sweeps, double cfl)
     p.nlines = nlines;
     p.H = adi::line_halo(dtype, method, sweeps, cfl);
     if (p.ns <= adi::LINE_WS) {
-        // single window: the smallest tile shape whose window holds the line
+        // single window: the smallest of the shapes 0 .. 2 whose window
+        // holds the line, or its quarter-width twin (3 .. 5) when the wide
+        // shape would launch fewer than 1024 workgroups (a workgroup's
+        // passes are latency-bound: 120^2 to 500^2 FP32 passes took 24-35
+        // us wide and 21-27 us narrow, FP64 25-44 against 14-27)
         p.ver = 1;
         p.cfg = 0;
-        for (int c = adi::LINE_NCFG - 1; c >= 0; --c)
+        for (int c = 2; c >= 0; --c)
             if (p.ns <= adi::line_ws(c)) { p.cfg = c; break; }
+        if ((nlines + adi::line_lanes(dtype, p.cfg) - 1) / adi::line_lanes(dtype, p.cfg) < 1024) p.cfg += 3;
         p.nwin = 1;
         p.S = p.ns;
         p.deep = 1;
@@ -1593,7 +1598,35 @@ int adi_run(adi_problem* pb, int64_t nsteps) {
     if (nsteps < 0) return fail(ADI_EINVAL, "nsteps < 0");
     if (nsteps == 0) return ADI_OK;
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+    // graph replay: the problem as a batch of one (the steady steps from a
+    // captured graph); runs with a health check or the tolerance test take
+    // the launch path
+    if (pb->graph && nsteps >= 3 && pb->chk_every <= 0 && pb->eps <= 0.0 && !pb->fsig.kind && !pb->bsig.kind) {
+        if (!pb->gbatch) {
+            adi_problem* one[1] = {pb};
+            const int rc = adi_batch_create(one, 1, pb->st, ADI_BATCH_GRAPH | ADI_BATCH_ONE_STREAM, &pb->gbatch);
+            if (rc != ADI_OK) return rc;
+        }
+        return adi_batch_run(pb->gbatch, nsteps);
+    }
     return pb->p.dtype != ADI_FP64 ? run_impl<float>(pb, nsteps) : run_impl<double>(pb, nsteps);
+}
+
+int adi_set_graph(adi_problem* pb, int on) {
+    g_err.clear();
+    if (!pb) return fail(ADI_EINVAL, "problem is NULL");
+    if (on) {
+        if (!pb->st) return fail(ADI_EINVAL, "graph replay needs a created stream, not the null stream");
+        if (pb->p.sweeps == 0) return fail(ADI_EINVAL, "direct solves (sweeps 0) run without graph replay");
+        if (pb->fsig.kind || pb->bsig.kind || pb->set_fsig.kind || pb->set_bsig.kind)
+            return fail(ADI_EINVAL, "problems with a forcing field or wall data run without graph replay");
+    } else if (pb->gbatch) {
+        HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
+        adi_batch_destroy(pb->gbatch);
+        pb->gbatch = nullptr;
+    }
+    pb->graph = on != 0;
+    return ADI_OK;
 }
 
 int adi_step(adi_problem* pb) { return adi_run(pb, 1); }
@@ -1842,6 +1875,10 @@ int adi_sweep_stats(adi_problem* pb, int64_t* passes, int64_t* sweeps) {
 
 int adi_destroy(adi_problem* pb) {
     if (!pb) return ADI_OK;
+    if (pb->gbatch) {
+        (void)hipSetDevice(pb->dev);
+        adi_batch_destroy(pb->gbatch);
+    }
     if ((pb->own_ws && pb->ws) || pb->eps_buf || pb->dst2) {
         (void)hipSetDevice(pb->dev);
         (void)hipStreamSynchronize(pb->st);

@@ -8,7 +8,9 @@ namespace adi {
 enum { LINE_CFD = 0, LINE_MFD = 1 };
 enum { LINE_SWEEP = 0, LINE_FINAL = 1, LINE_EXPLICIT = 2 };
 enum { LINE_WS = 512 };   // slots per window of the multi-window kernel
-enum { LINE_NCFG = 3 };   // single-window tile shapes: windows of 512, 256, 128 slots
+// single-window tile shapes: windows of 512, 256, 128 slots (0 .. 2), and
+// the same windows with a quarter of the lines per workgroup (3 .. 5)
+enum { LINE_NCFG = 6 };
 
 // Arguments of one line pass.  Along a line, slot s holds the pressure value
 // of index s (interior slots 1..n-1 for CFD, 1..n for MFD) and the velocity

@@ -51,13 +51,21 @@ namespace adi {
 // Tile shapes (lines per workgroup LW, slots per lane R, waves NW, carry
 // reach TS in segments) for windows of 512, 256 and 128 slots.  Short lines
 // take the smallest window that holds them, with more lines per workgroup.
+// Shapes 3 .. 5 have the windows of 0 .. 2 with 4 waves and a quarter of the
+// lines: four times the workgroups, for problems with few lines.
 template <typename T, int CF> struct Tile;
 template <> struct Tile<float, 0> { static constexpr int LW = 32, R = 16, NW = 16, TS = 2; };
 template <> struct Tile<float, 1> { static constexpr int LW = 64, R = 16, NW = 16, TS = 2; };
 template <> struct Tile<float, 2> { static constexpr int LW = 64, R = 8, NW = 16, TS = 4; };
+template <> struct Tile<float, 3> { static constexpr int LW = 8, R = 16, NW = 4, TS = 2; };
+template <> struct Tile<float, 4> { static constexpr int LW = 16, R = 16, NW = 4, TS = 2; };
+template <> struct Tile<float, 5> { static constexpr int LW = 16, R = 8, NW = 4, TS = 4; };
 template <> struct Tile<double, 0> { static constexpr int LW = 16, R = 8, NW = 16, TS = 4; };
 template <> struct Tile<double, 1> { static constexpr int LW = 32, R = 8, NW = 16, TS = 4; };
 template <> struct Tile<double, 2> { static constexpr int LW = 64, R = 8, NW = 16, TS = 4; };
+template <> struct Tile<double, 3> { static constexpr int LW = 4, R = 8, NW = 4, TS = 4; };
+template <> struct Tile<double, 4> { static constexpr int LW = 8, R = 8, NW = 4, TS = 4; };
+template <> struct Tile<double, 5> { static constexpr int LW = 16, R = 8, NW = 4, TS = 4; };
 
 template <typename T, int CF> struct K {
     static constexpr int LW = Tile<T, CF>::LW, R = Tile<T, CF>::R, NW = Tile<T, CF>::NW, TS = Tile<T, CF>::TS;
@@ -71,6 +79,9 @@ template <typename T, int CF> struct K {
 static_assert(K<float, 0>::WS == LINE_WS && K<double, 0>::WS == LINE_WS, "window size");
 static_assert(K<float, 1>::WS == 256 && K<double, 1>::WS == 256, "window size");
 static_assert(K<float, 2>::WS == 128 && K<double, 2>::WS == 128, "window size");
+static_assert(K<float, 3>::WS == LINE_WS && K<double, 3>::WS == LINE_WS, "window size");
+static_assert(K<float, 4>::WS == 256 && K<double, 4>::WS == 256, "window size");
+static_assert(K<float, 5>::WS == 128 && K<double, 5>::WS == 128, "window size");
 
 template <int METHOD> struct Halo;
 template <> struct Halo<LINE_CFD> { static constexpr int N = 1, DEEP = 3; };
@@ -570,6 +581,9 @@ hipError_t launch_lp_cfg(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int c
         case 0: return launch_lp<T, 0, COMP, FULL>(a, ga, method, mode, st);
         case 1: return launch_lp<T, 1, COMP, FULL>(a, ga, method, mode, st);
         case 2: return launch_lp<T, 2, COMP, FULL>(a, ga, method, mode, st);
+        case 3: return launch_lp<T, 3, COMP, FULL>(a, ga, method, mode, st);
+        case 4: return launch_lp<T, 4, COMP, FULL>(a, ga, method, mode, st);
+        case 5: return launch_lp<T, 5, COMP, FULL>(a, ga, method, mode, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -625,12 +639,15 @@ hipError_t launch_fill_zero(T* dst, int64_t dld, int rows, int cols, hipStream_t
 }
 
 int line_lanes(int dtype, int cfg) {
-    static const int lw[2][LINE_NCFG] = {{K<float, 0>::LW, K<float, 1>::LW, K<float, 2>::LW},
-                                         {K<double, 0>::LW, K<double, 1>::LW, K<double, 2>::LW}};
+    static const int lw[2][LINE_NCFG] = {
+        {K<float, 0>::LW, K<float, 1>::LW, K<float, 2>::LW, K<float, 3>::LW, K<float, 4>::LW, K<float, 5>::LW},
+        {K<double, 0>::LW, K<double, 1>::LW, K<double, 2>::LW, K<double, 3>::LW, K<double, 4>::LW,
+         K<double, 5>::LW}};
     return lw[dtype == 1 ? 1 : 0][cfg];
 }
 int line_ws(int cfg) {
-    static const int ws[LINE_NCFG] = {K<float, 0>::WS, K<float, 1>::WS, K<float, 2>::WS};
+    static const int ws[LINE_NCFG] = {K<float, 0>::WS, K<float, 1>::WS, K<float, 2>::WS,
+                                      K<float, 3>::WS, K<float, 4>::WS, K<float, 5>::WS};
     return ws[cfg];
 }
 

@@ -36,7 +36,7 @@ struct PassDesc {
     bool full() const { return a.dmpm != 0 || a.bnd != nullptr || a.ff != nullptr; }
     int tiles() const { return a.nlg * a.nwin; }
     // kernel variant: passes with equal keys can share a grouped launch
-    int key() const { return (((ver * 4 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0)) * 2 + (full() ? 1 : 0); }
+    int key() const { return (((ver * 8 + cfg) * 2 + method) * 8 + mode * 2 + (comp ? 1 : 0)) * 2 + (full() ? 1 : 0); }
 };
 
 int fail(int code, const char* fmt, ...);
@@ -58,6 +58,9 @@ struct adi_problem {
     double a = 0.0;
     int64_t step = 0;
     bool bound = false;
+    // graph replay of adi_run (adi_set_graph): a batch of this problem alone
+    bool graph = false;
+    adi_batch* gbatch = nullptr;
     // ready: the state of time level `step` lives in the workspace (the
     // pressure hand-off and velocities of the next pass); otherwise it is in
     // the bound arrays U, V, W

@@ -67,7 +67,7 @@ CASES = [
 def choices(pl):
     if pl["kernel"] == adi.KERNEL_WAVE:
         return list(range(7))
-    return [c for c, w in enumerate((512, 256, 128)) if w >= pl["slots"]]
+    return [c for c, w in enumerate((512, 256, 128, 512, 256, 128)) if w >= pl["slots"]]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -97,7 +97,7 @@ def test_every_launch_choice_and_the_tuned_one(case):
                 for u, v in zip(xa, xb):
                     assert torch.equal(u, v), (d, c)
             else:
-                assert pl["window"] == (512, 256, 128)[c] and pl["lines_per_group"] > 0
+                assert pl["window"] == (512, 256, 128, 512, 256, 128)[c] and pl["lines_per_group"] > 0
                 check_oracle(method, dtype, np3(xb), f, med, h, dt, src, 5)
             b.close()
     b, xb = problem(method, dtype, nx, ny, h, f, med, cmax, dt, src)
@@ -220,14 +220,14 @@ def test_direct_and_unbound_problems():
 def test_cached_shape_reaches_the_server(tmp_path, monkeypatch):
     """A cache entry (written by hand into the ADI_TUNE_CACHE file) pins the
     512-slot tile shape on a compact FP32 problem whose lines would take the
-    128-slot one; a problem created alone and a served request of that shape
+    narrow 128-slot one; a problem created alone and a served request of that shape
     both run with it (bit for bit equal), and both match the oracle."""
     m, d, nx, ny = adi.CFD, adi.FP32, 100, 90
     h, f, med, cmax, dt, src = setup(m, nx, ny, 123)
     pb, _ = problem(m, d, nx, ny, h, f, med, cmax, dt, src)
     plans = [pb.plan(k) for k in (0, 1)]
     pb.close()
-    assert all(pl["kernel"] == adi.KERNEL_SINGLE and pl["tile_shape"] == 2 and pl["tuned"] == 0 for pl in plans)
+    assert all(pl["kernel"] == adi.KERNEL_SINGLE and pl["tile_shape"] == 5 and pl["tuned"] == 0 for pl in plans)
     arch = None
     # the architecture string as the library writes it: from a tuning's file
     monkeypatch.setenv("ADI_TUNE_CACHE", str(tmp_path / "probe.txt"))
