@@ -619,6 +619,15 @@ def main():
               f"({bc['speedup']:.2f}x), {bc['grouped_launches']} grouped launches", file=sys.stderr, flush=True)
         out["batched"] = bc
     if args.serve_requests > 0:
+        # the server allocates its arena up front: hand back what the
+        # earlier legs left in torch's cache first
+        import gc
+        import torch
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print(f"# device memory before the served leg: {torch.cuda.memory_reserved() / 2**30:.1f} GiB reserved "
+              f"by torch, {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB free", file=sys.stderr, flush=True)
         sv = serve_case(args.serve_requests, args.serve_rate, args.serve_budget_gb)
         print(f"# served {sv['requests']} requests at {sv['rate_per_s']:.0f}/s: latency p50 {sv['latency_p50_s']:.3f} s, "
               f"p99 {sv['latency_p99_s']:.3f} s, {sv['pt_steps_s']:.4g} pt-steps/s served "
