@@ -363,13 +363,13 @@ int adi_set_step(adi_problem* pb, int64_t m);
  * running only while the earlier ones have not converged.
  *   eps         > 0 switches the test on, 0 restores the fixed count.
  *   min_sweeps  even, in [2, params.sweeps].
- * Applies to FP32 and FP64 problems whose lines are longer than 512 slots in
- * both directions (nx, ny >= 512 for CFD, >= 511 for MFD), run with adi_run /
- * adi_step; such a problem cannot join a batch.  If runs have left the
- * state in the workspace it is first written into the bound arrays, where
- * tolerance-tested runs start and end.  Clears the counters of
- * adi_sweep_stats.  Allocates 32 bytes of device memory per workgroup of
- * the wave-per-line kernel (about 150 KiB at 4096^2) the first time.
+ * Applies to FP32 and FP64 problems of any size (fixed sweeps, no damping
+ * layers, wall data or forcing field), run with adi_run / adi_step; such a
+ * problem cannot join a batch.  If runs have left the state in the workspace
+ * it is first written into the bound arrays, where tolerance-tested runs
+ * start and end.  Clears the counters of adi_sweep_stats.  Allocates 32
+ * bytes of device memory per workgroup of a pass (about 150 KiB at 4096^2)
+ * the first time.
  * Errors: ADI_EINVAL for a NULL problem, eps < 0 or not finite, min_sweeps
  * out of range, or a problem outside the scope above. */
 int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps);

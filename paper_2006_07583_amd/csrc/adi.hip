@@ -790,8 +790,8 @@ static_assert((kMaxAttempts + 1) * sizeof(int) <= 64, "flags");
 // One tolerance-tested pass (Algorithms 3 and 4): attempts with K = kmin,
 // kmin + 2, .. sweeps sweeps, each recomputing the pass from its unchanged
 // inputs and running only while the earlier ones have not converged; the
-// decisions stay on the device.  Each attempt has the windows of its own K
-// (the margin grows with K).
+// decisions stay on the device.  Each attempt of a multi-window plan has
+// the windows of its own K (the margin grows with K).
 template <typename T>
 hipError_t launch_tested(adi_problem* pb, adi::PassDesc<T> d) {
     const auto& p = pb->p;
@@ -803,11 +803,13 @@ hipError_t launch_tested(adi_problem* pb, adi::PassDesc<T> d) {
     hipError_t e = hipSuccess;
     for (int j = 0; j < J && e == hipSuccess; ++j) {
         const int K = kmin + 2 * j;
-        const Plan pk = make_plan(p.method, p.dtype, pl.n, pl.nlines, K, cfl);
         d.a.sweeps = K;
-        d.a.H = pk.H;
-        d.a.S = pk.S;
-        d.a.nwin = pk.nwin;
+        if (pl.ver == 3) {
+            const Plan pk = make_plan(p.method, p.dtype, pl.n, pl.nlines, K, cfl);
+            d.a.H = pk.H;
+            d.a.S = pk.S;
+            d.a.nwin = pk.nwin;
+        }
         d.a.eps_part = L.part;
         d.a.eps_go = L.go + j;
         const int nb = d.a.nlg * d.a.nwin;
@@ -1834,11 +1836,6 @@ int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
     if (pb->dmp0 != 0.0) return fail(ADI_EINVAL, "tolerance-tested stages run without damping layers");
     if (pb->fsig.kind || pb->bsig.kind)
         return fail(ADI_EINVAL, "tolerance-tested stages run without wall data or a forcing field");
-    if (pb->px.ver != 3 || pb->py.ver != 3)
-        return fail(ADI_EINVAL,
-                    "tolerance-tested stages need lines longer than %d slots in both directions "
-                    "(nx, ny >= %d for CFD, >= %d for MFD)",
-                    adi::LINE_WS, adi::LINE_WS, adi::LINE_WS - 1);
     HIP_TRY(hipSetDevice(pb->dev), "hipSetDevice");
     if (pb->ready) {
         // tolerance-tested runs start from the bound arrays
@@ -1847,6 +1844,20 @@ int adi_set_tolerance(adi_problem* pb, double eps, int min_sweeps) {
         pb->ready = false;
     }
     HIP_TRY(hipStreamSynchronize(pb->st), "hipStreamSynchronize");
+    // single-window plans take the quarter-width tile shapes: the tested
+    // form's spare array does not fit the registers of the 16-wave shapes
+    for (int d = 0; d < 2; ++d) {
+        Plan& pl = d == 0 ? pb->px : pb->py;
+        if (pl.ver != 1 || pl.cfg >= 3) continue;
+        set_cfg(pl, pb->p.dtype, pl.cfg + 3);
+        pl.tuned = false;
+        double h64[6 * adi::LINE_WS];
+        float h32[6 * adi::LINE_WS];
+        const int rc = pb->p.dtype == ADI_FP64 ? upload_tables<double>(pb, d, h64, pb->st)
+                                               : upload_tables<float>(pb, d, h32, pb->st);
+        if (rc != ADI_OK) return rc;
+        HIP_TRY(hipStreamSynchronize(pb->st), "factor tables");
+    }
     if (!pb->eps_buf) HIP_TRY(hipMalloc(&pb->eps_buf, eps_bytes(pb)), "tolerance state");
     // flags: attempt 0 of the next pass runs; counters cleared
     const EpsLayout L = eps_layout(pb);

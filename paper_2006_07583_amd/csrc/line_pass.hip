@@ -143,16 +143,20 @@ template <typename T, int CF, int METHOD> struct Pass {
             const T c3 = T(3) * ih;
 #pragma unroll
             for (int k = 0; k < R; ++k) o[k] = c3 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 1));
+            // (products and sums written as explicit fma chains here and
+            // below: every instantiation of the kernel then rounds them alike)
             if (bnd) {
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const int s = s0 + k;
                     if (s == 0)
-                        o[k] = ih * (T(-17) * xv(x, hl, hr, k) + T(9) * xv(x, hl, hr, k + 1) +
-                                     T(9) * xv(x, hl, hr, k + 2) - xv(x, hl, hr, k + 3));
+                        o[k] = ih * fma(T(-17), xv(x, hl, hr, k),
+                                        fma(T(9), xv(x, hl, hr, k + 1),
+                                            fma(T(9), xv(x, hl, hr, k + 2), -xv(x, hl, hr, k + 3))));
                     if (s == n)
-                        o[k] = ih * (xv(x, hl, hr, k - 3) - T(9) * xv(x, hl, hr, k - 2) -
-                                     T(9) * xv(x, hl, hr, k - 1) + T(17) * xv(x, hl, hr, k));
+                        o[k] = ih * fma(T(17), xv(x, hl, hr, k),
+                                        fma(T(-9), xv(x, hl, hr, k - 1),
+                                            fma(T(-9), xv(x, hl, hr, k - 2), xv(x, hl, hr, k - 3))));
                 }
             }
         } else {
@@ -160,8 +164,8 @@ template <typename T, int CF, int METHOD> struct Pass {
             const T c1 = T(9.0 / 8.0) * ih, c0 = T(-1.0 / 24.0) * ih;
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                o[k] = c1 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k)) +
-                       c0 * (xv(x, hl, hr, k + 2) - xv(x, hl, hr, k - 1));
+                o[k] = fma(c1, xv(x, hl, hr, k + 1) - xv(x, hl, hr, k),
+                           c0 * (xv(x, hl, hr, k + 2) - xv(x, hl, hr, k - 1)));
             if (bnd) {
                 const T g0[6] = {T(-47888.0 / 14245.0), T(1790.0 / 407.0), T(-14545.0 / 9768.0),
                                  T(8997.0 / 16280.0), T(-2335.0 / 22792.0), T(25.0 / 9768.0)};
@@ -173,25 +177,25 @@ template <typename T, int CF, int METHOD> struct Pass {
                     if (s == 0) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc += g0[c] * xv(x, hl, hr, k + c);
+                        for (int c = 0; c < 6; ++c) acc = fma(g0[c], xv(x, hl, hr, k + c), acc);
                         o[k] = acc * ih;
                     }
                     if (s == 1) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) acc += g1[c] * xv(x, hl, hr, k - 1 + c);
+                        for (int c = 0; c < 5; ++c) acc = fma(g1[c], xv(x, hl, hr, k - 1 + c), acc);
                         o[k] = acc * ih;
                     }
                     if (s == n - 1) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) acc += g1[c] * xv(x, hl, hr, k + 2 - c);
+                        for (int c = 0; c < 5; ++c) acc = fma(g1[c], xv(x, hl, hr, k + 2 - c), acc);
                         o[k] = -acc * ih;
                     }
                     if (s == n) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc += g0[c] * xv(x, hl, hr, k + 1 - c);
+                        for (int c = 0; c < 6; ++c) acc = fma(g0[c], xv(x, hl, hr, k + 1 - c), acc);
                         o[k] = -acc * ih;
                     }
                 }
@@ -212,19 +216,20 @@ template <typename T, int CF, int METHOD> struct Pass {
                 for (int k = 0; k < R; ++k) {
                     const int s = s0 + k;
                     if (s == 1)
-                        o[k] = ih * (-xv(x, hl, hr, k - 1) - T(9) * xv(x, hl, hr, k) +
-                                     T(9) * xv(x, hl, hr, k + 1) + xv(x, hl, hr, k + 2));
+                        o[k] = ih * fma(T(-9), xv(x, hl, hr, k),
+                                        fma(T(9), xv(x, hl, hr, k + 1),
+                                            xv(x, hl, hr, k + 2) - xv(x, hl, hr, k - 1)));
                     if (s == n - 1)
-                        o[k] = ih * (-xv(x, hl, hr, k - 2) - T(9) * xv(x, hl, hr, k - 1) +
-                                     T(9) * xv(x, hl, hr, k) + xv(x, hl, hr, k + 1));
+                        o[k] = ih * fma(T(-9), xv(x, hl, hr, k - 1),
+                                        fma(T(9), xv(x, hl, hr, k), xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 2)));
                 }
             }
         } else {
             const T c1 = T(9.0 / 8.0) * ih, c0 = T(-1.0 / 24.0) * ih;
 #pragma unroll
             for (int k = 0; k < R; ++k)
-                o[k] = c1 * (xv(x, hl, hr, k) - xv(x, hl, hr, k - 1)) +
-                       c0 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 2));
+                o[k] = fma(c1, xv(x, hl, hr, k) - xv(x, hl, hr, k - 1),
+                           c0 * (xv(x, hl, hr, k + 1) - xv(x, hl, hr, k - 2)));
             if (bnd) {
                 const T d0[6] = {T(-4751.0 / 5192.0), T(909.0 / 1298.0), T(6091.0 / 15576.0),
                                  T(-1165.0 / 5192.0), T(129.0 / 2596.0), T(-25.0 / 15576.0)};
@@ -234,13 +239,13 @@ template <typename T, int CF, int METHOD> struct Pass {
                     if (s == 1) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc += d0[c] * xv(x, hl, hr, k - 1 + c);
+                        for (int c = 0; c < 6; ++c) acc = fma(d0[c], xv(x, hl, hr, k - 1 + c), acc);
                         o[k] = acc * ih;
                     }
                     if (s == n) {
                         T acc = T(0);
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc += d0[c] * xv(x, hl, hr, k - c);
+                        for (int c = 0; c < 6; ++c) acc = fma(d0[c], xv(x, hl, hr, k - c), acc);
                         o[k] = -acc * ih;
                     }
                 }
@@ -343,8 +348,13 @@ template <typename T, int CF, int METHOD> struct Pass {
 // One workgroup's share of a pass: line group `tile` (one window per line).
 // FULL: the variant with the optional features (damping layers, wall data,
 // distributed forcing); the plain variant has none of their code.
-template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL = false>
+// EPS: the tolerance-tested form (LinePassArgs::eps_part; Algorithms 3 and
+// 4): the last two sweeps keep their previous iterate in a spare array and
+// the squared changes of u_{K-1}, v_{K-1}, u_K and v_K over the slots the
+// window writes become this tile's partials.
+template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL = false, bool EPS = false>
 __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* smem) {
+    static_assert(!(EPS && (COMP || FULL || MODE == LINE_EXPLICIT)), "tolerance-tested plain sweeps only");
     using P = Pass<T, CF, METHOD>;
     using C = K<T, CF>;
     constexpr int LW = C::LW, R = C::R, SPW = C::SPW, WS = C::WS;
@@ -367,6 +377,7 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
     const int vhi = n;                                          // velocity slots 0..n
 
     P p(a, smem, seg, lq, s0, q);
+    T ev[4] = {T(0), T(0), T(0), T(0)};   // tolerance test: change sums (EPS only)
 
     if (METHOD == LINE_CFD) {
         const T* src = a.coef + (size_t)g * 6 * WS;
@@ -444,17 +455,75 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
                 RR[k] *= e;
             }
         }
-        for (int it = 1; it < a.sweeps; ++it) {
+        if constexpr (EPS) {
+            // the slots this window writes (pressure: interior slots;
+            // velocity: slots 0..n); the masks pass through an empty asm at
+            // each use so that the per-slot tests are not hoisted out of
+            // the sweeps as lane masks, and the changes are masked by a
+            // product rather than a select
+            int umask = 0, vmask = 0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int s = s0 + k;
+                const bool own = qok && s >= c0 && s < c1;
+                if (own && s >= ulo && s <= uhi) umask |= 1 << k;
+                if (own && s <= vhi) vmask |= 1 << k;
+            }
+            auto opaque = [](int m) {
+                asm volatile("" : "+v"(m));
+                return m;
+            };
+            auto chg = [](T x, T y, int on) {
+                const T d = (x - y) * T(on);
+                return d * d;
+            };
+            T X[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) Tt[k] = B[k];                     // v_0
+            // one sweep (v_it, then u_{it+1}); tv: sum the change of v,
+            // qi >= 0: sum the change of u into ev[qi]
+            auto sweep = [&](bool tv, int qi) {
+                const int vm = opaque(vmask), um = opaque(umask);
+                p.template deriv<0>(U, X);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T vn = fma(-RR[k], X[k], B[k]);
+                    if (tv) ev[1] += chg(vn, Tt[k], (vm >> k) & 1);
+                    Tt[k] = vn;
+                }
+                p.template deriv<1>(Tt, X);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T un = fma(-KK[k], X[k], A[k]);
+                    if (qi >= 0) ev[qi] += chg(un, U[k], (um >> k) & 1);
+                    U[k] = un;
+                }
+            };
+            // sweeps it = 1 .. K - 1: untracked, then u_{K-1}, then v_{K-1} and u_K
+            for (int it = 1; it < a.sweeps - 2; ++it) sweep(false, -1);
+            if (a.sweeps >= 3) sweep(false, 0);
+            sweep(true, 2);
+            const int vm = opaque(vmask);
+            p.template deriv<0>(U, X);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {                                  // v_K
+                const T vn = fma(-RR[k], X[k], B[k]);
+                ev[3] += chg(vn, Tt[k], (vm >> k) & 1);
+                Tt[k] = vn;
+            }
+        } else {
+            for (int it = 1; it < a.sweeps; ++it) {
+                p.template deriv<0>(U, Tt);
+#pragma unroll
+                for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
+                p.template deriv<1>(Tt, U);
+#pragma unroll
+                for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            }
             p.template deriv<0>(U, Tt);
 #pragma unroll
-            for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);
-            p.template deriv<1>(Tt, U);
-#pragma unroll
-            for (int k = 0; k < R; ++k) U[k] = fma(-KK[k], U[k], A[k]);
+            for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // v_K
         }
-        p.template deriv<0>(U, Tt);
-#pragma unroll
-        for (int k = 0; k < R; ++k) Tt[k] = fma(-RR[k], Tt[k], B[k]);   // v_K
         if (MODE == LINE_SWEEP) {
             if (COMP) {
 #pragma unroll
@@ -480,6 +549,23 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
         }
     }
 
+    if constexpr (EPS) {
+        // wave sums, then the workgroup's, stored as this tile's partials
+        __shared__ double wsum[C::NW][4];
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            double v = (double)ev[qi];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) wsum[wave][qi] = v;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            for (int w = 0; w < C::NW; ++w) v += wsum[w][tid];
+            a.eps_part[(int64_t)tid * a.nlg * a.nwin + tile] = v;
+        }
+    }
     if ((FULL || COMP) && MODE != LINE_FINAL && a.ff) {
         // distributed forcing on the interior pressure slots
 #pragma unroll
@@ -492,10 +578,12 @@ __device__ __forceinline__ void lp_body(const LinePassArgs<T>& a, int tile, T* s
                                                   tid, MODE != LINE_FINAL);
 }
 
-template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL>
+template <typename T, int CF, int METHOD, int MODE, bool COMP, bool FULL, bool EPS = false>
 __global__ void __launch_bounds__((K<T, CF>::NT)) line_pass_kernel(const LinePassArgs<T> a) {
     __shared__ T smem[Pass<T, CF, METHOD>::SMEM];
-    lp_body<T, CF, METHOD, MODE, COMP, FULL>(a, (int)blockIdx.x, smem);
+    // uniform: an earlier attempt of a tolerance-tested pass converged
+    if (EPS && *a.eps_go == 0) return;
+    lp_body<T, CF, METHOD, MODE, COMP, FULL, EPS>(a, (int)blockIdx.x, smem);
 }
 
 // Several passes (of several problems) in one launch: each workgroup finds
@@ -556,8 +644,16 @@ hipError_t launch_lp(const LinePassArgs<T>* a, const GroupArgs<T>* ga, int metho
     const unsigned nb = a ? (unsigned)(a->nlg * a->nwin) : (unsigned)(((ga->total + 7) / 8) * 8);
     if (nb == 0) return hipSuccess;
     dim3 grid(nb), block(K<T, CF>::NT);
+    const bool eps = a && a->eps_part;
+    if (eps && (COMP || FULL || mode == LINE_EXPLICIT)) return hipErrorInvalidValue;
 #define LP_CASE(M, MD)                                                                                  \
     if (method == M && mode == MD) {                                                                    \
+        if constexpr (!COMP && !FULL && MD != LINE_EXPLICIT) {                                          \
+            if (eps) {                                                                                  \
+                hipLaunchKernelGGL((line_pass_kernel<T, CF, M, MD, false, false, true>), grid, block, 0, st, *a); \
+                return hipGetLastError();                                                               \
+            }                                                                                           \
+        }                                                                                               \
         if (a)                                                                                          \
             hipLaunchKernelGGL((line_pass_kernel<T, CF, M, MD, COMP, FULL>), grid, block, 0, st, *a);        \
         else                                                                                                  \

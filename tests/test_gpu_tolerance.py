@@ -13,11 +13,13 @@ from tests.gpu_util import log, max_rel, rel_l2, written_parts
 pytestmark = pytest.mark.gpu
 
 TOL64, TOL32 = 1e-12, 1e-4
-SIZES = {adi.CFD: (530, 520), adi.MFD: (520, 515)}   # lines over one window both ways
+# lines over one window both ways (wave-per-line kernel), within one window
+# both ways (single-window kernel), and one of each
+SIZES = {adi.CFD: [(530, 520), (120, 100), (600, 90)], adi.MFD: [(520, 515), (110, 130), (80, 600)]}
 
 
-def _case(method, seed):
-    nx, ny = SIZES[method]
+def _case(method, seed, size=0):
+    nx, ny = SIZES[method][size]
     h = 1.0 / max(nx, ny)
     f = inputs.random_fields(method, nx, ny, seed)
     med = inputs.random_medium(method, nx, ny, seed + 1)
@@ -68,17 +70,19 @@ def _stable_eps(method, c, nsteps, kmin, cap, eps_list, deepest):
     raise AssertionError("no stable tolerance found")
 
 
+@pytest.mark.parametrize("size", [0, 1, 2])
 @pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
 @pytest.mark.parametrize("dtype", [adi.FP64, adi.FP32])
-def test_tolerance_matches_oracle(method, dtype):
+def test_tolerance_matches_oracle(method, dtype, size):
     nsteps, kmin, cap = 2, 2, 12
-    c = _case(method, 11)
+    c = _case(method, 11, size)
     # FP32 iterates carry rounding noise of ~1e-7 of the fields: test well above it
     eps_list = [x * s for x in (10.0, 1.0, 0.1, 0.01) for s in (3, 1)]
     if dtype == adi.FP64:
         eps_list += [x * s for x in (1e-3, 1e-4, 1e-5) for s in (3, 1)]
     eps, used = _stable_eps(method, c, nsteps, kmin, cap, eps_list, 6 if dtype == adi.FP64 else 4)
-    log(f"case tolerance method={method} dtype={dtype} eps={eps:.3g} counts={list(used)}")
+    log(f"case tolerance method={method} dtype={dtype} size={SIZES[method][size]} eps={eps:.3g} "
+        f"counts={list(used)}")
     ref = _oracle(method, c, nsteps, eps, kmin, cap)
     got, (passes, sweeps) = _gpu(method, dtype, c, nsteps, cap, eps, kmin)
     assert passes == 2 * nsteps and sweeps == int(used.sum()), (passes, sweeps, list(used))
@@ -87,14 +91,15 @@ def test_tolerance_matches_oracle(method, dtype):
         assert err <= (TOL64 if dtype == adi.FP64 else TOL32), err
 
 
+@pytest.mark.parametrize("size", [0, 1])
 @pytest.mark.parametrize("method", [adi.CFD, adi.MFD])
-def test_tolerance_limits_equal_fixed_runs(method):
+def test_tolerance_limits_equal_fixed_runs(method, size):
     """Every change passes: each stage stops at min_sweeps; none passes: each
     runs the cap.  Both equal the fixed-count runs: bit for bit at the cap;
     to rounding at min_sweeps, whose fixed run plans its windows with the
     margin of min_sweeps sweeps rather than of the cap."""
     nsteps, kmin, cap = 2, 4, 8
-    c = _case(method, 12)
+    c = _case(method, 12, size)
     for eps, k in ((1e30, kmin), (1e-300, cap)):
         log(f"case tolerance limit method={method} eps={eps:g}")
         got, (passes, sweeps) = _gpu(method, adi.FP64, c, nsteps, cap, eps, kmin)
@@ -111,17 +116,18 @@ def test_tolerance_scope_errors():
     import torch
     c = _case(adi.CFD, 13)
     log("case tolerance scope errors")
-    # short lines: the segment / single-window kernels have no tolerance test
+    # the compensated mode has no tolerance test
     f = inputs.random_fields(adi.CFD, 100, 90, 1)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float64)
-    p = adi.make_params(adi.CFD, adi.FP64, 100, 90, 0.01, 0.005, 1.0)
-    pb = adi.Problem(p).bind(t(f["U"]), t(f["V"]), t(f["W"]))
-    with pytest.raises(RuntimeError, match="longer than"):
+    t32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", torch.float32)
+    p = adi.make_params(adi.CFD, adi.FP32C, 100, 90, 0.01, 0.005, 1.0)
+    pb = adi.Problem(p).bind(t32(f["U"]), t32(f["V"]), t32(f["W"]))
+    with pytest.raises(RuntimeError, match="FP32 or FP64"):
         pb.set_tolerance(1e-6, 2)
     assert pb.sweep_stats() == (0, 0)
     pb.close()
     # argument ranges, and batches refuse such a problem
-    nx, ny = SIZES[adi.CFD]
+    nx, ny = SIZES[adi.CFD][0]
     p = adi.make_params(adi.CFD, adi.FP64, nx, ny, c["h"], c["dt"], c["cmax"], sweeps=8)
     U, V, W = (t(c["f"][k]) for k in "UVW")
     pb = adi.Problem(p).bind(U, V, W)
