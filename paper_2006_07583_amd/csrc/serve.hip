@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/adi.h"
+#include "admission.h"
 #include "line_pass.h"
 #include "problem.h"
 
@@ -33,51 +34,7 @@ namespace {
 using adi::fail;
 using adi::hip_fail;
 
-// First-fit allocator over one device allocation (offsets, 256-byte units).
-class Arena {
-   public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = (bytes + 255) / 256 * 256;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) / 256 * 256;
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-
-   private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
+using adi::Arena;
 
 enum { ST_QUEUED = 0, ST_RUNNING = 1, ST_DONE = 2 };
 
@@ -347,16 +304,7 @@ void uploader(adi_server* S) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // reserves arena memory for the oldest pending request when it fits
-            auto admissible = [&] {
-                if (S->pending.empty() || S->admitted >= S->prm.max_active) return false;
-                Req* f = S->pending.front();
-                if (f->off == (size_t)-1) {
-                    size_t off;
-                    if (!S->arena.alloc(f->bytes, &off)) return false;
-                    f->off = off;
-                }
-                return true;
-            };
+            auto admissible = [&] { return adi::admissible(S->pending, S->admitted, S->prm.max_active, S->arena); };
             S->cv.wait(lk, [&] { return S->fatal || admissible() || (S->stop && S->pending.empty()); });
             if (S->fatal || !admissible()) return;
             adm = S->pending.front();
