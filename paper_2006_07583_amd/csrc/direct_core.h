@@ -338,12 +338,20 @@ DIRECT_HD T back_row(const IO& io, int i, int rb, T (&x)[MU + 1]) {
     return v;
 }
 
-// MFD pressure output of cell c from its solved value v.
-template <typename T, class IO>
-DIRECT_HD void put_cell(const IO& io, int c, T v, int mode, int src_s, T aF) {
+// Pressure outputs written one at a time (the IO's putU).
+struct PlainSink {
+    template <typename T, class IO>
+    DIRECT_HD void put(const IO& io, int s, T x) {
+        io.putU(s, x);
+    }
+};
+
+// MFD pressure output of cell c from its solved value v, through sink sk.
+template <typename T, class IO, class SK>
+DIRECT_HD void put_cell(const IO& io, SK& sk, int c, T v, int mode, int src_s, T aF) {
     const T A = io.A(c);
     const T u = mode == OUT_NEXT ? fma(T(2), v, -A) : v;
-    io.putU(c, u + (mode == OUT_NEXT && c == src_s ? aF : T(0)));
+    sk.put(io, c, u + (mode == OUT_NEXT && c == src_s ? aF : T(0)));
 }
 
 // Solve window w of one line and write its output slots.  mode OUT_NEXT
@@ -351,7 +359,8 @@ DIRECT_HD void put_cell(const IO& io, int c, T v, int mode, int src_s, T aF) {
 // 2 vel - B, the explicit part of the next stage along the same lines;
 // OUT_STAGE writes Ubar and vel.
 // WIDE = false is for windows whose rows are all interior rows (see
-// narrow_range).
+// narrow_range); their pressure outputs, produced in descending slot order,
+// go through io.u_sink(o0, o1), which may gather them into wider stores.
 template <typename T, int METHOD, bool WIDE, class IO>
 DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T inv_h, int mode, int src_s,
                             T aF) {
@@ -377,6 +386,7 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
     if constexpr (!WIDE) {
         // interior windows: branch-free loop bodies (unrolling them raised
         // the registers past the occupancy that hides the loads: kept rolled)
+        auto sk = io.u_sink(W.o0, W.o1);
         if constexpr (METHOD == MFD) {
 #pragma unroll 1
             for (int i = r0; i <= r1; ++i) {
@@ -390,12 +400,12 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
             // cell o1: its face o1 + 1 belongs to the next window
             {
                 const T v = back_row<T, MU>(io, W.o1, rb, x);
-                put_cell<T>(io, W.o1, v, mode, src_s, aF);
+                put_cell<T>(io, sk, W.o1, v, mode, src_s, aF);
             }
 #pragma unroll 1
             for (i = W.o1 - 1; i >= W.o0; --i) {
                 const T v = back_row<T, MU>(io, i, rb, x);
-                put_cell<T>(io, i, v, mode, src_s, aF);
+                put_cell<T>(io, sk, i, v, mode, src_s, aF);
                 put_face<T, MU>(io, n, i + 1, i, W.o0, W.o1, x, inv_h, mode);
             }
             // face o0, whose lowest cell is o0 - 1
@@ -420,7 +430,7 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
                 const T z = back_row<T, MU>(io, 2 * sl, rb, x);
                 const T A = io.A(sl), kk = io.K(sl);
                 const T u = mode == OUT_NEXT ? fma(T(-2) * kk, z, A) : fma(-kk, z, A);
-                io.putU(sl, u + (mode == OUT_NEXT && sl == src_s ? aF : T(0)));
+                sk.put(io, sl, u + (mode == OUT_NEXT && sl == src_s ? aF : T(0)));
             }
         }
         return;
@@ -434,11 +444,12 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
     }
 
     // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}
+    PlainSink sk;
     for (int i = r1; i >= rb; --i) {
         const T v = back_row<T, MU>(io, i, rb, x);
         if constexpr (METHOD == MFD) {
             const int c = i;
-            if (c >= W.o0 && c <= W.o1) put_cell<T>(io, c, v, mode, src_s, aF);
+            if (c >= W.o0 && c <= W.o1) put_cell<T>(io, sk, c, v, mode, src_s, aF);
             // faces whose lowest cell is c
             const int fo0 = w == 0 ? 0 : W.o0;
             if (c == 1) {
@@ -517,6 +528,7 @@ struct HostLine {
     void putV(int s, T x) const { v[s] = x; }
     void st(int i, int kk, T x) const { fs[(size_t)i * 8 + kk] = x; }
     T ld(int i, int kk) const { return fs[(size_t)i * 8 + kk]; }
+    PlainSink u_sink(int, int) const { return {}; }
 };
 
 // Margin of the windows, in slots: the distance from a unit impulse in the

@@ -10,12 +10,52 @@ namespace adi {
 
 namespace {
 
+// Pressure outputs of the interior windows, which arrive in descending slot
+// order.  With a transposed target (consecutive slots of a line contiguous,
+// 64 lines of a wave in 64 rows), one 4-byte store per lane and slot leaves
+// each lane a partial 32-byte sector that the L2 may evict before the rest
+// arrives.  Slots [lo, hi] (whole 32-byte pieces within the window's output
+// slots) are kept in a shift register instead and stored a piece at a time.
+template <typename T>
+struct GatherSink {
+    static constexpr int CH = 32 / sizeof(T);   // slots per piece
+    struct alignas(16) P16 {
+        T v[16 / sizeof(T)];
+    };
+    T b[CH];   // b[k]: slot s + k after slot s went in
+    int lo, hi;
+    bool on;
+    template <class IO>
+    DIRECT_HD void put(const IO& io, int s, T x) {
+        if (!on || s < lo || s > hi) {
+            io.putU(s, x);
+            return;
+        }
+#pragma unroll
+        for (int k = CH - 1; k > 0; --k) b[k] = b[k - 1];
+        b[0] = x;
+        if (((s - 1) & (CH - 1)) == 0 && io.live) {
+            P16* p = (P16*)io.uptr(s);
+            constexpr int E = 16 / sizeof(T);
+#pragma unroll
+            for (int j = 0; j < CH / E; ++j) {
+                P16 w;
+#pragma unroll
+                for (int k = 0; k < E; ++k) w.v[k] = b[j * E + k];
+                p[j] = w;
+            }
+        }
+    }
+};
+
 template <typename T, int NV>   // NV: values per kept row
 struct DevLine {
     DirectArgs<T> a;   // a copy: its fields stay in scalar registers
     int64_t q;
     int64_t tid;
     bool live;
+    bool ugather;   // u_s == 1 and 32-byte pieces of a u row start where s - 1
+                    // is a multiple of 32 / sizeof(T)
     DIRECT_HD T A(int s) const { return a.a[q * a.a_l + s * a.a_s]; }
     DIRECT_HD T B(int s) const { return a.b[q * a.b_l + s * a.b_s]; }
     DIRECT_HD T K(int s) const { return a.k[q * a.k_l + s * a.k_s]; }
@@ -26,6 +66,16 @@ struct DevLine {
     DIRECT_HD void putV(int s, T x) const {
         if (live) a.v[q * a.v_l + s * a.v_s] = x;
     }
+    DIRECT_HD T* uptr(int s) const { return a.u + q * a.u_l + s * a.u_s; }
+    // output slots o0..o1: the whole 32-byte pieces among them are gathered
+    DIRECT_HD GatherSink<T> u_sink(int o0, int o1) const {
+        constexpr int CH = GatherSink<T>::CH;
+        GatherSink<T> g;
+        g.on = ugather;
+        g.lo = 1 + ((o0 - 1 + CH - 1) / CH) * CH;      // first piece start >= o0
+        g.hi = 1 + ((o1 - 1 + 1) / CH) * CH - 1;        // last piece end <= o1
+        return g;
+    }
     DIRECT_HD int64_t fi(int i, int k) const {
         return (((tid >> 6) * a.drows + i) * NV + k) * 64 + (tid & 63);
     }
@@ -34,13 +84,13 @@ struct DevLine {
 };
 
 template <typename T, int METHOD, bool WIDE>
-__global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
+__global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p, int ugather) {
     const int64_t tid = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (tid >= p.nthr) return;
     const int q = (int)(tid % p.nlp), wi = (int)(tid / p.nlp);
     const int w = wi < p.wsplit ? p.wbase + wi : p.wbase2 + (wi - p.wsplit);
     const bool live = q < p.nlines;
-    const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live};
+    const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live, ugather != 0};
     const int src = (live && q == p.src_q) ? p.src_s : -1;
     direct::solve_window<T, METHOD, WIDE>(io, p.n, p.S, p.Se, p.H, w, p.inv_h, p.mode, src, p.aF);
 }
@@ -49,16 +99,18 @@ __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p) {
 
 template <typename T>
 hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st) {
+    // a transposed pressure target (u_s 1): slot s of line l at u + l u_l + s
+    const int ug = p.u_s == 1 && ((uintptr_t)(p.u + 1) % 32) == 0 && (p.u_l * (int64_t)sizeof(T)) % 32 == 0;
     if (p.wcount <= 0 || p.wsplit < 0 || p.wsplit > p.wcount || p.wbase < 0 || p.wbase + p.wsplit > p.nwin ||
         p.wbase2 < 0 || p.wbase2 + (p.wcount - p.wsplit) > p.nwin || p.nlp % 64 || (int64_t)p.nlp * p.wcount != p.nthr)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(p.nthr / 64)), block(64);
     if (method == LINE_MFD) {
-        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, false>), grid, block, 0, st, p);
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, true>), grid, block, 0, st, p, ug);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, false>), grid, block, 0, st, p, ug);
     } else {
-        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, false>), grid, block, 0, st, p);
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, true>), grid, block, 0, st, p, ug);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, false>), grid, block, 0, st, p, ug);
     }
     return hipGetLastError();
 }
