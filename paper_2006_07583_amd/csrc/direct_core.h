@@ -359,8 +359,9 @@ DIRECT_HD void put_cell(const IO& io, SK& sk, int c, T v, int mode, int src_s, T
 // 2 vel - B, the explicit part of the next stage along the same lines;
 // OUT_STAGE writes Ubar and vel.
 // WIDE = false is for windows whose rows are all interior rows (see
-// narrow_range); their pressure outputs, produced in descending slot order,
-// go through io.u_sink(o0, o1), which may gather them into wider stores.
+// narrow_range).  The pressure outputs, produced in descending slot order,
+// go through io.u_sink(first, last slot), which may gather them into wider
+// stores.
 template <typename T, int METHOD, bool WIDE, class IO>
 DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T inv_h, int mode, int src_s,
                             T aF) {
@@ -443,8 +444,10 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
         fwd_row<T, ML, MU>(io, i, r0, r1, rb, e, r, ur, yr);
     }
 
-    // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}
-    PlainSink sk;
+    // backward: x_i = y_i - sum_t u_{i,t} x_{i+t}; the pressure outputs
+    // (MFD cells o0..o1, CFD slots o0..o1 within 1..n-1) arrive in
+    // descending order
+    auto sk = METHOD == MFD ? io.u_sink(W.o0, W.o1) : io.u_sink(W.o0 > 1 ? W.o0 : 1, W.o1 < n - 1 ? W.o1 : n - 1);
     for (int i = r1; i >= rb; --i) {
         const T v = back_row<T, MU>(io, i, rb, x);
         if constexpr (METHOD == MFD) {
@@ -469,7 +472,7 @@ DIRECT_HD void solve_window(const IO& io, int n, int S, int Se, int H, int w, T 
                     const T A = io.A(s), kk = io.K(s);
                     T u = mode == OUT_NEXT ? fma(T(-2) * kk, v, A) : fma(-kk, v, A);
                     if (mode == OUT_NEXT && s == src_s) u += aF;
-                    io.putU(s, u);
+                    sk.put(io, s, u);
                 }
             }
         }
