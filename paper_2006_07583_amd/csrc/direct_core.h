@@ -346,6 +346,56 @@ struct PlainSink {
     }
 };
 
+// Pressure outputs gathered into 32-byte pieces.  The outputs of a window
+// arrive in descending slot order.  With a transposed target (consecutive
+// slots of a line contiguous, the 64 lines of a wave in 64 rows), one store
+// per lane and slot leaves each lane a partial 32-byte sector that the L2
+// may evict before the rest arrives.  The slots [lo, hi] (the whole pieces
+// within the output slots; a piece starts where s - 1 is a multiple of CH)
+// are kept in a shift register instead and stored a piece at a time, with
+// 16-byte stores at io.uptr(piece start); the others go through io.putU.
+// The IO's target must hold slot s at uptr(s) = base + s - 1 with base
+// 32-byte aligned whenever on is set.
+template <typename T>
+struct GatherSink {
+    static constexpr int CH = 32 / sizeof(T);   // slots per piece
+    struct alignas(16) P16 {
+        T v[16 / sizeof(T)];
+    };
+    T b[CH];   // b[k]: slot s + k after slot s went in
+    int lo, hi;
+    bool on;
+    // output slots o0..o1 (o0 >= 1)
+    static DIRECT_HD GatherSink make(int o0, int o1, bool on) {
+        GatherSink g;
+        g.on = on;
+        g.lo = 1 + ((o0 - 1 + CH - 1) / CH) * CH;   // first piece start >= o0
+        g.hi = (o1 / CH) * CH;                       // last piece end <= o1
+        return g;
+    }
+    template <class IO>
+    DIRECT_HD void put(const IO& io, int s, T x) {
+        if (!on || s < lo || s > hi) {
+            io.putU(s, x);
+            return;
+        }
+#pragma unroll
+        for (int k = CH - 1; k > 0; --k) b[k] = b[k - 1];
+        b[0] = x;
+        if (((s - 1) & (CH - 1)) == 0 && io.live) {
+            P16* p = (P16*)io.uptr(s);
+            constexpr int E = 16 / sizeof(T);
+#pragma unroll
+            for (int j = 0; j < CH / E; ++j) {
+                P16 w;
+#pragma unroll
+                for (int k = 0; k < E; ++k) w.v[k] = b[j * E + k];
+                p[j] = w;
+            }
+        }
+    }
+};
+
 // MFD pressure output of cell c from its solved value v, through sink sk.
 template <typename T, class IO, class SK>
 DIRECT_HD void put_cell(const IO& io, SK& sk, int c, T v, int mode, int src_s, T aF) {

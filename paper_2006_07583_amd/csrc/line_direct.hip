@@ -10,44 +10,6 @@ namespace adi {
 
 namespace {
 
-// Pressure outputs of the interior windows, which arrive in descending slot
-// order.  With a transposed target (consecutive slots of a line contiguous,
-// 64 lines of a wave in 64 rows), one 4-byte store per lane and slot leaves
-// each lane a partial 32-byte sector that the L2 may evict before the rest
-// arrives.  Slots [lo, hi] (whole 32-byte pieces within the window's output
-// slots) are kept in a shift register instead and stored a piece at a time.
-template <typename T>
-struct GatherSink {
-    static constexpr int CH = 32 / sizeof(T);   // slots per piece
-    struct alignas(16) P16 {
-        T v[16 / sizeof(T)];
-    };
-    T b[CH];   // b[k]: slot s + k after slot s went in
-    int lo, hi;
-    bool on;
-    template <class IO>
-    DIRECT_HD void put(const IO& io, int s, T x) {
-        if (!on || s < lo || s > hi) {
-            io.putU(s, x);
-            return;
-        }
-#pragma unroll
-        for (int k = CH - 1; k > 0; --k) b[k] = b[k - 1];
-        b[0] = x;
-        if (((s - 1) & (CH - 1)) == 0 && io.live) {
-            P16* p = (P16*)io.uptr(s);
-            constexpr int E = 16 / sizeof(T);
-#pragma unroll
-            for (int j = 0; j < CH / E; ++j) {
-                P16 w;
-#pragma unroll
-                for (int k = 0; k < E; ++k) w.v[k] = b[j * E + k];
-                p[j] = w;
-            }
-        }
-    }
-};
-
 template <typename T, int NV>   // NV: values per kept row
 struct DevLine {
     DirectArgs<T> a;   // a copy: its fields stay in scalar registers
@@ -67,14 +29,8 @@ struct DevLine {
         if (live) a.v[q * a.v_l + s * a.v_s] = x;
     }
     DIRECT_HD T* uptr(int s) const { return a.u + q * a.u_l + s * a.u_s; }
-    // output slots o0..o1: the whole 32-byte pieces among them are gathered
-    DIRECT_HD GatherSink<T> u_sink(int o0, int o1) const {
-        constexpr int CH = GatherSink<T>::CH;
-        GatherSink<T> g;
-        g.on = ugather;
-        g.lo = 1 + ((o0 - 1 + CH - 1) / CH) * CH;      // first piece start >= o0
-        g.hi = 1 + ((o1 - 1 + 1) / CH) * CH - 1;        // last piece end <= o1
-        return g;
+    DIRECT_HD direct::GatherSink<T> u_sink(int o0, int o1) const {
+        return direct::GatherSink<T>::make(o0, o1, ugather);
     }
     DIRECT_HD int64_t fi(int i, int k) const {
         return (((tid >> 6) * a.drows + i) * NV + k) * 64 + (tid & 63);

@@ -6,6 +6,9 @@
 //   direct_core_check margin method c2 tol : prints the window margin
 //   direct_core_check plan    : checks the window-plan invariants, prints the
 //                               number of violations (exit status 0 = none)
+//   direct_core_check sink    : checks the gathered pressure stores against
+//                               one store per slot, prints the number of
+//                               violations (exit status 0 = none)
 #define DIRECT_HD inline
 #define DIRECT_HOST_ONLY
 #include "direct_core.h"
@@ -17,7 +20,60 @@
 
 using namespace adi::direct;
 
+// A transposed pressure row for GatherSink: slot s at row[s - 1], the row
+// 32-byte aligned; counts the stores per slot and flags a piece store that
+// does not start a 32-byte piece.
+template <typename T>
+struct SinkRow {
+    T* row;
+    int* count;
+    int* misplaced;
+    bool live = true;
+    T* uptr(int s) const {
+        const int ch = GatherSink<T>::CH;
+        if ((s - 1) % ch != 0 || ((uintptr_t)(row + s - 1)) % 32 != 0) ++*misplaced;
+        for (int k = 0; k < ch; ++k) ++count[s - 1 + k];
+        return row + s - 1;
+    }
+    void putU(int s, T x) const {
+        row[s - 1] = x;
+        ++count[s - 1];
+    }
+};
+
+// Every window o0..o1 within 1..nmax, the slots put in descending order as
+// the backward passes do: each output slot must hold its value and have
+// been stored once, nothing else touched.
+template <typename T>
+int check_sink(bool on) {
+    constexpr int nmax = 80;
+    alignas(32) T row[nmax + 8];
+    int count[nmax + 8], misplaced = 0, bad = 0;
+    for (int o0 = 1; o0 <= nmax; ++o0)
+        for (int o1 = o0 - 1; o1 <= nmax; ++o1) {
+            for (int i = 0; i < nmax + 8; ++i) {
+                row[i] = T(-1);
+                count[i] = 0;
+            }
+            SinkRow<T> io{row, count, &misplaced};
+            auto sk = GatherSink<T>::make(o0, o1, on);
+            for (int s = o1; s >= o0; --s) sk.put(io, s, T(1000 + s));
+            for (int s = 1; s <= nmax + 8; ++s) {
+                const bool out = s >= o0 && s <= o1;
+                bad += count[s - 1] != (out ? 1 : 0);
+                bad += row[s - 1] != (out ? T(1000 + s) : T(-1));
+            }
+        }
+    return bad + misplaced;
+}
+
 int main(int argc, char** argv) {
+    if (argc >= 2 && !std::strcmp(argv[1], "sink")) {
+        const int bad = check_sink<float>(true) + check_sink<double>(true) + check_sink<float>(false) +
+                        check_sink<double>(false);
+        std::printf("%d\n", bad);
+        return bad ? 1 : 0;
+    }
     if (argc >= 5 && !std::strcmp(argv[1], "margin")) {
         std::printf("%d\n", direct_margin(std::atoi(argv[2]), std::atof(argv[3]), std::atof(argv[4])));
         return 0;

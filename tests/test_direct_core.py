@@ -123,3 +123,12 @@ def test_window_plan_invariants(exe):
     fits the per-thread factor store (host check of the index ranges)."""
     res = subprocess.run([exe, "plan"], capture_output=True, text=True)
     assert res.returncode == 0 and res.stdout.strip() == "0", res.stdout + res.stderr
+
+
+def test_gathered_pressure_stores(exe):
+    """The pressure outputs of a window, put in descending slot order, land
+    in their slots exactly once through the 32-byte piece stores and the
+    single stores at the window edges (every window within 80 slots, FP32
+    and FP64, gathering on and off); piece stores start on the piece grid."""
+    res = subprocess.run([exe, "sink"], capture_output=True, text=True)
+    assert res.returncode == 0 and res.stdout.strip() == "0", res.stdout + res.stderr
