@@ -294,7 +294,7 @@ namespace {
 // Vs, Vslo, FF (forcing field), BND (wall coefficients).
 struct Layout {
     size_t off[2][13];
-    size_t fs_off;    // factor store of the direct solves (shared by both directions)
+    size_t fs_off[2];   // factor stores of the direct solves, one per direction
     size_t dc_off;    // their constant materials
     size_t red_off;   // per-block partial maxima of the material check at bind
     size_t chk_off;   // health check: per-block partials and the running state
@@ -331,13 +331,16 @@ Layout layout(const adi_problem& pb) {
             cur += (sizes[i] * pb.esz + 255) / 256 * 256;
         }
     }
-    L.fs_off = cur;
+    L.fs_off[0] = L.fs_off[1] = cur;
     if (p.sweeps == 0) {
         const int nv = adi::direct_values_per_row(p.method == ADI_MFD ? adi::LINE_MFD : adi::LINE_CFD);
-        size_t fs = 0;
-        for (const Plan* pl : {&pb.px, &pb.py})
-            fs = std::max(fs, (size_t)pl->dnlp * pl->dnwin * pl->drows * nv * pb.esz);
-        cur += (fs + 255) / 256 * 256;
+        // one factor store per direction: the U entries of a direction's
+        // matrix stay from one pass to the next
+        for (int d = 0; d < 2; ++d) {
+            const Plan* pl = d == 0 ? &pb.px : &pb.py;
+            L.fs_off[d] = cur;
+            cur += ((size_t)pl->dnlp * pl->dnwin * pl->drows * nv * pb.esz + 255) / 256 * 256;
+        }
     }
     L.dc_off = cur;
     if (p.sweeps == 0) cur += 256;
@@ -858,7 +861,7 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     T* uo = a.uout + (pl.ver == 3 && a.utrans == 0 ? 1 : 0);
     if (a.utrans) { g.u = uo - 1; g.u_l = a.uout_ld; g.u_s = 1; }
     else { g.u = uo - a.uout_ld; g.u_l = 1; g.u_s = a.uout_ld; }
-    g.fs = (T*)pb->dfs;
+    g.fs = (T*)pb->dfs[d.dir];
     g.inv_h = a.inv_h;
     g.aF = a.aF;
     g.nlines = a.nlines;
@@ -876,7 +879,8 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
     // the second stream beside the interior windows, each launch with its
     // own part of the factor store
     const int nv_wide = adi::direct_values_per_row(d.method), nv_narrow = 4;
-    T* fs = (T*)pb->dfs;
+    T* fs = (T*)pb->dfs[d.dir];
+    const bool ustored = pb->dfs_u[d.dir];
     // windows [wbase, wbase + n1) and [wbase2, wbase2 + n2) in one launch
     auto go = [&](int wbase, int n1, int wbase2, int n2, bool wide, hipStream_t s) {
         g.wbase = wbase;
@@ -886,15 +890,22 @@ hipError_t launch_direct_pass(adi_problem* pb, const adi::PassDesc<T>& d) {
         g.nthr = (int64_t)pl.dnlp * g.wcount;
         g.fs = fs;
         fs += g.nthr * pl.drows * (wide ? nv_wide : nv_narrow);
-        return adi::launch_direct<T>(g, d.method, wide, s);
+        return adi::launch_direct<T>(g, d.method, wide, ustored, s);
     };
-    if (pl.dwa > pl.dwb) return go(0, pl.dnwin, 0, 0, true, pb->st);
-    hipError_t e = hipEventRecord(pb->dev_in, pb->st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(pb->dst2, pb->dev_in, 0);
-    if (e == hipSuccess) e = go(0, pl.dwa, pl.dwb + 1, pl.dnwin - pl.dwb - 1, true, pb->dst2);
-    if (e == hipSuccess) e = hipEventRecord(pb->dev_out, pb->dst2);
-    if (e == hipSuccess) e = go(pl.dwa, pl.dwb - pl.dwa + 1, 0, 0, false, pb->st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(pb->st, pb->dev_out, 0);
+    hipError_t e;
+    if (pl.dwa > pl.dwb) {
+        e = go(0, pl.dnwin, 0, 0, true, pb->st);
+    } else {
+        e = hipEventRecord(pb->dev_in, pb->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pb->dst2, pb->dev_in, 0);
+        if (e == hipSuccess) e = go(0, pl.dwa, pl.dwb + 1, pl.dnwin - pl.dwb - 1, true, pb->dst2);
+        if (e == hipSuccess) e = hipEventRecord(pb->dev_out, pb->dst2);
+        if (e == hipSuccess) e = go(pl.dwa, pl.dwb - pl.dwa + 1, 0, 0, false, pb->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pb->st, pb->dev_out, 0);
+    }
+    // later passes along these lines (stream-ordered after this one) find
+    // the U entries stored
+    if (e == hipSuccess) pb->dfs_u[d.dir] = true;
     return e;
 }
 
@@ -1387,7 +1398,10 @@ void place(adi_problem* pb, const Layout& L, char* w) {
         D.FF = pb->fsig.kind ? w + L.off[d][11] : nullptr;
         D.BND = pb->bsig.kind ? w + L.off[d][12] : nullptr;
     }
-    pb->dfs = p.sweeps == 0 ? w + L.fs_off : nullptr;
+    for (int d = 0; d < 2; ++d) {
+        pb->dfs[d] = p.sweeps == 0 ? w + L.fs_off[d] : nullptr;
+        pb->dfs_u[d] = false;
+    }
     pb->dconst = p.sweeps == 0 ? w + L.dc_off : nullptr;
 }
 

@@ -292,7 +292,9 @@ DIRECT_HD void put_face(const IO& io, int n, int f, int c, int fo0, int fo1, con
 // One forward row: drop the unknowns outside the window, eliminate with the
 // previous ML normalised U rows (ur[0] is row i - ML), push the new row and
 // store it as kept row i - rb (rows before rb go to slot 0, which row rb
-// overwrites: a store without a branch).
+// overwrites: a store without a branch).  The U entries depend on the
+// matrix only; when io.u_stored() says an earlier pass with the same matrix
+// stored them, only the right-hand side value is written.
 template <typename T, int ML, int MU, class IO>
 DIRECT_HD void fwd_row(const IO& io, int i, int r0, int r1, int rb, T (&e)[ML + MU + 1], T r, T (&ur)[ML][MU],
                        T (&yr)[ML]) {
@@ -322,8 +324,10 @@ DIRECT_HD void fwd_row(const IO& io, int i, int r0, int r1, int rb, T (&e)[ML + 
     for (int t = 0; t < MU; ++t) ur[ML - 1][t] = e[ML + 1 + t] * inv;
     const int si = i >= rb ? i - rb : 0;
     io.st(si, 0, yr[ML - 1]);
+    if (!io.u_stored()) {
 #pragma unroll
-    for (int t = 0; t < MU; ++t) io.st(si, t + 1, ur[ML - 1][t]);
+        for (int t = 0; t < MU; ++t) io.st(si, t + 1, ur[ML - 1][t]);
+    }
 }
 
 // One backward row: x_i = y_i - sum_t u_{i,t} x_{i+t}, pushed into x.
@@ -582,6 +586,7 @@ struct HostLine {
     void st(int i, int kk, T x) const { fs[(size_t)i * 8 + kk] = x; }
     T ld(int i, int kk) const { return fs[(size_t)i * 8 + kk]; }
     PlainSink u_sink(int, int) const { return {}; }
+    bool u_stored() const { return false; }
 };
 
 // Margin of the windows, in slots: the distance from a unit impulse in the

@@ -18,6 +18,8 @@ struct DevLine {
     bool live;
     bool ugather;   // u_s == 1 and 32-byte pieces of a u row start where s - 1
                     // is a multiple of 32 / sizeof(T)
+    bool ustored;   // the factor store already holds the U entries of this
+                    // matrix (an earlier pass along the same lines)
     DIRECT_HD T A(int s) const { return a.a[q * a.a_l + s * a.a_s]; }
     DIRECT_HD T B(int s) const { return a.b[q * a.b_l + s * a.b_s]; }
     DIRECT_HD T K(int s) const { return a.k[q * a.k_l + s * a.k_s]; }
@@ -29,6 +31,7 @@ struct DevLine {
         if (live) a.v[q * a.v_l + s * a.v_s] = x;
     }
     DIRECT_HD T* uptr(int s) const { return a.u + q * a.u_l + s * a.u_s; }
+    DIRECT_HD bool u_stored() const { return ustored; }
     DIRECT_HD direct::GatherSink<T> u_sink(int o0, int o1) const {
         return direct::GatherSink<T>::make(o0, o1, ugather);
     }
@@ -40,13 +43,13 @@ struct DevLine {
 };
 
 template <typename T, int METHOD, bool WIDE>
-__global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p, int ugather) {
+__global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p, int ugather, int ustored) {
     const int64_t tid = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (tid >= p.nthr) return;
     const int q = (int)(tid % p.nlp), wi = (int)(tid / p.nlp);
     const int w = wi < p.wsplit ? p.wbase + wi : p.wbase2 + (wi - p.wsplit);
     const bool live = q < p.nlines;
-    const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live, ugather != 0};
+    const DevLine<T, direct::BandOf<METHOD, WIDE>::MU + 1> io{p, live ? q : 0, tid, live, ugather != 0, ustored != 0};
     const int src = (live && q == p.src_q) ? p.src_s : -1;
     direct::solve_window<T, METHOD, WIDE>(io, p.n, p.S, p.Se, p.H, w, p.inv_h, p.mode, src, p.aF);
 }
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(64) void line_direct_kernel(DirectArgs<T> p, int ug
 }  // namespace
 
 template <typename T>
-hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st) {
+hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, bool ustored, hipStream_t st) {
     // a transposed pressure target (u_s 1): slot s of line l at u + l u_l + s
     const int ug = p.u_s == 1 && ((uintptr_t)(p.u + 1) % 32) == 0 && (p.u_l * (int64_t)sizeof(T)) % 32 == 0;
     if (p.wcount <= 0 || p.wsplit < 0 || p.wsplit > p.wcount || p.wbase < 0 || p.wbase + p.wsplit > p.nwin ||
@@ -62,17 +65,17 @@ hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStrea
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)(p.nthr / 64)), block(64);
     if (method == LINE_MFD) {
-        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, true>), grid, block, 0, st, p, ug);
-        else hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, false>), grid, block, 0, st, p, ug);
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, true>), grid, block, 0, st, p, ug, ustored ? 1 : 0);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::MFD, false>), grid, block, 0, st, p, ug, ustored ? 1 : 0);
     } else {
-        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, true>), grid, block, 0, st, p, ug);
-        else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, false>), grid, block, 0, st, p, ug);
+        if (wide) hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, true>), grid, block, 0, st, p, ug, ustored ? 1 : 0);
+        else hipLaunchKernelGGL((line_direct_kernel<T, direct::CFD, false>), grid, block, 0, st, p, ug, ustored ? 1 : 0);
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_direct<float>(const DirectArgs<float>&, int, bool, hipStream_t);
-template hipError_t launch_direct<double>(const DirectArgs<double>&, int, bool, hipStream_t);
+template hipError_t launch_direct<float>(const DirectArgs<float>&, int, bool, bool, hipStream_t);
+template hipError_t launch_direct<double>(const DirectArgs<double>&, int, bool, bool, hipStream_t);
 
 int direct_values_per_row(int method) {
     return method == LINE_MFD ? direct::Band<direct::MFD>::MU + 1 : direct::Band<direct::CFD>::MU + 1;

@@ -158,9 +158,11 @@ struct DirectArgs {
     int64_t nthr;        // nlp * wcount
 };
 // wide: the closure rows of the line ends are in reach (windows 0 and past
-// narrow_last); otherwise the interior (3, 3) band
+// narrow_last); otherwise the interior (3, 3) band.  ustored: the factor
+// store already holds the U entries of this matrix, from an earlier launch
+// over the same windows
 template <typename T>
-hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, hipStream_t st);
+hipError_t launch_direct(const DirectArgs<T>& p, int method, bool wide, bool ustored, hipStream_t st);
 int direct_values_per_row(int method);
 
 }  // namespace adi

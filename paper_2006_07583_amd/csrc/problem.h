@@ -121,10 +121,12 @@ struct adi_problem {
     // walls (bit 0: x = 0, 1: x = 1, 2: y = 0, 3: y = 1)
     double dmp0 = 0.0, dmpw = 0.0;
     int dmpwalls = 0;
-    // factor store of the direct solves (sweeps 0) and the constant
-    // materials {a kappa0, a rinv0} they read when K or R is absent, both
-    // part of the workspace
-    void* dfs = nullptr;
+    // factor stores of the direct solves (sweeps 0), one per direction, and
+    // the constant materials {a kappa0, a rinv0} they read when K or R is
+    // absent, all part of the workspace; dfs_u[d]: the store of direction d
+    // holds the U entries of its matrix (set by its first pass after a bind)
+    void* dfs[2] = {nullptr, nullptr};
+    bool dfs_u[2] = {false, false};
     void* dconst = nullptr;
     // second stream and its two events: the windows at the line ends run
     // beside the interior windows
