@@ -362,14 +362,15 @@ int direct_margin_of(const adi_params& p) {
 }
 
 // Windows of the direct solves along one direction: enough windows for
-// about 2^18 threads (measured best of 2^17..2^20 on 4096^2 lines), each
-// keeping at least twice its margin.
+// about 2^18 threads, 2^17 for mimetic FP64 (measured best of 2^17..2^20 on
+// 4096^2 lines), each keeping at least twice its margin.
 void direct_plan(Plan& pl, const adi_params& p) {
     const int m = p.method == ADI_MFD ? adi::direct::MFD : adi::direct::CFD;
     const int ns = pl.n - adi::direct::direct_smin(m) + 1;
     pl.dH = direct_margin_of(p);
     pl.dnlp = (pl.nlines + 63) / 64 * 64;
-    const int want = std::max(1, (1 << 18) / pl.dnlp);
+    const int target = m == adi::direct::MFD && p.dtype == ADI_FP64 ? 1 << 17 : 1 << 18;
+    const int want = std::max(1, target / pl.dnlp);
     int S = std::max({2 * pl.dH, 16, (ns + want - 1) / want});
     pl.dS = std::min(S, ns);
     // the end windows keep H + 4 slots: short chains for the wide band,
